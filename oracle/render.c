@@ -1,0 +1,503 @@
+/*
+ * render.c -- oracle geometry, plain path tracer with next-event estimation
+ * and the sphere-tracing renderer.  TEST INFRASTRUCTURE ONLY (see
+ * msst_oracle.h).
+ *
+ * Method (Sec. 3 and its overview figure): a camera path enters the
+ * translucent body and moves by free flights l = -log(1 - xi) / sigma_t
+ * (delta tracking in a homogeneous medium).  At a collision the plain path
+ * tracer scatters once (absorption roulette, HG direction).  The sphere
+ * tracer instead asks a signed distance for the largest sphere around the
+ * collision that stays inside the body, rescales sigma_t -> sigma_t r
+ * (Sec. 4.1) and replaces the whole scattering chain inside that sphere by
+ * one learned step: LengthGen gives N, the path survives with probability
+ * albedo^N (Sec. 3.2), PathGen gives the exit (theta, alpha, beta) placed by
+ * the rotation of Eq. (transform), EventGen a representative event (X, W).
+ * Direct light from a point light is added by next-event estimation
+ * (Sec. 4.3, Eq. directLighting): at every plain event with weight albedo,
+ * at the representative event of a sphere step with weight
+ * Lambda^(N) / albedo^N.  There is no refraction at the boundary (Sec. 4.3),
+ * so rays cross it unchanged; the background is black.
+ */
+#include "msst_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_PI 3.14159265358979323846264338327950288
+#define OR_U24 16777216.0
+#define OR_MAX_IV 16
+
+/* ---------------- primitives ---------------- */
+
+static double or_dot(const double a[3], const double b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static void or_normalize(double v[3]) {
+    double l = sqrt(or_dot(v, v));
+    v[0] /= l;
+    v[1] /= l;
+    v[2] /= l;
+}
+
+static double or_prim_sdf(const float* pr, const double p[3]) {
+    double q[3] = {p[0] - pr[1], p[1] - pr[2], p[2] - pr[3]};
+    if ((int)pr[0] == OR_PRIM_SPHERE) return sqrt(or_dot(q, q)) - pr[4];
+    double e[3] = {fabs(q[0]) - pr[4], fabs(q[1]) - pr[5], fabs(q[2]) - pr[6]};
+    double out[3] = {fmax(e[0], 0.0), fmax(e[1], 0.0), fmax(e[2], 0.0)};
+    double inside = fmin(fmax(e[0], fmax(e[1], e[2])), 0.0);
+    return sqrt(or_dot(out, out)) + inside;
+}
+
+double or_scene_sdf(const or_scene* sc, const double p[3]) {
+    double s = INFINITY;
+    for (int i = 0; i < sc->n_prims; ++i) s = fmin(s, or_prim_sdf(sc->prims + 8 * i, p));
+    return s;
+}
+
+/* Parametric interval [t0, t1] of a ray inside one convex primitive. */
+static int or_prim_interval(const float* pr, const double o[3], const double d[3], double* t0,
+                            double* t1) {
+    double q[3] = {o[0] - pr[1], o[1] - pr[2], o[2] - pr[3]};
+    if ((int)pr[0] == OR_PRIM_SPHERE) {
+        double b = or_dot(q, d);
+        double c = or_dot(q, q) - (double)pr[4] * pr[4];
+        double disc = b * b - c;
+        if (disc <= 0.0) return 0;
+        double s = sqrt(disc);
+        *t0 = -b - s;
+        *t1 = -b + s;
+        return 1;
+    }
+    double lo = -INFINITY, hi = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        double h = pr[4 + a];
+        if (d[a] == 0.0) {
+            if (q[a] < -h || q[a] > h) return 0;
+            continue;
+        }
+        double ta = (-h - q[a]) / d[a], tb = (h - q[a]) / d[a];
+        if (ta > tb) {
+            double tmp = ta;
+            ta = tb;
+            tb = tmp;
+        }
+        lo = fmax(lo, ta);
+        hi = fmin(hi, tb);
+    }
+    if (lo >= hi) return 0;
+    *t0 = lo;
+    *t1 = hi;
+    return 1;
+}
+
+/* Sorted, merged intervals of the ray inside the union of all primitives. */
+int or_ray_intervals(const or_scene* sc, const double o[3], const double d[3], double* t0,
+                     double* t1, int cap) {
+    double a[OR_MAX_IV * 8], b[OR_MAX_IV * 8];
+    int n = 0;
+    for (int i = 0; i < sc->n_prims && n < OR_MAX_IV * 8; ++i) {
+        double x0, x1;
+        if (or_prim_interval(sc->prims + 8 * i, o, d, &x0, &x1)) {
+            int k = n++;
+            while (k > 0 && a[k - 1] > x0) {
+                a[k] = a[k - 1];
+                b[k] = b[k - 1];
+                --k;
+            }
+            a[k] = x0;
+            b[k] = x1;
+        }
+    }
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        if (m > 0 && a[i] <= t1[m - 1]) {
+            if (b[i] > t1[m - 1]) t1[m - 1] = b[i];
+        } else if (m < cap) {
+            t0[m] = a[i];
+            t1[m] = b[i];
+            ++m;
+        }
+    }
+    return m;
+}
+
+/* fp16 bit pattern of x rounded toward zero (finite range only). */
+static uint16_t or_fp16_rtz(double x) {
+    uint16_t sign = x < 0 ? 0x8000u : 0;
+    double a = fabs(x);
+    if (a >= 65504.0) return (uint16_t)(sign | 0x7bffu);
+    if (a < ldexp(1.0, -24)) return sign;
+    int e;
+    frexp(a, &e);
+    int ex = e - 1; /* a in [2^ex, 2^(ex+1)) */
+    if (ex < -14) {
+        uint32_t m = (uint32_t)floor(a / ldexp(1.0, -24));
+        return (uint16_t)(sign | m);
+    }
+    uint32_t mant = (uint32_t)floor((a / ldexp(1.0, ex) - 1.0) * 1024.0);
+    return (uint16_t)(sign | ((uint32_t)(ex + 15) << 10) | mant);
+}
+
+static double or_fp16_value(uint16_t h) {
+    int s = h >> 15, e = (h >> 10) & 31, m = h & 1023;
+    double v = e == 0 ? ldexp((double)m, -24) : ldexp(1.0 + m / 1024.0, e - 15);
+    return s ? -v : v;
+}
+
+/* Grid of signed distances at voxel centres lo + (i + 1/2) h, rounded toward
+ * zero to binary16 so that |stored| <= |exact|: the voxel-grid distance
+ * pre-process of Sec. 3, with a Euclidean lower bound in place of the
+ * Chebyshev distance. */
+void or_build_sdf_grid(const or_scene* sc, int32_t res, const float lo[3], const float hi[3],
+                       uint16_t* out) {
+    for (int64_t k = 0; k < res; ++k)
+        for (int64_t j = 0; j < res; ++j)
+            for (int64_t i = 0; i < res; ++i) {
+                double p[3] = {lo[0] + (i + 0.5) * ((double)hi[0] - lo[0]) / res,
+                               lo[1] + (j + 0.5) * ((double)hi[1] - lo[1]) / res,
+                               lo[2] + (k + 0.5) * ((double)hi[2] - lo[2]) / res};
+                out[(k * res + j) * res + i] = or_fp16_rtz(or_scene_sdf(sc, p));
+            }
+}
+
+/* Radius of a sphere around p that lies inside the body.  Without a grid:
+ * the union distance min_i sdf_i, which bounds the interior distance from
+ * below, shrunk by 0.1 % so the sphere never touches the surface.  With a
+ * grid: the nearest voxel's stored value minus the half voxel diagonal
+ * (signed distances are 1-Lipschitz). */
+double or_conservative_radius(const or_scene* sc, const double p[3]) {
+    if (sc->sdf_fp16 && sc->res > 0) {
+        int idx[3];
+        double hmax = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double h = ((double)sc->hi[a] - sc->lo[a]) / sc->res;
+            hmax = fmax(hmax, h);
+            double f = (p[a] - sc->lo[a]) / h;
+            if (!(f >= 0.0) || f >= sc->res) return 0.0;
+            idx[a] = (int)floor(f);
+        }
+        double s = or_fp16_value(sc->sdf_fp16[((int64_t)idx[2] * sc->res + idx[1]) * sc->res + idx[0]]);
+        double r = -s - 0.5 * sqrt(3.0) * hmax;
+        return r > 0.0 ? r : 0.0;
+    }
+    double s = or_scene_sdf(sc, p);
+    return s < 0.0 ? -0.999 * s : 0.0;
+}
+
+/* In-medium length of the segment from p to q (the d_t of Sec. 4.3). */
+static double or_medium_length(const or_scene* sc, const double p[3], const double q[3]) {
+    double d[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+    double len = sqrt(or_dot(d, d));
+    if (len == 0.0) return 0.0;
+    for (int i = 0; i < 3; ++i) d[i] /= len;
+    double t0[OR_MAX_IV], t1[OR_MAX_IV];
+    int m = or_ray_intervals(sc, p, d, t0, t1, OR_MAX_IV);
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double a = fmax(t0[i], 0.0), b = fmin(t1[i], len);
+        if (b > a) acc += b - a;
+    }
+    return acc;
+}
+
+/* Point-light next-event estimate at x for a path arriving along d:
+ * I rho_g(d . w_{x->L}) exp(-sigma_t d_t) / |x_L - x|^2 (Sec. 4.3). */
+static double or_nee(const or_scene* sc, const or_light* lt, const or_medium* md, const double x[3],
+                     const double d[3]) {
+    double wl[3] = {lt->pos[0] - x[0], lt->pos[1] - x[1], lt->pos[2] - x[2]};
+    double dist2 = or_dot(wl, wl);
+    double dist = sqrt(dist2);
+    for (int i = 0; i < 3; ++i) wl[i] /= dist;
+    double dt = or_medium_length(sc, x, lt->pos);
+    return lt->intensity * or_hg_eval(md->g, or_dot(d, wl)) * exp(-md->sigma_t * dt) / dist2;
+}
+
+/* ---------------- learned sphere step ---------------- */
+
+/* De-standardised sample of one decoder from standard normals nrm[0..L+P). */
+static void or_model_sample(const or_render_desc* rd, int model, const double* cond,
+                            const double* nrm, double* y) {
+    const or_cvae_shape* s = &rd->shapes[model];
+    const double* st = rd->stats[model];
+    double cs[16], mu[16], lv[16];
+    for (int k = 0; k < s->p_in; ++k) cs[k] = (cond[k] - st[k]) / st[16 + k];
+    or_cvae_decode(s, rd->params[model], rd->precision, rd->act_scales[model], nrm, cs, mu, lv);
+    for (int k = 0; k < s->p_out; ++k)
+        y[k] = (mu[k] + exp(0.5 * lv[k]) * nrm[s->latent + k]) * st[48 + k] + st[32 + k];
+}
+
+static void or_draw_normals(const or_render_desc* rd, uint64_t id, uint32_t* c0, int count,
+                            double* nrm) {
+    for (int j = 0; j * 4 < count; ++j) or_normal4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, nrm + 4 * j);
+}
+
+/* Sum_{i=1..N} albedo^i / albedo^N, the next-event weight of a sphere step
+ * that survived its absorption test (Sec. 4.3 with the reject-first order
+ * of Sec. 3.2). */
+static double or_lambda_weight(double phi, double N) {
+    if (phi >= 1.0) return N;
+    return phi * expm1(-N * log(phi)) / (1.0 - phi);
+}
+
+typedef struct {
+    double x[3], w[3];  /* exit position and direction (world) */
+    double X[3], W[3];  /* representative event (world) */
+    double N;
+    int survived;
+} or_step;
+
+/* Learned step in the sphere of radius r around p entered along d. */
+static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t id, uint32_t* c0,
+                         const double p[3], const double d[3], double r, or_step* out) {
+    double str = md->sigma_t * r, lst = log(str), g = md->g, phi = md->albedo;
+    double nrm[16], y[8];
+    /* LengthGen */
+    double c_len[2] = {lst, g};
+    or_draw_normals(rd, id, c0, rd->shapes[0].latent + rd->shapes[0].p_out, nrm);
+    or_model_sample(rd, 0, c_len, nrm, y);
+    double ey = exp(fmin(y[0], 20.0));
+    double N = floor(ey + 0.5);
+    if (N < 1.0) N = 1.0;
+    out->N = N;
+    double u[4];
+    or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, u);
+    /* absorption along the bypassed chain: survive with probability albedo^N */
+    if (!(u[0] <= exp(N * log(phi)))) {
+        out->survived = 0;
+        return;
+    }
+    out->survived = 1;
+    double psi = 2.0 * OR_PI * u[1];
+    /* PathGen */
+    double c_path[3] = {lst, g, log(N)};
+    or_draw_normals(rd, id, c0, rd->shapes[1].latent + rd->shapes[1].p_out, nrm);
+    or_model_sample(rd, 1, c_path, nrm, y);
+    double ct = fmin(1.0, fmax(-1.0, y[0]));
+    double al = y[1], be = y[2];
+    double ga = sqrt(fmax(0.0, 1.0 - al * al - be * be));
+    double nl = sqrt(al * al + be * be + ga * ga);
+    al /= nl;
+    be /= nl;
+    ga /= nl;
+    /* EventGen */
+    double c_ev[7] = {lst, g, phi, ct, al, be, log(N)};
+    or_draw_normals(rd, id, c0, rd->shapes[2].latent + rd->shapes[2].p_out, nrm);
+    or_model_sample(rd, 2, c_ev, nrm, y);
+    double X[3] = {y[0], y[1], y[2]}, W[3] = {y[3], y[4], y[5]};
+    double xl = sqrt(or_dot(X, X));
+    if (xl > 1.0)
+        for (int i = 0; i < 3; ++i) X[i] /= xl;
+    double wl = sqrt(or_dot(W, W));
+    if (wl > 0.0) {
+        for (int i = 0; i < 3; ++i) W[i] /= wl;
+    } else {
+        W[0] = 0.0;
+        W[1] = 0.0;
+        W[2] = 1.0;
+    }
+    /* Eq. (transform): x = p + r R R_psi x~ with R = [e1 e2 d], plus the
+     * exit-frame direction of Sec. 4.1 and (X, W) rotated the same way. */
+    double e1[3], e2[3];
+    or_onb(d, e1, e2);
+    double cp = cos(psi), sp = sin(psi), st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double xt[3] = {st * cp, st * sp, ct};
+    double w0[3] = {be * ct + ga * st, al, -be * st + ga * ct};
+    double wt[3] = {cp * w0[0] - sp * w0[1], sp * w0[0] + cp * w0[1], w0[2]};
+    double Xt[3] = {cp * X[0] - sp * X[1], sp * X[0] + cp * X[1], X[2]};
+    double Wt[3] = {cp * W[0] - sp * W[1], sp * W[0] + cp * W[1], W[2]};
+    for (int i = 0; i < 3; ++i) {
+        out->x[i] = p[i] + r * (xt[0] * e1[i] + xt[1] * e2[i] + xt[2] * d[i]);
+        out->w[i] = wt[0] * e1[i] + wt[1] * e2[i] + wt[2] * d[i];
+        out->X[i] = p[i] + r * (Xt[0] * e1[i] + Xt[1] * e2[i] + Xt[2] * d[i]);
+        out->W[i] = Wt[0] * e1[i] + Wt[1] * e2[i] + Wt[2] * d[i];
+    }
+    or_normalize(out->w);
+    or_normalize(out->W);
+}
+
+/* Reference sphere step: the actual random walk inside the sphere (the
+ * process the CVAEs learn), with the representative event drawn by the
+ * albedo-power reservoir and the absorption decided after the walk. */
+static void or_exact_step(const or_render_desc* rd, const or_medium* md, uint64_t id, uint32_t* c0,
+                          const double p[3], const double d[3], double r, or_step* out) {
+    double x[3] = {p[0], p[1], p[2]}, dir[3] = {d[0], d[1], d[2]};
+    double phi = md->albedo, resv = 0.0;
+    uint32_t nev = 0;
+    for (;;) {
+        ++nev;
+        double u[4];
+        or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, u);
+        resv = (nev == 1) ? 1.0 : 1.0 + resv / phi;
+        if (u[3] * resv <= 1.0) {
+            memcpy(out->X, x, sizeof out->X);
+            memcpy(out->W, dir, sizeof out->W);
+        }
+        double mu = or_hg_sample(md->g, u[1]);
+        or_scatter_dir(dir, mu, 2.0 * OR_PI * u[2]);
+        double l = -log(u[0]) / md->sigma_t;
+        double q[3] = {x[0] - p[0] + l * dir[0], x[1] - p[1] + l * dir[1], x[2] - p[2] + l * dir[2]};
+        if (or_dot(q, q) >= r * r) {
+            double rel[3] = {x[0] - p[0], x[1] - p[1], x[2] - p[2]};
+            double b = or_dot(rel, dir), c = or_dot(rel, rel) - r * r;
+            double t = -b + sqrt(fmax(0.0, b * b - c));
+            for (int i = 0; i < 3; ++i) out->x[i] = x[i] + t * dir[i];
+            break;
+        }
+        for (int i = 0; i < 3; ++i) x[i] += l * dir[i];
+    }
+    memcpy(out->w, dir, sizeof out->w);
+    out->N = (double)nev;
+    double u[4];
+    or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, u);
+    out->survived = u[0] <= exp(out->N * log(phi));
+}
+
+/* ---------------- path ---------------- */
+
+typedef struct {
+    double value, events, steps;
+} or_path_result;
+
+static void or_camera_ray(const or_camera* cam, int64_t pixel, double jx, double jy, double o[3],
+                          double d[3]) {
+    double f[3] = {cam->look_at[0] - cam->eye[0], cam->look_at[1] - cam->eye[1],
+                   cam->look_at[2] - cam->eye[2]};
+    or_normalize(f);
+    double rt[3] = {f[1] * cam->up[2] - f[2] * cam->up[1], f[2] * cam->up[0] - f[0] * cam->up[2],
+                    f[0] * cam->up[1] - f[1] * cam->up[0]};
+    or_normalize(rt);
+    double uv[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2],
+                    rt[0] * f[1] - rt[1] * f[0]};
+    double th = tan(0.5 * cam->vfov_deg * OR_PI / 180.0);
+    double aspect = (double)cam->width / cam->height;
+    int64_t px = pixel % cam->width, py = pixel / cam->width;
+    double sx = (2.0 * (px + jx) / cam->width - 1.0) * th * aspect;
+    double sy = (1.0 - 2.0 * (py + jy) / cam->height) * th;
+    for (int i = 0; i < 3; ++i) {
+        o[i] = cam->eye[i];
+        d[i] = f[i] + sx * rt[i] + sy * uv[i];
+    }
+    or_normalize(d);
+}
+
+static or_path_result or_trace_path(const or_scene* sc, const or_camera* cam, const or_light* lt,
+                                    const or_medium* md, const or_render_desc* rd, int64_t pixel,
+                                    uint64_t sample) {
+    or_path_result res = {0.0, 0.0, 0.0};
+    const uint64_t id = (uint64_t)pixel | (sample << 32);
+    double jit[4];
+    or_uniform4(rd->seed, OR_TAG_RENDER_PIXEL, id, 0, jit);
+    double o[3], d[3];
+    or_camera_ray(cam, pixel, jit[0], jit[1], o, d);
+    const double phi = md->albedo;
+    const uint64_t surv_thr = (uint64_t)floor(phi * OR_U24);
+    uint32_t c0 = 0;
+    double t0[OR_MAX_IV], t1[OR_MAX_IV];
+    int m = or_ray_intervals(sc, o, d, t0, t1, OR_MAX_IV);
+    double t = 0.0;
+    uint32_t iters = 0;
+    for (;;) {
+        /* the medium interval that the ray is in or enters next */
+        int k = -1;
+        for (int i = 0; i < m; ++i)
+            if (t1[i] > t) {
+                k = i;
+                break;
+            }
+        if (k < 0) break; /* escapes to the black background */
+        if (t0[k] > t) t = t0[k];
+        uint32_t wv[4];
+        or_philox_blocks(rd->seed, OR_TAG_RENDER_PATH, id, c0++, 1, wv);
+        double l = -log(or_u01(wv[0])) / md->sigma_t;
+        if (t + l >= t1[k]) {
+            t = t1[k];
+            continue;
+        }
+        t += l;
+        double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+        if (rd->max_events && ++iters > rd->max_events) break;
+        if (rd->method == OR_METHOD_ST) {
+            double r = fmin(or_conservative_radius(sc, p), rd->st_max / md->sigma_t);
+            if (md->sigma_t * r >= rd->tau_min) {
+                or_step st;
+                if (rd->sampler == OR_SAMPLER_EXACT_WALK)
+                    or_exact_step(rd, md, id, &c0, p, d, r, &st);
+                else
+                    or_cvae_step(rd, md, id, &c0, p, d, r, &st);
+                res.steps += 1.0;
+                if (!st.survived) break;
+                res.value += or_lambda_weight(phi, st.N) * or_nee(sc, lt, md, st.X, st.W);
+                memcpy(o, st.x, sizeof o);
+                memcpy(d, st.w, sizeof d);
+                m = or_ray_intervals(sc, o, d, t0, t1, OR_MAX_IV);
+                t = 0.0;
+                continue;
+            }
+        }
+        /* plain event: NEE weighted by the albedo, roulette, HG scatter */
+        res.events += 1.0;
+        res.value += phi * or_nee(sc, lt, md, p, d);
+        if ((uint64_t)(wv[3] >> 8) + 1u > surv_thr) break;
+        double mu = or_hg_sample(md->g, or_u01(wv[1]));
+        or_scatter_dir(d, mu, 2.0 * OR_PI * or_u01(wv[2]));
+        memcpy(o, p, sizeof o);
+        m = or_ray_intervals(sc, o, d, t0, t1, OR_MAX_IV);
+        t = 0.0;
+    }
+    return res;
+}
+
+typedef struct {
+    const or_scene* sc;
+    const or_camera* cam;
+    const or_light* lt;
+    const or_medium* md;
+    const or_render_desc* rd;
+    const or_image_out* img;
+    int t, nt;
+} or_render_job;
+
+static void* or_render_worker(void* arg) {
+    or_render_job* j = (or_render_job*)arg;
+    const or_render_desc* rd = j->rd;
+    int64_t npx = rd->n_pixels > 0 ? rd->n_pixels : (int64_t)j->cam->width * j->cam->height;
+    for (int64_t q = j->t; q < npx; q += j->nt) {
+        int64_t pixel = rd->pixels ? rd->pixels[q] : q;
+        double s = 0.0, s2 = 0.0, ev = 0.0, stp = 0.0;
+        for (int32_t k = 0; k < rd->spp; ++k) {
+            or_path_result r =
+                or_trace_path(j->sc, j->cam, j->lt, j->md, rd, pixel, rd->sample_offset + (uint64_t)k);
+            s += r.value;
+            s2 += r.value * r.value;
+            ev += r.events;
+            stp += r.steps;
+        }
+        if (j->img->sum) j->img->sum[q] = s;
+        if (j->img->sumsq) j->img->sumsq[q] = s2;
+        if (j->img->events) j->img->events[q] = ev;
+        if (j->img->steps) j->img->steps[q] = stp;
+    }
+    return NULL;
+}
+
+int or_render(const or_scene* sc, const or_camera* cam, const or_light* light,
+              const or_medium* med, const or_render_desc* rd, const or_image_out* img) {
+    if (!sc || !cam || !light || !med || !rd || !img) return -1;
+    int nt = rd->n_threads > 0 ? rd->n_threads : 1;
+    if (nt > 256) nt = 256;
+    pthread_t th[256];
+    or_render_job jobs[256];
+    for (int t = 0; t < nt; ++t) {
+        or_render_job jb = {sc, cam, light, med, rd, img, t, nt};
+        jobs[t] = jb;
+        if (nt == 1) or_render_worker(&jobs[t]);
+        else pthread_create(&th[t], NULL, or_render_worker, &jobs[t]);
+    }
+    if (nt > 1)
+        for (int t = 0; t < nt; ++t) pthread_join(th[t], NULL);
+    return 0;
+}

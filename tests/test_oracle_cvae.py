@@ -1,0 +1,210 @@
+"""Pins of the oracle CVAE (Sec. 3.2, Sec. 4.2): gradients by central finite
+differences, closed forms of the ELBO terms, the AdamW update on a constant
+gradient, and the bfloat16 / FP8 rounding against torch's conversions."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+LOG2PI = math.log(2 * math.pi)
+
+
+def real_param_mask(shape):
+    """True where a parameter is a real weight or bias (not 16x16 padding)."""
+    nl = shape["n_linear"]
+    mask = np.zeros((2 * nl, 16 * 16 + 16), bool)
+    for net in range(2):
+        in0 = shape["latent"] + shape["p_in"] if net else shape["p_out"] + shape["p_in"]
+        outl = 2 * shape["p_out"] if net else 2 * shape["latent"]
+        for j in range(nl):
+            n_in = in0 if j == 0 else shape["width"]
+            n_out = outl if j == nl - 1 else shape["width"]
+            W = np.zeros((16, 16), bool)
+            W[:n_out, :n_in] = True
+            b = np.zeros(16, bool)
+            b[:n_out] = True
+            mask[net * nl + j] = np.concatenate([W.ravel(), b])
+    return mask.ravel()
+
+
+def batch(shape, B, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(B, shape["p_in"])), rng.normal(size=(B, shape["p_out"]))
+
+
+@pytest.mark.parametrize("name", ["length", "path", "event"])
+def test_gradient_central_differences(oracle, name):
+    shape = oracle.SHAPES[name]
+    p = oracle.cvae_init(shape, seed=3)
+    cond, target = batch(shape, 8, 4)
+    loss, kl, nll, grad = oracle.cvae_loss_grad(shape, p, cond, target, seed=9, step=2)
+    assert abs(loss - (kl + nll)) < 1e-12
+    idx = np.flatnonzero(real_param_mask(shape))
+    rng = np.random.default_rng(0)
+    for i in rng.choice(idx, 80, replace=False):
+        h = 1e-6 * max(1.0, abs(p[i]))
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (oracle.cvae_loss_grad(shape, pp, cond, target, 9, 2, want_grad=False)[0]
+              - oracle.cvae_loss_grad(shape, pm, cond, target, 9, 2, want_grad=False)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(grad[i])) + 1e-8, (i, fd, grad[i])
+    # padding never receives gradient
+    assert np.all(grad[~real_param_mask(shape)] == 0)
+
+
+def zero_last_layers(shape, p):
+    nl = shape["n_linear"]
+    p = p.copy()
+    for layer in (nl - 1, 2 * nl - 1):
+        p[layer * 272: (layer + 1) * 272] = 0.0
+    return p
+
+
+@pytest.mark.parametrize("name", ["length", "path", "event"])
+def test_elbo_closed_form_at_standard_normal(oracle, name):
+    """Zero output layers give mu = 0, log var = 0: KL = 0 and NLL = P/2 (log 2 pi) + |y|^2 / 2."""
+    shape = oracle.SHAPES[name]
+    p = zero_last_layers(shape, oracle.cvae_init(shape, seed=5))
+    cond, target = batch(shape, 16, 6)
+    loss, kl, nll, _ = oracle.cvae_loss_grad(shape, p, cond, target, seed=1, step=1)
+    assert kl == 0.0
+    exp = np.mean(0.5 * (shape["p_out"] * LOG2PI + np.sum(target**2, axis=1)))
+    assert abs(nll - exp) < 1e-12
+
+
+def test_softplus_identities(oracle):
+    for x in np.linspace(-30, 30, 121):
+        assert abs(oracle.softplus(x) - oracle.softplus(-x) - x) < 1e-12
+        if abs(x) < 20:
+            assert abs(oracle.softplus(x) - math.log1p(math.exp(x))) < 1e-12 * max(1, abs(x))
+
+
+def test_adamw_constant_gradient_closed_form(oracle):
+    n = 50
+    rng = np.random.default_rng(7)
+    g = rng.normal(size=n)
+    p0 = rng.normal(size=n)
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    lr, eps = 1e-3, 1e-8
+    for t in range(1, 4):
+        oracle.adamw_step(p, m, v, g, t, lr=lr, eps=eps)
+        # with a constant gradient m_hat = g and v_hat = g^2 at every step
+        np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-14)
+    # decoupled decay: zero gradient shrinks by (1 - lr wd) per step
+    q, m2, v2 = p0.copy(), np.zeros(n), np.zeros(n)
+    oracle.adamw_step(q, m2, v2, np.zeros(n), 1, lr=lr, weight_decay=0.1)
+    np.testing.assert_allclose(q, p0 * (1 - lr * 0.1), atol=1e-15)
+
+
+def test_bf16_rounding_matches_torch(oracle):
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.normal(size=3000) * 10.0 ** rng.integers(-6, 6, 3000),
+                        [0.0, -0.0, 1.0, 1 + 2**-8, 1 + 3 * 2**-8, 1 + 2**-9, 65504.0]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle.round_bf16(v) for v in x])
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_fp8_e4m3_rounding_matches_torch(oracle):
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-448, 448, 3000) * 10.0 ** rng.integers(-4, 1, 3000)
+    x = np.concatenate([x, [0.0, 448.0, -448.0, 2**-9, 2**-10, 3 * 2**-10, 0.5, 240.0, 232.0]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = np.array([oracle.round_fp8_e4m3(v) for v in x])
+    np.testing.assert_array_equal(got, ref)
+    assert oracle.round_fp8_e4m3(1000.0) == 448.0  # saturating
+
+
+@pytest.mark.parametrize("name", ["length", "path", "event"])
+def test_decode_of_bias_only_network(oracle, name):
+    shape = oracle.SHAPES[name]
+    nl = shape["n_linear"]
+    p = oracle.cvae_init(shape, seed=10)
+    last = 2 * nl - 1
+    p[last * 272: last * 272 + 256] = 0.0
+    P = shape["p_out"]
+    bias = p[last * 272 + 256: last * 272 + 256 + 2 * P]
+    z = np.random.default_rng(1).normal(size=shape["latent"])
+    c = np.random.default_rng(2).normal(size=shape["p_in"])
+    mu, lv = oracle.cvae_decode(shape, p, z, c)
+    np.testing.assert_array_equal(mu, bias[:P])
+    np.testing.assert_array_equal(lv, np.clip(bias[P:], -12, 8))
+
+
+@pytest.mark.parametrize("name", ["length", "path", "event"])
+def test_bf16_emulation_exact_on_representable_inputs(oracle, name):
+    """When weights and inputs are already bfloat16 values and the hidden
+    activations are not rounded differently, BF16 emulation equals FP64 on
+    the first layer's pre-activations; end to end it stays within bf16 error."""
+    shape = oracle.SHAPES[name]
+    p = np.array([oracle.round_bf16(v) for v in oracle.cvae_init(shape, seed=11)])
+    z = np.array([oracle.round_bf16(v) for v in np.random.default_rng(3).normal(size=shape["latent"])])
+    c = np.array([oracle.round_bf16(v) for v in np.random.default_rng(4).normal(size=shape["p_in"])])
+    mu64, lv64 = oracle.cvae_decode(shape, p, z, c, precision=oracle.PREC_FP64)
+    mu16, lv16 = oracle.cvae_decode(shape, p, z, c, precision=oracle.PREC_BF16)
+    np.testing.assert_allclose(mu16, mu64, atol=0.05)
+    np.testing.assert_allclose(lv16, lv64, atol=0.05)
+
+
+def test_sample_destandardises(oracle):
+    shape = oracle.SHAPES["path"]
+    p = oracle.cvae_init(shape, seed=12)
+    last = 2 * shape["n_linear"] - 1
+    p[last * 272: last * 272 + 256] = 0.0
+    P = shape["p_out"]
+    p[last * 272 + 256: last * 272 + 256 + P] = [0.5, -1.0, 2.0]
+    p[last * 272 + 256 + P: last * 272 + 256 + 2 * P] = -40.0  # clamped to -12
+    stats = np.zeros(64)
+    stats[16:32] = 1.0
+    stats[32:35] = [1.0, 2.0, 3.0]
+    stats[48:51] = [2.0, 0.5, 0.1]
+    cond = np.random.default_rng(5).normal(size=(1000, shape["p_in"]))
+    out = oracle.cvae_sample(shape, p, stats, cond, seed=3)
+    exp = np.array([0.5 * 2 + 1, -1.0 * 0.5 + 2, 2.0 * 0.1 + 3])
+    sd = np.exp(-6.0) * stats[48:51]
+    assert np.all(np.abs(out - exp) < 6 * sd)
+    # the residual is sqrt(Sigma) eps with eps standard normal
+    eps = (out - exp) / sd
+    assert abs(eps.mean()) < 0.1 and abs(eps.std() - 1) < 0.1
+
+
+@pytest.mark.parametrize("name", ["length", "path", "event"])
+def test_init_bounds(oracle, name):
+    shape = oracle.SHAPES[name]
+    p = oracle.cvae_init(shape, seed=13)
+    mask = real_param_mask(shape)
+    assert np.all(p[~mask] == 0)
+    nl = shape["n_linear"]
+    for layer in range(2 * nl):
+        blk = p[layer * 272:(layer + 1) * 272]
+        in0 = (shape["latent"] + shape["p_in"]) if layer >= nl else (shape["p_out"] + shape["p_in"])
+        fan = in0 if layer % nl == 0 else shape["width"]
+        assert np.all(np.abs(blk) <= 1 / math.sqrt(fan))
+
+
+def test_length_target_round_trip(oracle):
+    w = oracle.random_walk(5000, seed=3, mode=oracle.WALK_TRAINING)
+    cond, target = oracle.cvae_features(0, w, seed=4)
+    N = np.floor(np.exp(target[:, 0]) + 0.5)
+    np.testing.assert_array_equal(N, w["n_scatter"])
+    np.testing.assert_allclose(cond[:, 0], np.log(w["params"][0]))
+    c2, t2 = oracle.cvae_features(2, w, seed=4)
+    np.testing.assert_allclose(c2[:, 6], np.log(w["n_scatter"]))
+    np.testing.assert_allclose(t2[:, :3].T, w["event_pos"])
+
+
+def test_training_reduces_loss(oracle):
+    """Invariant of a working optimiser: 300 AdamW steps on a fixed batch lower the loss."""
+    shape = oracle.SHAPES["length"]
+    p = oracle.cvae_init(shape, seed=1)
+    m, v = np.zeros_like(p), np.zeros_like(p)
+    rng = np.random.default_rng(2)
+    cond = rng.normal(size=(64, 2))
+    target = (0.8 * cond[:, :1] - 0.3 * cond[:, 1:] ** 2) + 0.1 * rng.normal(size=(64, 1))
+    first = oracle.cvae_loss_grad(shape, p, cond, target, 5, 1)[0]
+    for t in range(1, 301):
+        loss, _, _, g = oracle.cvae_loss_grad(shape, p, cond, target, 5, t)
+        oracle.adamw_step(p, m, v, g, t, lr=3e-3)
+    assert loss < first - 0.3

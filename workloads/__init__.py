@@ -1,0 +1,118 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds only input descriptions and seeded generators (scene
+constants, cameras, lights, media, random weights and conditions).  It holds
+none of the method's arithmetic, so both the GPU library and the CPU oracle
+can be fed from it without sharing code.
+
+The paper's meshes are not available; the scenes are synthetic stand-ins with
+the structure of its workloads: a voluminous body with a thin part (sphere
+plus box arm), density doubling, strong forward scattering g = 0.8 and
+albedo near one.
+"""
+import numpy as np
+
+PRIM_SPHERE, PRIM_BOX = 0, 1
+
+# ---------------------------------------------------------------- walks
+WALK_C1 = dict(n_photons=100_000, seed=0, sigma_t=10.0, g=0.8, albedo=0.99, radius=1.0)
+WALK_C2 = dict(n_photons=1 << 24, seed=0, st_range=(0.1, 200.0), g_range=(-0.9, 0.95),
+               albedo_range=(0.9, 1.0))
+
+# ---------------------------------------------------------------- CVAE shapes
+SHAPES = {
+    "length": dict(model=0, p_in=2, p_out=1, latent=4, width=16, n_linear=3),
+    "path": dict(model=1, p_in=3, p_out=3, latent=4, width=16, n_linear=3),
+    "event": dict(model=2, p_in=7, p_out=6, latent=4, width=16, n_linear=3),
+}
+SHAPE_LIST = [SHAPES["length"], SHAPES["path"], SHAPES["event"]]
+TRAIN_C3 = dict(batch=4096, n_samples=1 << 22, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                weight_decay=0.0)
+
+
+# ---------------------------------------------------------------- scenes
+def prim_sphere(c, r):
+    return [PRIM_SPHERE, c[0], c[1], c[2], r, 0.0, 0.0, 0.0]
+
+
+def prim_box(c, half):
+    return [PRIM_BOX, c[0], c[1], c[2], half[0], half[1], half[2], 0.0]
+
+
+def scene_c4():
+    """Unit sphere at the origin united with a 1.6 x 0.8 x 0.8 box arm centred at (1.2, 0, 0)."""
+    return np.array([prim_sphere((0, 0, 0), 1.0), prim_box((1.2, 0, 0), (0.8, 0.4, 0.4))], np.float32)
+
+
+def scene_sphere(r=1.0):
+    return np.array([prim_sphere((0, 0, 0), r)], np.float32)
+
+
+def scene_c5(seed=0, n=64):
+    """64 spheres, radii U(0.05, 0.3), centres U(-0.7, 0.7)^3, from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-0.7, 0.7, size=(n, 3))
+    r = rng.uniform(0.05, 0.3, size=n)
+    return np.array([prim_sphere(c[i], r[i]) for i in range(n)], np.float32)
+
+
+def camera_c4(width=512, height=512):
+    return dict(eye=(0.5, 0.6, 4.5), look_at=(0.5, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=40.0,
+                width=width, height=height)
+
+
+def light_c4():
+    return dict(pos=(1.5, 3.0, 3.0), intensity=10.0)
+
+
+def medium_c4(sigma_t):
+    return dict(sigma_t=float(sigma_t), g=0.8, albedo=0.995)
+
+
+C4_SIGMAS = (10.0, 20.0, 40.0, 80.0)
+C4 = dict(width=512, height=512, spp=256, sigmas=C4_SIGMAS)
+
+
+def camera_c5(width=1024, height=1024):
+    return dict(eye=(0.0, 0.0, 3.2), look_at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=40.0,
+                width=width, height=height)
+
+
+def light_c5():
+    return dict(pos=(2.0, 2.5, 3.0), intensity=10.0)
+
+
+def medium_c5():
+    return dict(sigma_t=100.0, g=0.8, albedo=0.995)
+
+
+# ---------------------------------------------------------------- random inputs
+def random_conditions(model, n, seed):
+    """Raw (unstandardised) conditions spanning the training ranges of each model."""
+    rng = np.random.default_rng(seed)
+    lst = rng.uniform(np.log(0.1), np.log(200.0), n)
+    g = rng.uniform(-0.9, 0.95, n)
+    if model == 0:
+        return np.stack([lst, g], 1)
+    logn = rng.uniform(0.0, 8.0, n)
+    if model == 1:
+        return np.stack([lst, g, logn], 1)
+    phi = rng.uniform(0.9, 1.0, n)
+    ct = rng.uniform(-1, 1, n)
+    a = rng.uniform(-0.7, 0.7, n)
+    b = rng.uniform(-0.7, 0.7, n)
+    return np.stack([lst, g, phi, ct, a, b, logn], 1)
+
+
+def random_stats(model, seed):
+    """Plausible standardisation constants [mean_c, std_c, mean_y, std_y] (16 each)."""
+    rng = np.random.default_rng(seed)
+    st = np.zeros(64)
+    st[16:32] = 1.0
+    st[48:64] = 1.0
+    p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
+    st[:p_in] = rng.normal(0, 0.5, p_in)
+    st[16:16 + p_in] = rng.uniform(0.5, 2.0, p_in)
+    st[32:32 + p_out] = rng.normal(0, 0.5, p_out)
+    st[48:48 + p_out] = rng.uniform(0.3, 1.5, p_out)
+    return st
