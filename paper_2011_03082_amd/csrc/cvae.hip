@@ -1,0 +1,825 @@
+// cvae.hip -- conditional VAEs of Sec. 3.2 / Sec. 4.2 on gfx950: parameter
+// init, training features, FP64 column moments, fused forward + backward on
+// bfloat16 MFMA with FP32 master weights and AdamW, packing of the decoder
+// for inference, and decoder-only sampling.
+#include <math.h>
+
+#include "host.hpp"
+#include "packed.hpp"
+
+namespace msst {
+
+constexpr float kLvMin = -12.0f, kLvMax = 8.0f;
+constexpr float kLog2Pi = 1.83787706640934548f;
+constexpr int kTrainWaves = 4;  // waves per training block
+constexpr int kNL = 3;          // linear maps per network (two hidden layers)
+
+struct Shape {
+    int model, p_in, p_out, latent, width, n_linear;
+};
+
+__device__ __forceinline__ float clamp_lv(float x) { return __builtin_fminf(kLvMax, __builtin_fmaxf(kLvMin, x)); }
+__device__ __forceinline__ float clamp_mask(float x) { return (x > kLvMin && x < kLvMax) ? 1.0f : 0.0f; }
+
+// Normals n[4 j .. 4 j + 3] of Philox block c0 + j: Box-Muller on the word
+// pairs (0, 1) and (2, 3).
+__device__ __forceinline__ void normals4(const Rng& r, uint32_t c0, float* n) {
+    const uint4 w = r.block(c0);
+    box_muller(u01(w.x), u01(w.y), n[0], n[1]);
+    box_muller(u01(w.z), u01(w.w), n[2], n[3]);
+}
+
+// ---------------------------------------------------------------------------
+// init
+
+struct LayerDims {
+    int n_in, n_out;
+};
+__host__ __device__ inline LayerDims layer_dims(const Shape& s, int layer) {
+    const int nl = s.n_linear;
+    const bool dec = layer >= nl;
+    const int j = dec ? layer - nl : layer;
+    const int in0 = dec ? s.latent + s.p_in : s.p_out + s.p_in;
+    const int outl = dec ? 2 * s.p_out : 2 * s.latent;
+    return LayerDims{j == 0 ? in0 : s.width, j == nl - 1 ? outl : s.width};
+}
+
+__global__ void cvae_init_kernel(Shape s, uint64_t seed, float* master, int n_params) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_params) return;
+    const int layer = p / kLayerFloats, flat = p % kLayerFloats;
+    const LayerDims d = layer_dims(s, layer);
+    int row, col;
+    if (flat < kTile * kTile) {
+        row = flat / kTile;
+        col = flat % kTile;
+    } else {
+        row = flat - kTile * kTile;
+        col = 0;
+    }
+    float v = 0.0f;
+    if (row < d.n_out && col < d.n_in) {
+        const Rng r = make_rng(seed, MS_TAG_CVAE_INIT, (uint64_t)s.model);
+        const uint4 w = r.block((uint32_t)p >> 2);
+        const uint32_t word = (p & 3) == 0 ? w.x : (p & 3) == 1 ? w.y : (p & 3) == 2 ? w.z : w.w;
+        v = (2.0f * u01(word) - 1.0f) / sqrtf((float)d.n_in);
+    }
+    master[p] = v;
+}
+
+// ---------------------------------------------------------------------------
+// features (Sec. 4.2 model inputs; LengthGen target dequantised)
+
+__global__ void cvae_features_kernel(int model, int64_t n, const float* params3, const uint32_t* n_scatter,
+                                     const float* exit_param, const float* event_pos, const float* event_dir,
+                                     uint64_t seed, uint64_t id_offset, const double* stats, float* cond,
+                                     float* target) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float lst = logf(params3[i]), g = params3[n + i], phi = params3[2 * n + i];
+        const float N = (float)n_scatter[i];
+        float c[7], y[6];
+        int pc, py;
+        if (model == MS_MODEL_LENGTH) {
+            const Rng r = make_rng(seed, MS_TAG_DEQUANT, id_offset + (uint64_t)i);
+            const float u = u01(r.block(0).x);
+            c[0] = lst;
+            c[1] = g;
+            y[0] = logf(N + u - 0.5f);
+            pc = 2;
+            py = 1;
+        } else if (model == MS_MODEL_PATH) {
+            c[0] = lst;
+            c[1] = g;
+            c[2] = logf(N);
+            for (int k = 0; k < 3; ++k) y[k] = exit_param[k * n + i];
+            pc = 3;
+            py = 3;
+        } else {
+            c[0] = lst;
+            c[1] = g;
+            c[2] = phi;
+            for (int k = 0; k < 3; ++k) c[3 + k] = exit_param[k * n + i];
+            c[6] = logf(N);
+            for (int k = 0; k < 3; ++k) {
+                y[k] = event_pos[k * n + i];
+                y[3 + k] = event_dir[k * n + i];
+            }
+            pc = 7;
+            py = 6;
+        }
+        if (stats) {
+            for (int k = 0; k < pc; ++k) c[k] = (float)((c[k] - stats[k]) / stats[16 + k]);
+            for (int k = 0; k < py; ++k) y[k] = (float)((y[k] - stats[32 + k]) / stats[48 + k]);
+        }
+        for (int k = 0; k < pc; ++k) cond[i * pc + k] = c[k];
+        for (int k = 0; k < py; ++k) target[i * py + k] = y[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 column moments: deterministic two-pass (mean, then centred squares).
+
+constexpr int kMomBlocks = 256;
+
+__global__ void moments_partial_kernel(const float* x, int64_t n, int dim, const double* mean, double* partial) {
+    __shared__ double red[256][16];
+    double acc[16];
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < dim; ++k) {
+            double v = (double)x[i * dim + k];
+            if (mean) {
+                v -= mean[k];
+                v *= v;
+            }
+            acc[k] += v;
+        }
+    }
+    for (int k = 0; k < 16; ++k) red[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < dim; ++k) red[threadIdx.x][k] += red[threadIdx.x + off][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < dim) partial[blockIdx.x * 16 + threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ void moments_final_kernel(const double* partial, int nblocks, int64_t n, int dim, double* out,
+                                     int second_pass) {
+    const int k = threadIdx.x;
+    if (k >= dim) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[b * 16 + k];
+    if (!second_pass) out[k] = s / (double)n;
+    else out[16 + k] = sqrt(s / (double)n);
+}
+
+// ---------------------------------------------------------------------------
+// Training: fused forward + backward of encoder and decoder on 16-sample
+// tiles, one tile at a time per wave; per-block gradient partials.
+
+struct TrainArgs {
+    Shape s;
+    const float* master;
+    const float* cond;
+    const float* target;
+    int64_t n_rows;
+    int batch;
+    int sample_rows;
+    uint64_t seed;
+    int64_t step;
+    uint64_t id_offset;
+    float* partial;       // [blocks][n_params]
+    double* loss_partial; // [blocks][2]
+};
+
+// Per-wave LDS: inputs of the 6 layers and two work tiles.
+struct WaveLds {
+    float act[6][kTile * kTile];
+    float work[2][kTile * kTile];
+};
+
+__device__ __forceinline__ bf16x4 w_frag(const float* layer) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(layer + frag_row() * kTile + frag_k0());
+    return to_bf16x4(v);
+}
+__device__ __forceinline__ bf16x4 wt_frag(const float* layer) {
+    const int c = frag_row(), k0 = frag_k0();
+    return to_bf16x4(layer[(k0 + 0) * kTile + c], layer[(k0 + 1) * kTile + c], layer[(k0 + 2) * kTile + c],
+                     layer[(k0 + 3) * kTile + c]);
+}
+__device__ __forceinline__ f32x4 bias_d(const float* layer) {
+    const int k0 = frag_k0();
+    const float* b = layer + kTile * kTile;
+    return f32x4{b[k0], b[k0 + 1], b[k0 + 2], b[k0 + 3]};
+}
+
+// Forward of one net (NL layers starting at FIRST) from act[FIRST].
+template <int FIRST, int NL>
+__device__ __forceinline__ f32x4 net_forward(const float* master, WaveLds& L, f32x4* pre) {
+    constexpr int first = FIRST, nl = NL;
+    f32x4 acc;
+#pragma unroll
+    for (int j = 0; j < nl; ++j) {
+        const float* layer = master + (first + j) * kLayerFloats;
+        const bf16x4 x = to_bf16x4(tile_load_d(L.act[first + j]));
+        acc = mfma_bf16(w_frag(layer), x, bias_d(layer));
+        pre[first + j] = acc;
+        if (j < nl - 1) {
+            f32x4 a;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = bf16_round(softplus(acc[q]));
+            tile_store_d(L.act[first + j + 1], a);
+            wave_sync();
+        }
+    }
+    return acc;
+}
+
+// Backward of one net given d loss / d (last linear output) in D layout.
+// Accumulates dW (D layout: row = output unit, column = input unit) and db,
+// and returns d loss / d (input of the first layer) in D layout.
+template <int FIRST, int NL>
+__device__ __forceinline__ f32x4 net_backward(const float* master, WaveLds& L, const f32x4* pre, f32x4 dpre,
+                                              f32x4* dw, f32x4* db) {
+    constexpr int first = FIRST, nl = NL;
+    f32x4 dx = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int j = nl - 1; j >= 0; --j) {
+        const int layer = first + j;
+        const float* wl = master + layer * kLayerFloats;
+        db[layer] += dpre;
+        // dW += dPre X^T: both operands read transposed from LDS
+        tile_store_d(L.work[0], f32x4{bf16_round(dpre[0]), bf16_round(dpre[1]), bf16_round(dpre[2]),
+                                      bf16_round(dpre[3])});
+        wave_sync();
+        const bf16x4 a = to_bf16x4(tile_load_t(L.work[0]));
+        const bf16x4 b = to_bf16x4(tile_load_t(L.act[layer]));
+        dw[layer] = mfma_bf16(a, b, dw[layer]);
+        wave_sync();
+        // dX = W^T dPre
+        dx = mfma_bf16(wt_frag(wl), to_bf16x4(dpre), f32x4{0, 0, 0, 0});
+        if (j > 0) {
+            const f32x4 p = pre[layer - 1];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dpre[q] = dx[q] * sigmoid(p[q]);
+        }
+    }
+    return dx;
+}
+
+__global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
+    __shared__ WaveLds lds_all[kTrainWaves];
+    const int wave = threadIdx.x >> 6;
+    WaveLds& L = lds_all[wave];
+    const Shape s = a.s;
+    constexpr int nl = kNL;
+    const int P = s.p_out, Lt = s.latent, C = s.p_in;
+    const int lane = lane_id();
+    const float inv_b = 1.0f / (float)a.batch;
+
+    f32x4 dw[6], db[6], pre[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        dw[i] = f32x4{0, 0, 0, 0};
+        db[i] = f32x4{0, 0, 0, 0};
+    }
+    double kl_acc = 0.0, nll_acc = 0.0;
+
+    const int n_tiles = a.batch / kTile;
+    const int wave_global = blockIdx.x * kTrainWaves + wave;
+    const int n_waves = gridDim.x * kTrainWaves;
+    for (int tile = wave_global; tile < n_tiles; tile += n_waves) {
+        const int b = tile * kTile + (lane & 15);  // sample of this lane's column
+        // zero the two input tiles, then gather (target, cond) rows
+        for (int q = lane; q < kTile * kTile; q += 64) {
+            L.act[0][q] = 0.0f;
+            L.act[nl][q] = 0.0f;
+        }
+        wave_sync();
+        float mu_z[8], lv_z[8], lvr_z[8], eps[8];
+        if (lane < 16) {
+            int64_t row = b;
+            if (a.sample_rows) {
+                const Rng rb = make_rng(a.seed, MS_TAG_CVAE_BATCH, (uint64_t)b);
+                row = (int64_t)(((uint64_t)rb.block((uint32_t)a.step).x * (uint64_t)a.n_rows) >> 32);
+            }
+            for (int k = 0; k < P; ++k) L.act[0][k * kTile + lane] = bf16_round(a.target[row * P + k]);
+            for (int k = 0; k < C; ++k) {
+                const float cv = bf16_round(a.cond[row * C + k]);
+                L.act[0][(P + k) * kTile + lane] = cv;
+                L.act[nl][(Lt + k) * kTile + lane] = cv;
+            }
+        }
+        wave_sync();
+        // encoder
+        const f32x4 oe = net_forward<0, kNL>(a.master, L, pre);
+        tile_store_d(L.work[0], oe);
+        wave_sync();
+        if (lane < 16) {
+            const Rng rr = make_rng(a.seed, MS_TAG_CVAE_REPARAM, a.id_offset + (uint64_t)b);
+            for (int j = 0; 4 * j < Lt; ++j) normals4(rr, (uint32_t)(4 * a.step + j), eps + 4 * j);
+            float kl = 0.0f;
+            for (int i = 0; i < Lt; ++i) {
+                mu_z[i] = L.work[0][i * kTile + lane];
+                lvr_z[i] = L.work[0][(Lt + i) * kTile + lane];
+                lv_z[i] = clamp_lv(lvr_z[i]);
+                const float z = __builtin_fmaf(fast_exp(0.5f * lv_z[i]), eps[i], mu_z[i]);
+                L.act[nl][i * kTile + lane] = bf16_round(z);
+                kl += 0.5f * (mu_z[i] * mu_z[i] + fast_exp(lv_z[i]) - lv_z[i] - 1.0f);
+            }
+            kl_acc += (double)kl;
+        }
+        wave_sync();
+        // decoder
+        const f32x4 od = net_forward<kNL, kNL>(a.master, L, pre);
+        tile_store_d(L.work[0], od);
+        for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
+        wave_sync();
+        if (lane < 16) {
+            int64_t row = b;
+            if (a.sample_rows) {
+                const Rng rb = make_rng(a.seed, MS_TAG_CVAE_BATCH, (uint64_t)b);
+                row = (int64_t)(((uint64_t)rb.block((uint32_t)a.step).x * (uint64_t)a.n_rows) >> 32);
+            }
+            float nll = 0.0f;
+            for (int k = 0; k < P; ++k) {
+                const float mu = L.work[0][k * kTile + lane];
+                const float lvr = L.work[0][(P + k) * kTile + lane];
+                const float lv = clamp_lv(lvr);
+                const float y = a.target[row * P + k];
+                const float r = y - mu, iv = fast_exp(-lv);
+                nll += 0.5f * (kLog2Pi + lv + r * r * iv);
+                L.work[1][k * kTile + lane] = -r * iv * inv_b;
+                L.work[1][(P + k) * kTile + lane] = 0.5f * (1.0f - r * r * iv) * clamp_mask(lvr) * inv_b;
+            }
+            nll_acc += (double)nll;
+        }
+        wave_sync();
+        const f32x4 dzc = net_backward<kNL, kNL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
+        tile_store_d(L.work[0], dzc);
+        for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
+        wave_sync();
+        if (lane < 16) {
+            for (int i = 0; i < Lt; ++i) {
+                const float dz = L.work[0][i * kTile + lane];
+                const float sd = fast_exp(0.5f * lv_z[i]);
+                L.work[1][i * kTile + lane] = dz + mu_z[i] * inv_b;
+                L.work[1][(Lt + i) * kTile + lane] =
+                    (0.5f * dz * eps[i] * sd + 0.5f * (fast_exp(lv_z[i]) - 1.0f) * inv_b) * clamp_mask(lvr_z[i]);
+            }
+        }
+        wave_sync();
+        net_backward<0, kNL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
+        wave_sync();
+    }
+
+    // bias gradients: sum over the 16 sample columns of each lane group
+#pragma unroll
+    for (int i = 0; i < 2 * nl; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float v = db[i][q];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            v += __shfl_xor(v, 8);
+            db[i][q] = v;
+        }
+    }
+    __syncthreads();
+    // block reduction in a fixed order through LDS (reuses the tile space)
+    const int n_params = 2 * nl * kLayerFloats;
+    float* red = reinterpret_cast<float*>(lds_all);  // [kTrainWaves][n_params]
+    {
+        float* mine = red + wave * n_params;
+        const int c = frag_row(), k0 = frag_k0();
+#pragma unroll
+        for (int i = 0; i < 2 * nl; ++i) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mine[i * kLayerFloats + (k0 + q) * kTile + c] = dw[i][q];
+            if (c == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mine[i * kLayerFloats + kTile * kTile + k0 + q] = db[i][q];
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < n_params; p += blockDim.x) {
+        float acc = 0.0f;
+        for (int w = 0; w < kTrainWaves; ++w) acc += red[w * n_params + p];
+        a.partial[(int64_t)blockIdx.x * n_params + p] = acc;
+    }
+    // loss partials: lanes 0..15 of each wave hold sums
+    __syncthreads();
+    double* dred = reinterpret_cast<double*>(lds_all);
+    if (lane < 16) {
+        dred[(wave * 16 + lane) * 2 + 0] = kl_acc;
+        dred[(wave * 16 + lane) * 2 + 1] = nll_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double k = 0.0, n = 0.0;
+        for (int i = 0; i < kTrainWaves * 16; ++i) {
+            k += dred[i * 2 + 0];
+            n += dred[i * 2 + 1];
+        }
+        a.loss_partial[blockIdx.x * 2 + 0] = k;
+        a.loss_partial[blockIdx.x * 2 + 1] = n;
+    }
+}
+
+struct AdamArgs {
+    int n_params, n_blocks, batch;
+    const float* partial;
+    const double* loss_partial;
+    float* master;
+    float* m;
+    float* v;
+    float* grad_out;
+    double* loss_out;
+    int do_update;
+    float lr, beta1, beta2, eps, wd, bc1, bc2;
+};
+
+__global__ void cvae_adam_kernel(const AdamArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < a.n_params) {
+        float g = 0.0f;
+        for (int b = 0; b < a.n_blocks; ++b) g += a.partial[(int64_t)b * a.n_params + p];
+        if (a.grad_out) a.grad_out[p] = g;
+        if (a.do_update) {
+            const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * g;
+            const float v = a.beta2 * a.v[p] + (1.0f - a.beta2) * g * g;
+            a.m[p] = m;
+            a.v[p] = v;
+            const float mh = m / a.bc1, vh = v / a.bc2;
+            const float th = a.master[p];
+            a.master[p] = th - a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * th);
+        }
+    }
+    if (p == 0 && a.loss_out) {
+        double k = 0.0, n = 0.0;
+        for (int b = 0; b < a.n_blocks; ++b) {
+            k += a.loss_partial[b * 2 + 0];
+            n += a.loss_partial[b * 2 + 1];
+        }
+        a.loss_out[0] = (k + n) / a.batch;
+        a.loss_out[1] = k / a.batch;
+        a.loss_out[2] = n / a.batch;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pack
+
+__device__ __forceinline__ uint32_t fp8_e4m3_bits(float x) {
+    // OCP E4M3: bias 7, 3 mantissa bits, max 448, round to nearest even,
+    // saturating.
+    const uint32_t sign = x < 0.0f ? 0x80u : 0u;
+    float a = __builtin_fabsf(x);
+    if (!(a == a)) return 0x7fu | sign;
+    if (a >= 448.0f) return 0x7eu | sign;
+    if (a < 0x1p-10f) return sign;  // rounds to zero (half of the smallest subnormal 2^-9)
+    int e;
+    frexpf(a, &e);
+    int eu = e - 1;
+    if (eu < -6) eu = -6;
+    const float q = ldexpf(1.0f, eu - 3);
+    float m = rintf(a / q);  // ties to even
+    float v = m * q;
+    if (v > 448.0f) v = 448.0f;
+    // encode v
+    if (v < 0x1p-6f) return sign | (uint32_t)(v / 0x1p-9f);
+    int ev;
+    frexpf(v, &ev);
+    const int eb = ev - 1 + 7;
+    const uint32_t mant = (uint32_t)((v / ldexpf(1.0f, ev - 1) - 1.0f) * 8.0f + 0.5f);
+    return sign | ((uint32_t)eb << 3) | (mant & 7u);
+}
+
+__global__ void cvae_pack_kernel(Shape s, const float* master, const double* stats, int precision, PackedModel* pm) {
+    const int lane = threadIdx.x;  // 64 threads
+    const int nl = s.n_linear;
+    if (lane == 0) {
+        pm->magic = (int32_t)kPackedMagic;
+        pm->model = s.model;
+        pm->p_in = s.p_in;
+        pm->p_out = s.p_out;
+        pm->latent = s.latent;
+        pm->width = s.width;
+        pm->n_linear = nl;
+        pm->precision = precision;
+    }
+    if (lane < 16) {
+        pm->mean_c[lane] = stats ? (float)stats[lane] : 0.0f;
+        pm->inv_std_c[lane] = stats ? (float)(1.0 / stats[16 + lane]) : 1.0f;
+        pm->mean_y[lane] = stats ? (float)stats[32 + lane] : 0.0f;
+        pm->std_y[lane] = stats ? (float)stats[48 + lane] : 1.0f;
+    }
+    __shared__ float smax[64];
+    for (int j = 0; j < kMaxLayers; ++j) {
+        const bool real = j < nl;
+        const float* layer = master + (nl + (real ? j : 0)) * kLayerFloats;
+        float scale = 1.0f;
+        if (precision == MS_PREC_FP8) {
+            float mx = 0.0f;
+            for (int q = lane; q < kTile * kTile; q += 64) mx = fmaxf(mx, real ? fabsf(layer[q]) : 0.0f);
+            smax[lane] = mx;
+            __syncthreads();
+            for (int off = 32; off > 0; off >>= 1) {
+                if (lane < off) smax[lane] = fmaxf(smax[lane], smax[lane + off]);
+                __syncthreads();
+            }
+            scale = smax[0] > 0.0f ? smax[0] / 448.0f : 1.0f;
+            __syncthreads();
+        }
+        if (lane == 0) pm->w_scale[j] = scale;
+        if (lane < 16) pm->bias[j][lane] = real ? layer[kTile * kTile + lane] : 0.0f;
+        const int r = lane & 15, kg = lane >> 4;
+        uint32_t w0 = 0, w1 = 0;
+        if (real) {
+            if (precision == MS_PREC_FP8) {
+                // K = 32 operand: lane holds K = 8 kg .. 8 kg + 7; real K < 16
+                uint32_t bytes[8];
+                for (int q = 0; q < 8; ++q) {
+                    const int k = 8 * kg + q;
+                    bytes[q] = k < kTile ? fp8_e4m3_bits(layer[r * kTile + k] / scale) : 0u;
+                }
+                w0 = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | (bytes[3] << 24);
+                w1 = bytes[4] | (bytes[5] << 8) | (bytes[6] << 16) | (bytes[7] << 24);
+            } else {
+                const float* row = layer + r * kTile + 4 * kg;
+                w0 = (uint32_t)bf16_bits(row[0]) | ((uint32_t)bf16_bits(row[1]) << 16);
+                w1 = (uint32_t)bf16_bits(row[2]) | ((uint32_t)bf16_bits(row[3]) << 16);
+            }
+        }
+        pm->frag[j][lane][0] = w0;
+        pm->frag[j][lane][1] = w1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// decoder-only sampling: 64 paths per wave = four 16-path MFMA tiles
+
+constexpr int kSampleWaves = 4;
+
+struct SampleLds {
+    float x[64][kTile];
+    float o[64][kTile];
+};
+
+__global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm, const float* cond, int64_t n,
+                                                          uint64_t seed, uint64_t id_offset, float* out) {
+    __shared__ SampleLds lds_all[kSampleWaves];
+    SampleLds& L = lds_all[threadIdx.x >> 6];
+    const int lane = lane_id();
+    const int P = pm->p_out, Lt = pm->latent, C = pm->p_in;
+    const int64_t n_chunks = (n + 63) / 64;
+    const int64_t wave_global = blockIdx.x * (int64_t)kSampleWaves + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * kSampleWaves;
+    for (int64_t chunk = wave_global; chunk < n_chunks; chunk += n_waves) {
+        const int64_t i = chunk * 64 + lane;
+        const bool valid = i < n;
+        float nrm[16];
+        for (int q = 0; q < kTile; ++q) L.x[lane][q] = 0.0f;
+        if (valid) {
+            const Rng r = make_rng(seed, MS_TAG_CVAE_SAMPLE, id_offset + (uint64_t)i);
+            for (int j = 0; 4 * j < Lt + P; ++j) normals4(r, (uint32_t)j, nrm + 4 * j);
+            for (int q = 0; q < Lt; ++q) L.x[lane][q] = nrm[q];
+            for (int k = 0; k < C; ++k) L.x[lane][Lt + k] = (cond[i * C + k] - pm->mean_c[k]) * pm->inv_std_c[k];
+        }
+        wave_sync();
+        const int64_t remaining = n - chunk * 64;
+        const int n_tiles = remaining >= 64 ? 4 : (int)((remaining + 15) / 16);
+        for (int t = 0; t < n_tiles; ++t) {
+            const int path = 16 * t + frag_row();
+            const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
+            const f32x4 o = decoder_tile(pm, to_bf16x4(xin));
+            *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+        }
+        wave_sync();
+        if (valid) {
+            for (int k = 0; k < P; ++k) {
+                const float mu = L.o[lane][k];
+                const float lv = clamp_lv(L.o[lane][P + k]);
+                const float y = __builtin_fmaf(fast_exp(0.5f * lv), nrm[Lt + k], mu);
+                out[i * P + k] = __builtin_fmaf(y, pm->std_y[k], pm->mean_y[k]);
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+static ms_status check_shape(const ms_cvae_shape* sh, Shape* out) {
+    MS_REQUIRE(sh != nullptr, "CVAE shape is NULL");
+    MS_REQUIRE(sh->model >= 0 && sh->model <= 2, "CVAE model must be 0, 1 or 2");
+    MS_REQUIRE(sh->p_in >= 1 && sh->p_out >= 1 && sh->latent >= 1 && sh->width >= 1, "CVAE sizes must be positive");
+    if (sh->width > 16 || sh->p_out + sh->p_in > 16 || sh->latent + sh->p_in > 16 || 2 * sh->p_out > 16 ||
+        2 * sh->latent > 16 || sh->n_linear != 3 || sh->width != 16 || sh->latent > 8)
+        return set_error(MS_ERR_UNSUPPORTED,
+                         "CVAE shape unsupported: needs width 16, n_linear 3, latent <= 8, "
+                         "p_out + p_in <= 16, latent + p_in <= 16, 2 p_out <= 16");
+    *out = Shape{sh->model, sh->p_in, sh->p_out, sh->latent, sh->width, sh->n_linear};
+    return MS_OK;
+}
+
+static int train_blocks(int batch) {
+    const int tiles = batch / kTile;
+    int waves = tiles < 1024 ? tiles : 1024;
+    return (waves + kTrainWaves - 1) / kTrainWaves;
+}
+
+}  // namespace msst
+
+extern "C" {
+
+ms_status cvae_param_count(const ms_cvae_shape* shape, size_t* n_floats) {
+    msst::Shape s;
+    ms_status st = msst::check_shape(shape, &s);
+    if (st != MS_OK) return st;
+    MS_REQUIRE(n_floats != nullptr, "cvae_param_count: n_floats is NULL");
+    *n_floats = (size_t)(2 * s.n_linear * msst::kLayerFloats);
+    return MS_OK;
+}
+
+ms_status cvae_init(const ms_cvae_shape* shape, uint64_t seed, float* master_dev, void* stream) {
+    using namespace msst;
+    Shape s;
+    ms_status st = check_shape(shape, &s);
+    if (st != MS_OK) return st;
+    MS_REQUIRE(master_dev != nullptr, "cvae_init: master_dev is NULL");
+    int cus;
+    if ((st = device_cu_count(&cus)) != MS_OK) return st;
+    const int n = 2 * s.n_linear * kLayerFloats;
+    hipLaunchKernelGGL(cvae_init_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, s, seed,
+                       master_dev, n);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+ms_status cvae_features(int32_t model, int64_t n, const float* params3_dev, const uint32_t* n_scatter_dev,
+                        const float* exit_param_dev, const float* event_pos_dev, const float* event_dir_dev,
+                        uint64_t seed, uint64_t id_offset, const double* stats_dev, float* cond_dev,
+                        float* target_dev, void* stream) {
+    using namespace msst;
+    MS_REQUIRE(model >= 0 && model <= 2, "cvae_features: model must be 0, 1 or 2");
+    MS_REQUIRE(n > 0, "cvae_features: n must be positive");
+    MS_REQUIRE(params3_dev && n_scatter_dev && cond_dev && target_dev, "cvae_features: NULL array");
+    MS_REQUIRE(model == 0 || exit_param_dev, "cvae_features: exit_param is required for PathGen and EventGen");
+    MS_REQUIRE(model != 2 || (event_pos_dev && event_dir_dev), "cvae_features: event arrays required for EventGen");
+    int cus;
+    ms_status st = device_cu_count(&cus);
+    if (st != MS_OK) return st;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > cus * 8) blocks = cus * 8;
+    hipLaunchKernelGGL(cvae_features_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, model, n,
+                       params3_dev, n_scatter_dev, exit_param_dev, event_pos_dev, event_dir_dev, seed, id_offset,
+                       stats_dev, cond_dev, target_dev);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+ms_status ms_column_moments_workspace_size(int64_t n, int32_t dim, size_t* bytes) {
+    MS_REQUIRE(bytes != nullptr, "ms_column_moments_workspace_size: bytes is NULL");
+    *bytes = (size_t)msst::kMomBlocks * 16 * sizeof(double);
+    return MS_OK;
+}
+
+ms_status ms_column_moments(const float* x_dev, int64_t n, int32_t dim, double* out_dev, void* workspace_dev,
+                            size_t workspace_bytes, void* stream) {
+    using namespace msst;
+    MS_REQUIRE(x_dev && out_dev, "ms_column_moments: NULL array");
+    MS_REQUIRE(n > 0 && dim >= 1 && dim <= 16, "ms_column_moments: need n > 0 and 1 <= dim <= 16");
+    MS_REQUIRE(workspace_dev != nullptr, "ms_column_moments: workspace is NULL");
+    if (workspace_bytes < (size_t)kMomBlocks * 16 * sizeof(double))
+        return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "ms_column_moments: workspace too small");
+    int cus;
+    ms_status st = device_cu_count(&cus);
+    if (st != MS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double* partial = reinterpret_cast<double*>(workspace_dev);
+    hipLaunchKernelGGL(moments_partial_kernel, dim3(kMomBlocks), dim3(256), 0, s, x_dev, n, dim, (const double*)nullptr,
+                       partial);
+    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(64), 0, s, partial, kMomBlocks, n, dim, out_dev, 0);
+    hipLaunchKernelGGL(moments_partial_kernel, dim3(kMomBlocks), dim3(256), 0, s, x_dev, n, dim, (const double*)out_dev,
+                       partial);
+    hipLaunchKernelGGL(moments_final_kernel, dim3(1), dim3(64), 0, s, partial, kMomBlocks, n, dim, out_dev, 1);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+ms_status cvae_workspace_size(const ms_cvae_shape* shape, int32_t batch, size_t* bytes) {
+    using namespace msst;
+    Shape s;
+    ms_status st = check_shape(shape, &s);
+    if (st != MS_OK) return st;
+    MS_REQUIRE(bytes != nullptr, "cvae_workspace_size: bytes is NULL");
+    MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= (1 << 20), "cvae_workspace_size: batch must be a positive multiple of 16, <= 2^20");
+    const int nb = train_blocks(batch);
+    const int n_params = 2 * s.n_linear * kLayerFloats;
+    *bytes = align_up((size_t)nb * n_params * sizeof(float), 256) + (size_t)nb * 2 * sizeof(double);
+    return MS_OK;
+}
+
+ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev, float* adam_v_dev,
+                          const ms_adam* adam, const float* cond_dev, const float* target_dev, int64_t n_rows,
+                          int32_t batch, int32_t sample_rows, uint64_t seed, int64_t step, uint64_t id_offset,
+                          void* workspace_dev, size_t workspace_bytes, double* loss_dev, float* grad_dev,
+                          void* stream) {
+    using namespace msst;
+    Shape s;
+    ms_status st = check_shape(shape, &s);
+    if (st != MS_OK) return st;
+    MS_REQUIRE(master_dev && cond_dev && target_dev, "cvae_train_step: NULL array");
+    MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= (1 << 20), "cvae_train_step: batch must be a positive multiple of 16, <= 2^20");
+    MS_REQUIRE(n_rows > 0 && n_rows < ((int64_t)1 << 32), "cvae_train_step: n_rows must be in [1, 2^32)");
+    MS_REQUIRE(sample_rows || n_rows >= batch, "cvae_train_step: n_rows < batch without row sampling");
+    MS_REQUIRE(step >= 0 && step < ((int64_t)1 << 30), "cvae_train_step: step must be in [0, 2^30)");
+    if (adam) {
+        MS_REQUIRE(adam_m_dev && adam_v_dev, "cvae_train_step: AdamW moments are NULL");
+        MS_REQUIRE(adam->step >= 1, "cvae_train_step: AdamW step must be >= 1");
+        MS_REQUIRE(adam->lr > 0 && adam->beta1 >= 0 && adam->beta1 < 1 && adam->beta2 >= 0 && adam->beta2 < 1 &&
+                       adam->eps > 0 && adam->weight_decay >= 0,
+                   "cvae_train_step: invalid AdamW hyper-parameters");
+    }
+    size_t need = 0;
+    cvae_workspace_size(shape, batch, &need);
+    MS_REQUIRE(workspace_dev != nullptr, "cvae_train_step: workspace is NULL");
+    if (workspace_bytes < need) return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "cvae_train_step: workspace needs %zu bytes", need);
+    int cus;
+    if ((st = device_cu_count(&cus)) != MS_OK) return st;
+
+    const int nb = train_blocks(batch);
+    const int n_params = 2 * s.n_linear * kLayerFloats;
+    TrainArgs ta{};
+    ta.s = s;
+    ta.master = master_dev;
+    ta.cond = cond_dev;
+    ta.target = target_dev;
+    ta.n_rows = n_rows;
+    ta.batch = batch;
+    ta.sample_rows = sample_rows;
+    ta.seed = seed;
+    ta.step = step;
+    ta.id_offset = id_offset;
+    ta.partial = reinterpret_cast<float*>(workspace_dev);
+    ta.loss_partial = reinterpret_cast<double*>(reinterpret_cast<char*>(workspace_dev) +
+                                                align_up((size_t)nb * n_params * sizeof(float), 256));
+    hipStream_t hs = (hipStream_t)stream;
+    hipLaunchKernelGGL(cvae_train_kernel, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta);
+    MS_LAUNCHED();
+    AdamArgs aa{};
+    aa.n_params = n_params;
+    aa.n_blocks = nb;
+    aa.batch = batch;
+    aa.partial = ta.partial;
+    aa.loss_partial = ta.loss_partial;
+    aa.master = master_dev;
+    aa.m = adam_m_dev;
+    aa.v = adam_v_dev;
+    aa.grad_out = grad_dev;
+    aa.loss_out = loss_dev;
+    aa.do_update = adam != nullptr;
+    if (adam) {
+        aa.lr = (float)adam->lr;
+        aa.beta1 = (float)adam->beta1;
+        aa.beta2 = (float)adam->beta2;
+        aa.eps = (float)adam->eps;
+        aa.wd = (float)adam->weight_decay;
+        aa.bc1 = (float)(1.0 - pow(adam->beta1, (double)adam->step));
+        aa.bc2 = (float)(1.0 - pow(adam->beta2, (double)adam->step));
+    }
+    hipLaunchKernelGGL(cvae_adam_kernel, dim3((n_params + 255) / 256), dim3(256), 0, hs, aa);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+size_t cvae_packed_bytes(void) { return sizeof(msst::PackedModel); }
+
+ms_status cvae_pack(const ms_cvae_shape* shape, const float* master_dev, const double* stats_dev, int32_t precision,
+                    void* packed_dev, size_t packed_bytes, void* stream) {
+    using namespace msst;
+    Shape s;
+    ms_status st = check_shape(shape, &s);
+    if (st != MS_OK) return st;
+    MS_REQUIRE(master_dev && packed_dev, "cvae_pack: NULL array");
+    MS_REQUIRE(precision == MS_PREC_BF16 || precision == MS_PREC_FP8, "cvae_pack: precision must be BF16 or FP8");
+    MS_REQUIRE(((uintptr_t)packed_dev & 15u) == 0, "cvae_pack: packed buffer must be 16-byte aligned");
+    if (packed_bytes < sizeof(PackedModel))
+        return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "cvae_pack: packed buffer needs %zu bytes", sizeof(PackedModel));
+    int cus;
+    if ((st = device_cu_count(&cus)) != MS_OK) return st;
+    hipLaunchKernelGGL(cvae_pack_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, s, master_dev, stats_dev, precision,
+                       reinterpret_cast<PackedModel*>(packed_dev));
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+ms_status cvae_sample(const void* packed_dev, const float* cond_dev, int64_t n, uint64_t seed, uint64_t id_offset,
+                      float* out_dev, void* stream) {
+    using namespace msst;
+    MS_REQUIRE(packed_dev && cond_dev && out_dev, "cvae_sample: NULL array");
+    MS_REQUIRE(n > 0 && n < ((int64_t)1 << 40), "cvae_sample: n must be in [1, 2^40)");
+    MS_REQUIRE(((uintptr_t)packed_dev & 15u) == 0, "cvae_sample: packed buffer must be 16-byte aligned");
+    int cus;
+    ms_status st = device_cu_count(&cus);
+    if (st != MS_OK) return st;
+    int64_t blocks = (n + 64 * kSampleWaves - 1) / (64 * kSampleWaves);
+    if (blocks > cus * 8) blocks = cus * 8;
+    hipLaunchKernelGGL(cvae_sample_kernel, dim3((unsigned)blocks), dim3(64 * kSampleWaves), 0, (hipStream_t)stream,
+                       reinterpret_cast<const PackedModel*>(packed_dev), cond_dev, n, seed, id_offset, out_dev);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,756 @@
+// render.hip -- persistent path tracer with next-event estimation and the
+// learned sphere tracer (Sec. 3 and its overview figure; Sec. 4.1 radius
+// rescale and exit frame; Sec. 4.3 direct light at a representative event).
+//
+// One lane carries one camera path at a time.  Work units are
+// (pixel, chunk of samples), taken from a per-wave ticket pool, so waves stay
+// full however long individual scattering chains are.  Each iteration of the
+// wave loop has two phases:
+//   VALU phase -- every lane that is not waiting advances its path by one
+//                 free flight (plain scattering event, boundary crossing,
+//                 path start or end);
+//   MFMA phase -- once enough lanes wait for a learned sphere step, their
+//                 decoder inputs are compacted into 16-path tiles in LDS and
+//                 LengthGen, the absorption test, PathGen and EventGen run on
+//                 matrix cores for exactly those lanes.
+// Per-unit results go to a partial buffer and are reduced per pixel in a
+// fixed order, so images are bitwise reproducible.
+#include <math.h>
+
+#include "host.hpp"
+#include "packed.hpp"
+
+namespace msst {
+
+constexpr int kMaxPrims = 4;
+constexpr int kRenderWaves = 4;
+constexpr float kTwoPiRev = 1.0f;  // angles are passed in revolutions
+
+enum : int { S_IDLE = 0, S_NEW = 1, S_FLY = 2, S_WAIT = 3, S_DONE = 4 };
+
+struct RenderArgs {
+    const float* prims;  // device [n_prims][8]
+    int n_prims;
+    const uint16_t* grid;
+    int res;
+    float grid_lo[3], grid_inv_h[3], grid_half_diag;
+    float eye[3], fwd[3], right[3], upv[3];
+    int width, height;
+    int64_t npix;
+    float light[3], intensity;
+    float sigma_t, inv_sigma_t, g, albedo, ln_albedo;
+    uint32_t surv_thr;
+    int method, sampler;
+    const PackedModel* pm[3];
+    float tau_min, st_max;
+    int spp, chunk, n_chunks;
+    int64_t n_units;
+    uint64_t seed, sample_offset;
+    uint32_t max_events;
+    int batch_min;
+    float* part_sum;
+    float* part_comp;
+    float* part_sq;
+    uint32_t* part_events;
+    uint32_t* part_steps;
+    unsigned long long* ticket;
+    unsigned long long* counters;
+};
+
+// Primitives held in registers for the whole kernel.
+struct Prims {
+    float p[kMaxPrims][8];
+    int n;
+};
+
+struct RenderLds {
+    float x[64][kTile];
+    float o[64][kTile];
+};
+
+// ---------------------------------------------------------------- geometry
+
+__device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float& t0, float& t1) {
+    const V3 q = v3(o.x - pr[1], o.y - pr[2], o.z - pr[3]);
+    if (pr[0] == 0.0f) {  // sphere
+        const float b = dot(q, d);
+        const float c = dot(q, q) - pr[4] * pr[4];
+        const float disc = b * b - c;
+        if (!(disc > 0.0f)) return false;
+        const float s = __builtin_sqrtf(disc);
+        t0 = -b - s;
+        t1 = -b + s;
+        return true;
+    }
+    float lo = -INFINITY, hi = INFINITY;
+    const float qa[3] = {q.x, q.y, q.z}, da[3] = {d.x, d.y, d.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float h = pr[4 + a];
+        if (da[a] == 0.0f) {
+            if (qa[a] < -h || qa[a] > h) return false;
+            continue;
+        }
+        float ta = (-h - qa[a]) / da[a], tb = (h - qa[a]) / da[a];
+        if (ta > tb) {
+            const float tmp = ta;
+            ta = tb;
+            tb = tmp;
+        }
+        lo = __builtin_fmaxf(lo, ta);
+        hi = __builtin_fminf(hi, tb);
+    }
+    if (!(lo < hi)) return false;
+    t0 = lo;
+    t1 = hi;
+    return true;
+}
+
+// Intervals of one ray in each primitive (unused slots: [+inf, -inf]).
+struct RayIv {
+    float a[kMaxPrims], b[kMaxPrims];
+};
+
+__device__ __forceinline__ void ray_intervals(const Prims& P, V3 o, V3 d, RayIv& iv) {
+#pragma unroll
+    for (int i = 0; i < kMaxPrims; ++i) {
+        iv.a[i] = INFINITY;
+        iv.b[i] = -INFINITY;
+        float t0, t1;
+        if (i < P.n && prim_interval(P.p[i], o, d, t0, t1)) {
+            iv.a[i] = t0;
+            iv.b[i] = t1;
+        }
+    }
+}
+
+// The connected piece [s, e] of the union of primitive intervals that
+// contains t or starts first after it; false if the ray leaves for good.
+__device__ __forceinline__ bool union_piece(const RayIv& iv, float t, float& s, float& e) {
+    s = INFINITY;
+#pragma unroll
+    for (int i = 0; i < kMaxPrims; ++i)
+        if (iv.b[i] > t) s = __builtin_fminf(s, __builtin_fmaxf(iv.a[i], t));
+    if (s == INFINITY) return false;
+    e = s;
+#pragma unroll
+    for (int pass = 0; pass < kMaxPrims; ++pass)
+#pragma unroll
+        for (int i = 0; i < kMaxPrims; ++i)
+            if (iv.a[i] <= e && iv.b[i] > e) e = iv.b[i];
+    return true;
+}
+
+__device__ __forceinline__ float prim_sdf(const float* pr, V3 p) {
+    const V3 q = v3(p.x - pr[1], p.y - pr[2], p.z - pr[3]);
+    if (pr[0] == 0.0f) return __builtin_sqrtf(dot(q, q)) - pr[4];
+    const float ex = __builtin_fabsf(q.x) - pr[4], ey = __builtin_fabsf(q.y) - pr[5], ez = __builtin_fabsf(q.z) - pr[6];
+    const float ox = __builtin_fmaxf(ex, 0.0f), oy = __builtin_fmaxf(ey, 0.0f), oz = __builtin_fmaxf(ez, 0.0f);
+    const float inside = __builtin_fminf(__builtin_fmaxf(ex, __builtin_fmaxf(ey, ez)), 0.0f);
+    return __builtin_sqrtf(ox * ox + oy * oy + oz * oz) + inside;
+}
+
+__device__ __forceinline__ float fp16_value(uint16_t h) {
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// Radius of a sphere around p inside the body (see the C header): analytic
+// union distance shrunk by 0.1 %, or nearest grid voxel minus half a voxel
+// diagonal.
+__device__ __forceinline__ float conservative_radius(const RenderArgs& A, const Prims& P, V3 p) {
+    if (A.grid) {
+        const float fx = (p.x - A.grid_lo[0]) * A.grid_inv_h[0];
+        const float fy = (p.y - A.grid_lo[1]) * A.grid_inv_h[1];
+        const float fz = (p.z - A.grid_lo[2]) * A.grid_inv_h[2];
+        const float fr = (float)A.res;
+        if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f && fx < fr && fy < fr && fz < fr)) return 0.0f;
+        const int64_t ix = (int64_t)fx, iy = (int64_t)fy, iz = (int64_t)fz;
+        const float s = fp16_value(A.grid[(iz * A.res + iy) * A.res + ix]);
+        return __builtin_fmaxf(0.0f, -s - A.grid_half_diag);
+    }
+    float s = INFINITY;
+#pragma unroll
+    for (int i = 0; i < kMaxPrims; ++i)
+        if (i < P.n) s = __builtin_fminf(s, prim_sdf(P.p[i], p));
+    return s < 0.0f ? -0.999f * s : 0.0f;
+}
+
+// Point-light next-event estimate at x for a path travelling along d:
+// I rho_g(d . w_{x->L}) exp(-sigma_t d_t) / |x_L - x|^2 (Sec. 4.3).
+__device__ __forceinline__ float nee(const RenderArgs& A, const Prims& P, V3 x, V3 d) {
+    V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
+    const float dist2 = dot(wl, wl);
+    const float inv_dist = fast_rsq(dist2);
+    const float dist = dist2 * inv_dist;
+    wl = inv_dist * wl;
+    RayIv iv;
+    ray_intervals(P, x, wl, iv);
+    float acc = 0.0f, t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxPrims; ++k) {
+        float s, e;
+        if (t < dist && union_piece(iv, t, s, e) && s < dist) {
+            acc += __builtin_fminf(e, dist) - s;
+            t = e;
+        } else {
+            t = dist;
+        }
+    }
+    return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) / dist2;
+}
+
+// ---------------------------------------------------------------- kernel
+
+__device__ __forceinline__ void neumaier_add(float& sum, float& comp, float v) {
+    const float t = sum + v;
+    if (__builtin_fabsf(sum) >= __builtin_fabsf(v)) comp += (sum - t) + v;
+    else comp += (v - t) + sum;
+    sum = t;
+}
+
+// Sum_{i<=N} albedo^i / albedo^N = albedo (albedo^-N - 1) / (1 - albedo).
+__device__ __forceinline__ float lambda_weight(const RenderArgs& A, float N) {
+    if (A.albedo >= 1.0f) return N;
+    return A.albedo * (fast_exp(-N * A.ln_albedo) - 1.0f) / (1.0f - A.albedo);
+}
+
+// Stages this lane's decoder input (if `mine`) at its compacted slot, runs
+// the decoder on the occupied 16-path tiles and returns the de-standardised
+// sample y[0..P) of this lane.
+template <int P>
+__device__ __forceinline__ void decode_compacted(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
+                                                 const float* in16, const float* eps, float* y) {
+    if (mine) {
+#pragma unroll
+        for (int q = 0; q < kTile; ++q) L.x[slot][q] = in16[q];
+    }
+    wave_sync();
+    const int n_tiles = (n + 15) >> 4;
+    for (int t = 0; t < n_tiles; ++t) {
+        const int path = 16 * t + frag_row();
+        const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
+        const f32x4 o = decoder_tile(pm, to_bf16x4(xin));
+        *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+    }
+    wave_sync();
+    if (mine) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const float mu = L.o[slot][k];
+            const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.o[slot][P + k]));
+            const float ys = __builtin_fmaf(fast_exp(0.5f * lv), eps[k], mu);
+            y[k] = __builtin_fmaf(ys, pm->std_y[k], pm->mean_y[k]);
+        }
+    }
+    wave_sync();
+}
+
+__device__ __forceinline__ void draw_normals(const Rng& r, uint32_t& c0, int count, float* nrm) {
+    for (int j = 0; 4 * j < count; ++j) {
+        const uint4 w = r.block(c0++);
+        box_muller(u01(w.x), u01(w.y), nrm[4 * j + 0], nrm[4 * j + 1]);
+        box_muller(u01(w.z), u01(w.w), nrm[4 * j + 2], nrm[4 * j + 3]);
+    }
+}
+
+__global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
+    __shared__ RenderLds lds_all[kRenderWaves];
+    RenderLds& L = lds_all[threadIdx.x >> 6];
+    Prims P;
+    P.n = A.n_prims;
+#pragma unroll
+    for (int i = 0; i < kMaxPrims; ++i)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) P.p[i][k] = i < A.n_prims ? A.prims[i * 8 + k] : 0.0f;
+
+    TicketPool pool;
+    pool.reset();
+    int state = S_IDLE;
+    // unit state
+    int64_t pixel = 0, unit = 0;
+    int s = 0, s_end = 0;
+    float acc_sum = 0.0f, acc_comp = 0.0f, acc_sq = 0.0f;
+    uint32_t acc_ev = 0, acc_st = 0;
+    // path state
+    Rng rng = make_rng(A.seed, MS_TAG_RENDER_PATH, 0);
+    V3 o = v3(0, 0, 0), d = v3(0, 0, 1);
+    float t = 0.0f, Lp = 0.0f, r_step = 0.0f;
+    uint32_t c0 = 0, iters = 0, p_ev = 0, p_st = 0;
+    RayIv iv;
+    uint64_t cnt_paths = 0, cnt_events = 0, cnt_steps = 0, cnt_trunc = 0;
+
+    for (;;) {
+        // ---- work units
+        const bool need = state == S_IDLE;
+        const uint64_t tk = pool.take(need, A.ticket, 64);
+        if (need) {
+            if (tk < (uint64_t)A.n_units) {
+                unit = (int64_t)tk;
+                const int64_t ch = unit / A.npix;
+                pixel = unit - ch * A.npix;
+                s = (int)ch * A.chunk;
+                s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
+                acc_sum = acc_comp = acc_sq = 0.0f;
+                acc_ev = acc_st = 0;
+                state = S_NEW;
+            } else {
+                state = S_DONE;
+            }
+        }
+        if (ballot(state != S_DONE) == 0) break;
+
+        // ---- VALU phase
+        bool path_end = false, truncated = false;
+        if (state == S_NEW) {
+            const uint64_t sample = A.sample_offset + (uint64_t)s;
+            const uint64_t id = (uint64_t)pixel | (sample << 32);
+            const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
+            const uint4 jw = rp.block(0);
+            rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
+            const int64_t py = pixel / A.width, px = pixel - py * A.width;
+            const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
+            const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
+            o = v3(A.eye[0], A.eye[1], A.eye[2]);
+            d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0], A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
+                             A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
+            ray_intervals(P, o, d, iv);
+            t = 0.0f;
+            Lp = 0.0f;
+            c0 = 0;
+            iters = 0;
+            p_ev = 0;
+            p_st = 0;
+            state = S_FLY;
+        }
+        if (state == S_FLY) {
+            float ps, pe;
+            if (!union_piece(iv, t, ps, pe)) {
+                path_end = true;
+            } else {
+                t = __builtin_fmaxf(t, ps);
+                const uint4 w = rng.block(c0++);
+                const float l = -fast_ln(u01(w.x)) * A.inv_sigma_t;
+                if (t + l >= pe) {
+                    t = pe;
+                } else {
+                    t += l;
+                    const V3 p = fma3(t, d, o);
+                    if (++iters > A.max_events) {
+                        path_end = true;
+                        truncated = true;
+                    } else {
+                        bool plain = true;
+                        if (A.method == MS_METHOD_ST) {
+                            const float r = __builtin_fminf(conservative_radius(A, P, p), A.st_max * A.inv_sigma_t);
+                            if (A.sigma_t * r >= A.tau_min) {
+                                plain = false;
+                                if (A.sampler == MS_SAMPLER_EXACT_WALK) {
+                                    // the actual walk inside the sphere (reference sampler)
+                                    V3 x = p, dir = d, Xk = p, Wk = d;
+                                    float resv = 0.0f;
+                                    const float r2 = r * r;
+                                    const float inv_phi = 1.0f / A.albedo;
+                                    uint32_t nev = 0;
+                                    for (;;) {
+                                        if (++nev > A.max_events) break;  // bounded even for degenerate input
+                                        const uint4 ww = rng.block(c0++);
+                                        resv = nev == 1 ? 1.0f : __builtin_fmaf(resv, inv_phi, 1.0f);
+                                        if (u01(ww.w) * resv <= 1.0f) {
+                                            Xk = x;
+                                            Wk = dir;
+                                        }
+                                        const HgSample h = hg_sample(A.g, u01(ww.y));
+                                        dir = scatter(dir, h.mu, h.sin_t, u01(ww.z));
+                                        const float ll = -fast_ln(u01(ww.x)) * A.inv_sigma_t;
+                                        const V3 rel = x - p;
+                                        const V3 qn = fma3(ll, dir, rel);
+                                        if (!(dot(qn, qn) < r2)) {
+                                            x = fma3(sphere_exit(rel, dir, r2), dir, x);
+                                            break;
+                                        }
+                                        x = fma3(ll, dir, x);
+                                    }
+                                    ++p_st;
+                                    const uint4 wa = rng.block(c0++);
+                                    const float N = (float)nev;
+                                    if (!(u01(wa.x) <= fast_exp(N * A.ln_albedo))) {
+                                        path_end = true;
+                                    } else {
+                                        Lp += lambda_weight(A, N) * nee(A, P, Xk, Wk);
+                                        o = x;
+                                        d = dir;
+                                        ray_intervals(P, o, d, iv);
+                                        t = 0.0f;
+                                    }
+                                } else {
+                                    o = p;
+                                    r_step = r;
+                                    state = S_WAIT;
+                                }
+                            }
+                        }
+                        if (plain) {
+                            ++p_ev;
+                            Lp += A.albedo * nee(A, P, p, d);
+                            if (u24(w.w) > A.surv_thr) {
+                                path_end = true;
+                            } else {
+                                const HgSample h = hg_sample(A.g, u01(w.y));
+                                d = scatter(d, h.mu, h.sin_t, u01(w.z));
+                                o = p;
+                                ray_intervals(P, o, d, iv);
+                                t = 0.0f;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+
+        // ---- MFMA phase: learned sphere steps for the waiting lanes
+        const uint64_t wmask = ballot(state == S_WAIT);
+        const uint64_t lmask = ballot(state == S_NEW || state == S_FLY || state == S_WAIT);
+        const int n_wait = __popcll(wmask);
+        if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask)) {
+            const bool mine = state == S_WAIT;
+            float nrm[12], in16[kTile], y[6];
+            float N = 1.0f, psi = 0.0f;
+            const float str = A.sigma_t * r_step;
+            const float lst = fast_ln(str);
+            // LengthGen (sigma_t r, g) -> N
+            const PackedModel* pl = A.pm[0];
+            if (mine) {
+                draw_normals(rng, c0, 5, nrm);
+#pragma unroll
+                for (int q = 0; q < kTile; ++q) in16[q] = 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) in16[q] = nrm[q];
+                in16[4] = (lst - pl->mean_c[0]) * pl->inv_std_c[0];
+                in16[5] = (A.g - pl->mean_c[1]) * pl->inv_std_c[1];
+            }
+            decode_compacted<1>(pl, L, mine, rank_in(wmask), n_wait, in16, nrm + 4, y);
+            bool alive = false;
+            if (mine) {
+                ++p_st;
+                N = __builtin_fmaxf(1.0f, floorf(fast_exp(__builtin_fminf(y[0], 20.0f)) + 0.5f));
+                const uint4 wa = rng.block(c0++);
+                psi = u01(wa.y);
+                // absorption along the bypassed chain (Sec. 3.2)
+                alive = u01(wa.x) <= fast_exp(N * A.ln_albedo);
+                if (!alive) path_end = true;
+            }
+            const uint64_t amask = ballot(alive);
+            const int n_alive = __popcll(amask);
+            if (n_alive > 0) {
+                const int slot = rank_in(amask);
+                // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
+                const PackedModel* pp = A.pm[1];
+                const float lnN = fast_ln(N);
+                if (alive) {
+                    draw_normals(rng, c0, 7, nrm);
+#pragma unroll
+                    for (int q = 0; q < kTile; ++q) in16[q] = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) in16[q] = nrm[q];
+                    in16[4] = (lst - pp->mean_c[0]) * pp->inv_std_c[0];
+                    in16[5] = (A.g - pp->mean_c[1]) * pp->inv_std_c[1];
+                    in16[6] = (lnN - pp->mean_c[2]) * pp->inv_std_c[2];
+                }
+                decode_compacted<3>(pp, L, alive, slot, n_alive, in16, nrm + 4, y);
+                float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
+                if (alive) {
+                    ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
+                    al = y[1];
+                    be = y[2];
+                    ga = __builtin_sqrtf(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
+                    const float inl = fast_rsq(al * al + be * be + ga * ga);
+                    al *= inl;
+                    be *= inl;
+                    ga *= inl;
+                }
+                // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
+                const PackedModel* pe = A.pm[2];
+                if (alive) {
+                    draw_normals(rng, c0, 10, nrm);
+                    const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
+#pragma unroll
+                    for (int q = 0; q < kTile; ++q) in16[q] = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) in16[q] = nrm[q];
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) in16[4 + k] = (c7[k] - pe->mean_c[k]) * pe->inv_std_c[k];
+                }
+                decode_compacted<6>(pe, L, alive, slot, n_alive, in16, nrm + 4, y);
+                if (alive) {
+                    V3 X = v3(y[0], y[1], y[2]), W = v3(y[3], y[4], y[5]);
+                    const float xl2 = dot(X, X);
+                    if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
+                    const float wl2 = dot(W, W);
+                    W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
+                    // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
+                    V3 e1, e2;
+                    onb(d, e1, e2);
+                    const float cp = cos_rev(psi), sp = sin_rev(psi);
+                    const float st = __builtin_sqrtf(__builtin_fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+                    const V3 xt = v3(st * cp, st * sp, ct);
+                    const V3 w0 = v3(be * ct + ga * st, al, -be * st + ga * ct);
+                    const V3 wt = v3(cp * w0.x - sp * w0.y, sp * w0.x + cp * w0.y, w0.z);
+                    const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
+                    const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
+                    const V3 xw = o + r_step * (xt.x * e1 + xt.y * e2 + xt.z * d);
+                    const V3 ww = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
+                    const V3 Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
+                    const V3 Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
+                    Lp += lambda_weight(A, N) * nee(A, P, Xw, Ww);
+                    o = xw;
+                    d = ww;
+                    ray_intervals(P, o, d, iv);
+                    t = 0.0f;
+                    state = S_FLY;
+                }
+            }
+        }
+
+        // ---- path and unit ends
+        if (path_end) {
+            neumaier_add(acc_sum, acc_comp, Lp);
+            acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
+            acc_ev += p_ev;
+            acc_st += p_st;
+            ++cnt_paths;
+            cnt_events += p_ev;
+            cnt_steps += p_st;
+            cnt_trunc += truncated;
+            ++s;
+            if (s >= s_end) {
+                A.part_sum[unit] = acc_sum;
+                A.part_comp[unit] = acc_comp;
+                A.part_sq[unit] = acc_sq;
+                A.part_events[unit] = acc_ev;
+                A.part_steps[unit] = acc_st;
+                state = S_IDLE;
+            } else {
+                state = S_NEW;
+            }
+        }
+    }
+    if (A.counters) {
+        const uint64_t a0 = wave_sum_u64(cnt_paths), a1 = wave_sum_u64(cnt_events);
+        const uint64_t a2 = wave_sum_u64(cnt_steps), a3 = wave_sum_u64(cnt_trunc);
+        if (lane_id() == 0) {
+            atomicAdd(A.counters + 0, (unsigned long long)a0);
+            atomicAdd(A.counters + 1, (unsigned long long)a1);
+            atomicAdd(A.counters + 2, (unsigned long long)a2);
+            atomicAdd(A.counters + 3, (unsigned long long)a3);
+        }
+    }
+}
+
+// Per-pixel fixed-order reduction of the unit partials, added to the image
+// with the compensation carried in the comp buffer.
+__global__ void render_reduce_kernel(int64_t npix, int n_chunks, const float* part_sum, const float* part_comp,
+                                     const float* part_sq, const uint32_t* part_events, const uint32_t* part_steps,
+                                     float* sum, float* comp, float* sumsq, uint32_t* events, uint32_t* steps,
+                                     const unsigned long long* bad_models) {
+    if (*bad_models) {
+        // invalid packed models: no path was traced; poison the image
+        for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
+            sum[p] = __builtin_nanf("");
+        return;
+    }
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
+        double s = (double)sum[p] + (comp ? (double)comp[p] : 0.0);
+        double q = sumsq ? (double)sumsq[p] : 0.0;
+        uint32_t ev = events ? events[p] : 0u, st = steps ? steps[p] : 0u;
+        for (int c = 0; c < n_chunks; ++c) {
+            const int64_t u = (int64_t)c * npix + p;
+            s += (double)part_sum[u] + (double)part_comp[u];
+            q += (double)part_sq[u];
+            ev += part_events[u];
+            st += part_steps[u];
+        }
+        const float sf = (float)s;
+        sum[p] = sf;
+        if (comp) comp[p] = (float)(s - (double)sf);
+        if (sumsq) sumsq[p] = (float)q;
+        if (events) events[p] = ev;
+        if (steps) steps[p] = st;
+    }
+}
+
+__global__ void render_check_models(const RenderArgs A, unsigned long long* flag) {
+    if (threadIdx.x != 0) return;
+    const int want_in[3] = {2, 3, 7}, want_out[3] = {1, 3, 6};
+    int ok = 1;
+    for (int m = 0; m < 3; ++m) {
+        const PackedModel* pm = A.pm[m];
+        ok &= pm->magic == (int32_t)kPackedMagic && pm->model == m && pm->latent == 4 && pm->p_in == want_in[m] &&
+              pm->p_out == want_out[m] && pm->precision == MS_PREC_BF16 && pm->n_linear == 3;
+    }
+    *flag = ok ? 0ull : 1ull;
+}
+
+__global__ void render_zero_kernel(unsigned long long* ticket, unsigned long long* flag) {
+    if (threadIdx.x == 0) {
+        ticket[0] = 0ull;
+        flag[0] = 0ull;
+    }
+}
+
+// With invalid models the ticket counter starts past the last unit, so the
+// render kernel does no work, and the reduction poisons the image.
+__global__ void render_gate_kernel(const unsigned long long* flag, unsigned long long* ticket, int64_t n_units) {
+    if (threadIdx.x == 0) ticket[0] = flag[0] ? (unsigned long long)n_units : 0ull;
+}
+
+static int default_chunk(int spp) {
+    int c = 16;
+    if (spp >= 1024) c = 64;
+    if (c > spp) c = spp;
+    return c;
+}
+
+}  // namespace msst
+
+extern "C" {
+
+ms_status sphere_trace_render_workspace_size(const ms_camera* cam, const ms_render_desc* desc, size_t* bytes) {
+    using namespace msst;
+    MS_REQUIRE(cam && desc && bytes, "sphere_trace_render_workspace_size: NULL argument");
+    MS_REQUIRE(cam->width > 0 && cam->height > 0, "sphere_trace_render_workspace_size: empty image");
+    MS_REQUIRE(desc->spp > 0, "sphere_trace_render_workspace_size: spp must be positive");
+    const int chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(desc->spp);
+    const int64_t n_chunks = (desc->spp + chunk - 1) / chunk;
+    const int64_t n_units = (int64_t)cam->width * cam->height * n_chunks;
+    *bytes = 256 + align_up((size_t)n_units * 4, 256) * 5;
+    return MS_OK;
+}
+
+ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const ms_light* light,
+                              const ms_medium* medium, const ms_render_desc* desc, const ms_image_out* out,
+                              void* workspace_dev, size_t workspace_bytes, void* stream) {
+    using namespace msst;
+    MS_REQUIRE(scene && cam && light && medium && desc && out, "sphere_trace_render: NULL descriptor");
+    MS_REQUIRE(scene->prims != nullptr && scene->n_prims >= 1 && scene->n_prims <= kMaxPrims,
+               "sphere_trace_render: need 1..4 primitives");
+    MS_REQUIRE(cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < ((int64_t)1 << 31),
+               "sphere_trace_render: image size must be positive and below 2^31 pixels");
+    MS_REQUIRE(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f, "sphere_trace_render: vfov must be in (0, 180)");
+    MS_REQUIRE(medium->sigma_t > 0.0f && medium->g > -1.0f && medium->g < 1.0f && medium->albedo > 0.0f &&
+                   medium->albedo <= 1.0f,
+               "sphere_trace_render: need sigma_t > 0, |g| < 1, albedo in (0, 1]");
+    MS_REQUIRE(desc->method == MS_METHOD_PLAIN_NEE || desc->method == MS_METHOD_ST,
+               "sphere_trace_render: method must be PLAIN_NEE or ST");
+    MS_REQUIRE(desc->sampler == MS_SAMPLER_CVAE || desc->sampler == MS_SAMPLER_EXACT_WALK,
+               "sphere_trace_render: unknown sampler");
+    const bool learned = desc->method == MS_METHOD_ST && desc->sampler == MS_SAMPLER_CVAE;
+    MS_REQUIRE(!learned || (desc->packed[0] && desc->packed[1] && desc->packed[2]),
+               "sphere_trace_render: ST with the CVAE sampler needs three packed models");
+    MS_REQUIRE(desc->spp > 0 && desc->spp <= (1 << 24), "sphere_trace_render: spp must be in [1, 2^24]");
+    MS_REQUIRE(desc->chunk >= 0 && desc->blocks_per_cu >= 0 && desc->blocks_per_cu <= 64 && desc->cvae_batch_min >= 0 &&
+                   desc->cvae_batch_min <= 64,
+               "sphere_trace_render: invalid launch parameters");
+    MS_REQUIRE(desc->tau_min >= 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min >= 0, st_max > 0");
+    MS_REQUIRE(out->sum && out->sumsq, "sphere_trace_render: sum and sumsq images are required");
+    MS_REQUIRE(scene->sdf_fp16 == nullptr || (scene->res > 0 && scene->res <= 4096 && scene->hi[0] > scene->lo[0] &&
+                                             scene->hi[1] > scene->lo[1] && scene->hi[2] > scene->lo[2]),
+               "sphere_trace_render: invalid SDF grid description");
+    size_t need = 0;
+    sphere_trace_render_workspace_size(cam, desc, &need);
+    MS_REQUIRE(workspace_dev != nullptr, "sphere_trace_render: workspace is NULL");
+    if (workspace_bytes < need)
+        return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "sphere_trace_render: workspace needs %zu bytes", need);
+    int cus;
+    ms_status st = device_cu_count(&cus);
+    if (st != MS_OK) return st;
+
+    RenderArgs A{};
+    A.prims = scene->prims;
+    A.n_prims = scene->n_prims;
+    A.grid = scene->sdf_fp16;
+    A.res = scene->res;
+    for (int k = 0; k < 3; ++k) {
+        A.grid_lo[k] = scene->lo[k];
+        A.grid_inv_h[k] = scene->res > 0 ? (float)(scene->res / ((double)scene->hi[k] - scene->lo[k])) : 0.0f;
+    }
+    double hmax = 0.0;
+    for (int k = 0; k < 3; ++k)
+        if (scene->res > 0) hmax = fmax(hmax, ((double)scene->hi[k] - scene->lo[k]) / scene->res);
+    A.grid_half_diag = (float)(0.5 * sqrt(3.0) * hmax);
+    // camera basis in double, as the pinhole definition reads
+    double f[3], up[3] = {cam->up[0], cam->up[1], cam->up[2]};
+    for (int k = 0; k < 3; ++k) f[k] = (double)cam->look_at[k] - cam->eye[k];
+    double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (int k = 0; k < 3; ++k) f[k] /= fl;
+    double rt[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    double rl = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    MS_REQUIRE(rl > 0.0, "sphere_trace_render: up is parallel to the view direction");
+    for (int k = 0; k < 3; ++k) rt[k] /= rl;
+    double uv[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
+    const double th = tan(0.5 * cam->vfov_deg * M_PI / 180.0), aspect = (double)cam->width / cam->height;
+    for (int k = 0; k < 3; ++k) {
+        A.eye[k] = cam->eye[k];
+        A.fwd[k] = (float)f[k];
+        A.right[k] = (float)(rt[k] * th * aspect);
+        A.upv[k] = (float)(uv[k] * th);
+        A.light[k] = light->pos[k];
+    }
+    A.width = cam->width;
+    A.height = cam->height;
+    A.npix = (int64_t)cam->width * cam->height;
+    A.intensity = light->intensity;
+    A.sigma_t = medium->sigma_t;
+    A.inv_sigma_t = 1.0f / medium->sigma_t;
+    A.g = medium->g;
+    A.albedo = medium->albedo;
+    A.ln_albedo = (float)log((double)medium->albedo);
+    A.surv_thr = (uint32_t)floor((double)medium->albedo * 16777216.0);
+    A.method = desc->method;
+    A.sampler = desc->sampler;
+    for (int m = 0; m < 3; ++m) A.pm[m] = reinterpret_cast<const PackedModel*>(desc->packed[m]);
+    A.tau_min = desc->tau_min;
+    A.st_max = desc->st_max;
+    A.spp = desc->spp;
+    A.chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(desc->spp);
+    A.n_chunks = (desc->spp + A.chunk - 1) / A.chunk;
+    A.n_units = A.npix * A.n_chunks;
+    A.seed = desc->seed;
+    A.sample_offset = desc->sample_offset;
+    A.max_events = desc->max_events ? desc->max_events : (1u << 20);
+    A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 32;
+    char* ws = reinterpret_cast<char*>(workspace_dev);
+    A.ticket = reinterpret_cast<unsigned long long*>(ws);
+    unsigned long long* flag = A.ticket + 1;
+    const size_t plane = align_up((size_t)A.n_units * 4, 256);
+    A.part_sum = reinterpret_cast<float*>(ws + 256);
+    A.part_comp = reinterpret_cast<float*>(ws + 256 + plane);
+    A.part_sq = reinterpret_cast<float*>(ws + 256 + 2 * plane);
+    A.part_events = reinterpret_cast<uint32_t*>(ws + 256 + 3 * plane);
+    A.part_steps = reinterpret_cast<uint32_t*>(ws + 256 + 4 * plane);
+    A.counters = reinterpret_cast<unsigned long long*>(out->counters);
+
+    hipStream_t hs = (hipStream_t)stream;
+    if (learned) {
+        hipLaunchKernelGGL(render_check_models, dim3(1), dim3(64), 0, hs, A, flag);
+        hipLaunchKernelGGL(render_gate_kernel, dim3(1), dim3(64), 0, hs, flag, A.ticket, A.n_units);
+    } else {
+        hipLaunchKernelGGL(render_zero_kernel, dim3(1), dim3(64), 0, hs, A.ticket, flag);
+    }
+    MS_LAUNCHED();
+    const int bpc = desc->blocks_per_cu ? desc->blocks_per_cu : 4;
+    int64_t blocks = (int64_t)cus * bpc;
+    const int64_t need_blocks = (A.n_units + 255) / 256;
+    if (blocks > need_blocks) blocks = need_blocks;
+    hipLaunchKernelGGL(render_kernel, dim3((unsigned)blocks), dim3(64 * kRenderWaves), 0, hs, A);
+    MS_LAUNCHED();
+    int64_t rb = (A.npix + 255) / 256;
+    if (rb > cus * 8) rb = cus * 8;
+    hipLaunchKernelGGL(render_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, hs, A.npix, A.n_chunks, A.part_sum,
+                       A.part_comp, A.part_sq, A.part_events, A.part_steps, out->sum, out->comp, out->sumsq,
+                       out->events, out->steps, flag);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+}  // extern "C"

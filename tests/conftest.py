@@ -17,3 +17,18 @@ def oracle():
     import oracle as O
     O.lib()
     return O
+
+
+@pytest.fixture(scope="session")
+def msst():
+    """The HIP library binding; a GPU test fails (never skips) without it."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_2011_03082_amd as M
+    M.lib()
+    return M
+
+
+def announce(msg):
+    """Names the GPU case about to run, flushed, so a crash log shows it."""
+    print(f"[gpu-case] {msg}", flush=True)

@@ -1,0 +1,80 @@
+"""C-ABI contract on the CPU: the library loads, exports every function that
+include/msst.h declares, and rejects invalid arguments before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msst.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:ms_status|int32_t|const char\*|size_t)\s+(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_2011_03082_amd as M
+    if not os.path.exists(M._abi.LIB_PATH):
+        from paper_2011_03082_amd import build
+        build.build()
+    M.lib()
+    return M
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ms_random_walk", "cvae_train_step", "cvae_sample", "sphere_trace_render"):
+        assert required in names
+    assert len(names) >= 19
+
+
+def test_library_exports_every_declared_symbol(M):
+    L = C.CDLL(M._abi.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_functions()) <= set(M._abi.SIGNATURES)
+
+
+def test_version_and_error_text(M):
+    assert M.lib().ms_abi_version() == 1
+
+
+def _walk_status(M, **kw):
+    d = M.walk_desc(**kw)
+    o = M._abi.WalkOut()
+    ws = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    return M.lib().ms_random_walk(C.byref(d), C.byref(o), ws, 256, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_photons=0), dict(n_photons=10, sigma_t=0.0), dict(n_photons=10, g=1.0),
+    dict(n_photons=10, g=-1.5), dict(n_photons=10, albedo=1.01), dict(n_photons=10, radius=-1.0),
+    dict(n_photons=10, mode=7), dict(n_photons=10, mode=1, st_range=(0.0, 1.0)),
+    dict(n_photons=10, mode=1, g_range=(0.5, 0.1)), dict(n_photons=10, mode=1, albedo_range=(0.9, 1.5)),
+    dict(n_photons=10, mode=1, event_weighting=5), dict(n_photons=1 << 41),
+])
+def test_walk_rejects_invalid(M, kw):
+    assert _walk_status(M, **kw) == M._abi.MS_ERR_INVALID_ARGUMENT
+    assert M.lib().ms_last_error().decode()
+
+
+def test_walk_rejects_missing_workspace(M):
+    d = M.walk_desc(10)
+    o = M._abi.WalkOut()
+    assert M.lib().ms_random_walk(C.byref(d), C.byref(o), None, 0, None) == M._abi.MS_ERR_INVALID_ARGUMENT
+    assert "workspace" in M.lib().ms_last_error().decode()
+    n = C.c_size_t()
+    assert M.lib().ms_random_walk_workspace_size(C.byref(d), C.byref(n)) == 0 and n.value >= 8
+
+
+def test_philox_fill_rejects_invalid(M):
+    L = M.lib()
+    assert L.ms_philox_fill(0, 0, 0, 0, 0, 1, C.c_void_p(0x1000), None) == M._abi.MS_ERR_INVALID_ARGUMENT
+    assert L.ms_philox_fill(0, 0, 0, 4, 0, 1, None, None) == M._abi.MS_ERR_INVALID_ARGUMENT
+    assert L.ms_philox_fill(0, 0, 0, 4, 0, 1, C.c_void_p(0x1004), None) == M._abi.MS_ERR_INVALID_ARGUMENT

@@ -1,0 +1,206 @@
+"""GPU CVAE kernels against the FP64 oracle (Sec. 3.2, Sec. 4.2): init,
+features, FP64 moments, gradients of the bfloat16 MFMA forward/backward,
+AdamW, packing and decoder-only sampling."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+BF16_U = 2.0**-8  # unit roundoff of bfloat16 (8 significant bits)
+MODELS = [0, 1, 2]
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda().contiguous()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_init_matches_oracle(msst, oracle, model):
+    announce(f"cvae init model={model}")
+    shape = W.SHAPE_LIST[model]
+    n = msst.cvae_param_count(model)
+    master = torch.empty(n, dtype=torch.float32, device="cuda")
+    msst.cvae_init(model, 77, master)
+    ref = oracle.cvae_init(shape, 77)
+    np.testing.assert_allclose(master.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+
+
+def test_features_and_moments(msst, oracle):
+    announce("cvae features + moments")
+    n = 20000
+    walk = msst.random_walk(n, seed=5, mode=1)
+    torch.cuda.synchronize()
+    w64 = {k: v.cpu().numpy().astype(np.float64) if v.dtype == torch.float32 else v.cpu().numpy()
+           for k, v in walk.items()}
+    w64["n_scatter"] = w64["n_scatter"].astype(np.uint32)
+    for model in MODELS:
+        p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
+        cond = torch.empty((n, p_in), dtype=torch.float32, device="cuda")
+        target = torch.empty((n, p_out), dtype=torch.float32, device="cuda")
+        wk = {k: walk[k] for k in ("params", "n_scatter", "exit_param", "event_pos", "event_dir")}
+        wk["n_scatter"] = walk["n_scatter"]
+        msst.cvae_features(model, n, wk, 9, 100, None, cond, target)
+        rc, rt = oracle.cvae_features(model, w64, seed=9, id_offset=100)
+        np.testing.assert_allclose(cond.cpu().numpy(), rc, rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(target.cpu().numpy(), rt, rtol=1e-5, atol=1e-6)
+        # FP64 column moments of the float32 rows, against numpy in float64
+        st = msst.make_stats(cond, target).cpu().numpy()
+        c64 = cond.cpu().numpy().astype(np.float64)
+        t64 = target.cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(st[:p_in], c64.mean(0), rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(st[16:16 + p_in], c64.std(0), rtol=1e-12)
+        np.testing.assert_allclose(st[32:32 + p_out], t64.mean(0), rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(st[48:48 + p_out], t64.std(0), rtol=1e-12)
+        # standardised rows
+        msst.cvae_features(model, n, wk, 9, 100, dev(st, torch.float64), cond, target)
+        np.testing.assert_allclose(cond.cpu().numpy(), (rc - st[:p_in]) / st[16:16 + p_in], rtol=1e-5, atol=1e-5)
+
+
+def grad_case(msst, oracle, model, B, sample_rows=0, n_rows=None):
+    shape = W.SHAPE_LIST[model]
+    master64 = oracle.cvae_init(shape, seed=31 + model).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(model)
+    n_rows = n_rows or B
+    cond = rng.normal(size=(n_rows, shape["p_in"])).astype(np.float32)
+    target = rng.normal(size=(n_rows, shape["p_out"])).astype(np.float32)
+    seed, step = 1234, 7
+    n = master64.size
+    master = dev(master64)
+    grad = torch.zeros(n, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    ws = torch.empty(msst.cvae_workspace_size(model, B), dtype=torch.uint8, device="cuda")
+    msst.cvae_train_step(model, master, None, None, None, dev(cond), dev(target), n_rows, B, sample_rows, seed, step,
+                         0, ws, loss, grad)
+    torch.cuda.synchronize()
+    if sample_rows:
+        words = np.array([oracle.philox_blocks(seed, oracle.TAG_CVAE_BATCH, b, step, 1)[0, 0] for b in range(B)],
+                         dtype=np.uint64)
+        rows = ((words * np.uint64(n_rows)) >> np.uint64(32)).astype(np.int64)
+    else:
+        rows = np.arange(B)
+    l64, kl64, nll64, g64 = oracle.cvae_loss_grad(shape, master64, cond[rows].astype(np.float64),
+                                                  target[rows].astype(np.float64), seed, step)
+    return grad.cpu().numpy().astype(np.float64), g64, loss.cpu().numpy(), (l64, kl64, nll64)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_gradient_parity_bf16(msst, oracle, model):
+    """Gradients of the bfloat16 MFMA forward/backward against FP64 (tolerance
+    ~10 bfloat16 roundoffs relative in L2; direction to cosine 0.999)."""
+    announce(f"cvae grad parity model={model}")
+    g, g64, loss, ref = grad_case(msst, oracle, model, B=256)
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    cos = g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64))
+    print(f"model {model}: grad rel-L2 {rel:.3e}, cosine {cos:.6f}, loss {loss} vs {ref}")
+    assert rel < 10 * BF16_U and cos > 0.999
+    np.testing.assert_allclose(loss, ref, rtol=10 * BF16_U, atol=1e-3)
+    assert abs(loss[0] - loss[1] - loss[2]) < 1e-9 * abs(loss[0])
+
+
+def test_gradient_parity_sampled_rows_and_ragged(msst, oracle):
+    announce("cvae grad sampled rows")
+    g, g64, loss, ref = grad_case(msst, oracle, 2, B=16 * 37, sample_rows=1, n_rows=5000)
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    assert rel < 10 * BF16_U
+    np.testing.assert_allclose(loss, ref, rtol=10 * BF16_U, atol=1e-3)
+
+
+def test_adamw_step_matches_oracle(msst, oracle):
+    announce("cvae adamw")
+    model, B = 1, 128
+    shape = W.SHAPE_LIST[model]
+    master64 = oracle.cvae_init(shape, seed=3).astype(np.float32).astype(np.float64)
+    n = master64.size
+    rng = np.random.default_rng(4)
+    m0 = (rng.normal(size=n) * 1e-3).astype(np.float32).astype(np.float64)
+    v0 = (rng.uniform(size=n) * 1e-6).astype(np.float32).astype(np.float64)
+    cond = rng.normal(size=(B, shape["p_in"])).astype(np.float32)
+    target = rng.normal(size=(B, shape["p_out"])).astype(np.float32)
+    master, m, v = dev(master64), dev(m0), dev(v0)
+    grad = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ws = torch.empty(msst.cvae_workspace_size(model, B), dtype=torch.uint8, device="cuda")
+    adam = msst.adam_params(step=5, lr=1e-3, weight_decay=0.01)
+    msst.cvae_train_step(model, master, m, v, adam, dev(cond), dev(target), B, B, 0, 1, 1, 0, ws, None, grad)
+    torch.cuda.synchronize()
+    p, mm, vv = master64.copy(), m0.copy(), v0.copy()
+    oracle.adamw_step(p, mm, vv, grad.cpu().numpy().astype(np.float64), 5, lr=1e-3, weight_decay=0.01)
+    np.testing.assert_allclose(master.cpu().numpy(), p, rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(m.cpu().numpy(), mm, rtol=1e-5, atol=1e-10)
+    np.testing.assert_allclose(v.cpu().numpy(), vv, rtol=1e-5, atol=1e-14)
+
+
+def test_training_reduces_loss_and_keeps_padding_zero(msst, oracle):
+    announce("cvae training loop")
+    model, B = 0, 1024
+    n_rows = 1 << 15
+    rng = np.random.default_rng(2)
+    cond = rng.normal(size=(n_rows, 2)).astype(np.float32)
+    target = (0.8 * cond[:, :1] - 0.3 * cond[:, 1:] ** 2 + 0.1 * rng.normal(size=(n_rows, 1))).astype(np.float32)
+    cd, td = dev(cond), dev(target)
+    n = msst.cvae_param_count(model)
+    master = torch.empty(n, dtype=torch.float32, device="cuda")
+    msst.cvae_init(model, 5, master)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    ws = torch.empty(msst.cvae_workspace_size(model, B), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    hist = []
+    for step in range(1, 401):
+        msst.cvae_train_step(model, master, m, v, msst.adam_params(step, lr=3e-3), cd, td, n_rows, B, 1, 11, step, 0,
+                             ws, loss)
+        if step in (1, 400):
+            hist.append(loss.cpu().numpy().copy())
+    assert hist[1][0] < hist[0][0] - 0.5, hist
+    mp = master.cpu().numpy()
+    pad = ~_real_mask(W.SHAPE_LIST[model])
+    assert np.all(mp[pad] == 0)
+
+
+def _real_mask(shape):
+    nl = shape["n_linear"]
+    mask = np.zeros((2 * nl, 272), bool)
+    for net in range(2):
+        in0 = shape["latent"] + shape["p_in"] if net else shape["p_out"] + shape["p_in"]
+        outl = 2 * shape["p_out"] if net else 2 * shape["latent"]
+        for j in range(nl):
+            n_in = in0 if j == 0 else shape["width"]
+            n_out = outl if j == nl - 1 else shape["width"]
+            Wm = np.zeros((16, 16), bool)
+            Wm[:n_out, :n_in] = True
+            b = np.zeros(16, bool)
+            b[:n_out] = True
+            mask[net * nl + j] = np.concatenate([Wm.ravel(), b])
+    return mask.ravel()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_sample_matches_bf16_emulating_oracle(msst, oracle, model):
+    """Decoder sampling on MFMA against the oracle that rounds weights and layer
+    inputs to bfloat16 exactly where the kernel does.  Remaining differences
+    come from FP32 vs FP64 accumulation and transcendentals, except where such
+    a difference flips a bfloat16 rounding (one bfloat16 ulp on one unit)."""
+    announce(f"cvae sample model={model}")
+    shape = W.SHAPE_LIST[model]
+    master64 = oracle.cvae_init(shape, seed=50 + model).astype(np.float32).astype(np.float64)
+    stats = W.random_stats(model, seed=model)
+    n = 4000 + 37  # ragged last wave and tile
+    cond = W.random_conditions(model, n, seed=model).astype(np.float32)
+    packed = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+    msst.cvae_pack(model, dev(master64), dev(stats, torch.float64), 1, packed)
+    out = torch.empty((n, shape["p_out"]), dtype=torch.float32, device="cuda")
+    msst.cvae_sample(packed, dev(cond), n, 99, 1000, out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 99, 1000, precision=oracle.PREC_BF16)
+    scale = stats[48:48 + shape["p_out"]]
+    err = np.abs(got - ref).max(axis=1) / scale.max()
+    print(f"model {model}: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}, max {err.max():.2e}")
+    assert np.quantile(err, 0.99) < 1e-4
+    assert err.max() < 0.05
+    ref64 = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 99, 1000)
+    err64 = np.abs(got - ref64).max(axis=1) / scale.max()
+    print(f"model {model}: error against the FP64 decoder median {np.median(err64):.2e}, max {err64.max():.2e}")
+    assert np.median(err64) < 0.05

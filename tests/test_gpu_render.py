@@ -1,0 +1,228 @@
+"""GPU renderer against the FP64 oracle on the same Philox streams (Sec. 3,
+Sec. 4.1, Sec. 4.3): plain path tracing with next-event estimation, sphere
+tracing with exact in-sphere walks, and sphere tracing with the learned
+decoders (oracle rounding weights and layer inputs to bfloat16 like the
+kernel)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+PLAIN, ST = 1, 2
+CVAE, EXACT = 0, 1
+
+
+def f32(v):
+    return tuple(float(np.float32(x)) for x in v)
+
+
+def f32_camera(cam):
+    c = dict(cam)
+    for k in ("eye", "look_at", "up"):
+        c[k] = f32(cam[k])
+    c["vfov_deg"] = float(np.float32(cam["vfov_deg"]))
+    return c
+
+
+def f32_light(light):
+    return dict(pos=f32(light["pos"]), intensity=float(np.float32(light["intensity"])))
+
+
+def f32_medium(med):
+    return {k: float(np.float32(v)) for k, v in med.items()}
+
+
+def gpu_render(msst, prims, cam, light, med, **kw):
+    r = msst.Renderer(prims, cam, light)
+    out = r.render(med, **kw)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def models_for_test(oracle):
+    models, packed_src = [], []
+    for m in range(3):
+        shape = W.SHAPE_LIST[m]
+        master = oracle.cvae_init(shape, seed=500 + m).astype(np.float32).astype(np.float64)
+        stats = W.render_test_stats(m)
+        models.append(dict(shape=shape, params=master, stats=stats))
+        packed_src.append((master, stats))
+    return models, packed_src
+
+
+def pack_all(msst, packed_src):
+    out = []
+    for m, (master, stats) in enumerate(packed_src):
+        p = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+        msst.cvae_pack(m, torch.as_tensor(master, dtype=torch.float32).cuda(),
+                       torch.as_tensor(stats, dtype=torch.float64).cuda(), 1, p)
+        out.append(p)
+    return out
+
+
+def compare_paths(g, o, rel=1e-3):
+    """Per pixel (spp = 1: per path) agreement; returns the diverged fraction."""
+    gs, os_ = g["sum"].astype(np.float64) + g["comp"], o["sum"]
+    tol = rel * np.abs(os_) + 1e-7 * max(1e-30, np.abs(os_).max())
+    bad = np.abs(gs - os_) > tol
+    bad |= g["events"].astype(np.int64) != o["events"].astype(np.int64)
+    bad |= g["steps"].astype(np.int64) != o["steps"].astype(np.int64)
+    return bad.mean(), bad
+
+
+def c4_inputs(sigma_t, w, h=None):
+    h = h or w
+    return (W.scene_c4(), f32_camera(W.camera_c4(w, h)), f32_light(W.light_c4()), f32_medium(W.medium_c4(sigma_t)))
+
+
+@pytest.mark.parametrize("sigma_t", [10.0, 40.0])
+def test_plain_nee_path_by_path(msst, oracle, sigma_t):
+    announce(f"render PLAIN_NEE parity sigma_t={sigma_t}")
+    prims, cam, light, med = c4_inputs(sigma_t, 48)
+    g = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=1, seed=3)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=1, seed=3)
+    frac, bad = compare_paths(g, o)
+    print(f"diverged {frac:.2e}; lit pixels {(o['sum'] > 0).mean():.2f}")
+    assert frac < 2e-3
+    assert (o["sum"] > 0).mean() > 0.2
+
+
+def test_exact_walk_sphere_tracing_path_by_path(msst, oracle):
+    announce("render ST exact-walk parity")
+    prims, cam, light, med = c4_inputs(20.0, 40)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=EXACT, spp=1, seed=4)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST,
+                      sampler=oracle.SAMPLER_EXACT_WALK, spp=1, seed=4)
+    frac, _ = compare_paths(g, o)
+    print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}")
+    assert frac < 5e-3
+    assert o["steps"].sum() > 100
+
+
+def test_learned_sphere_tracing_path_by_path(msst, oracle):
+    announce("render ST CVAE parity")
+    prims, cam, light, med = c4_inputs(20.0, 40)
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=5)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      precision=oracle.PREC_BF16, models=models, spp=1, seed=5)
+    frac, _ = compare_paths(g, o, rel=2e-3)
+    print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
+    assert o["steps"].sum() > 100
+    assert frac < 0.03
+
+
+def test_tau_above_all_radii_is_plain(msst):
+    announce("render ST with tau_min huge")
+    prims, cam, light, med = c4_inputs(10.0, 32)
+    a = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=3, seed=6)
+    b = gpu_render(msst, prims, cam, light, med, method=ST, sampler=EXACT, tau_min=1e30, spp=3, seed=6)
+    np.testing.assert_array_equal(a["sum"], b["sum"])
+    assert b["steps"].sum() == 0
+
+
+def test_exact_walk_regroups_plain_tracing(msst):
+    """Same expectation of the two estimators (z-test on the image mean)."""
+    announce("render exact-walk regrouping z-test")
+    prims, cam, light, med = c4_inputs(40.0, 64)
+    spp = 256
+    a = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=spp, seed=7)
+    b = gpu_render(msst, prims, cam, light, med, method=ST, sampler=EXACT, spp=spp, seed=8)
+    n = spp * a["sum"].size
+
+    def ms(o):
+        m = (o["sum"].astype(np.float64) + o["comp"]).sum() / n
+        v = o["sumsq"].astype(np.float64).sum() / n - m * m
+        return m, np.sqrt(v / n)
+
+    (ma, sa), (mb, sb) = ms(a), ms(b)
+    print(f"plain {ma:.6e} +- {sa:.1e}, exact-walk ST {mb:.6e} +- {sb:.1e}")
+    assert abs(ma - mb) < 5 * np.hypot(sa, sb)
+    assert b["steps"].sum() > 0 and b["events"].sum() < a["events"].sum()
+
+
+def test_deterministic_and_resumable(msst):
+    announce("render determinism + resume")
+    prims, cam, light, med = c4_inputs(20.0, 24)
+    r = msst.Renderer(prims, cam, light)
+    one = r.render(med, method=PLAIN, spp=8, chunk=4, seed=9)
+    two = r.render(med, method=PLAIN, spp=8, chunk=4, seed=9)
+    torch.cuda.synchronize()
+    for k in ("sum", "comp", "sumsq", "events"):
+        assert torch.equal(one[k], two[k])
+    part = r.render(med, method=PLAIN, spp=4, chunk=4, seed=9)
+    r.render(med, method=PLAIN, spp=4, chunk=4, seed=9, sample_offset=4, out=part)
+    torch.cuda.synchronize()
+    tot1 = one["sum"].double() + one["comp"].double()
+    tot2 = part["sum"].double() + part["comp"].double()
+    assert torch.allclose(tot1, tot2, rtol=1e-6, atol=1e-12)
+    assert torch.equal(one["events"], part["events"])
+    assert one["counters"][0].item() == 8 * 24 * 24
+
+
+@pytest.mark.parametrize("w,h,spp,chunk", [(1, 1, 3, 0), (7, 5, 5, 2), (33, 17, 2, 1)])
+def test_ragged_images(msst, oracle, w, h, spp, chunk):
+    announce(f"render ragged {w}x{h} spp={spp}")
+    prims, cam, light, med = c4_inputs(10.0, w, h)
+    cam["look_at"] = f32((1.0, 0.0, 0.0))
+    g = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=spp, chunk=chunk, seed=10)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=spp, seed=10)
+    gs = g["sum"].astype(np.float64) + g["comp"]
+    assert np.mean(np.abs(gs - o["sum"]) > 1e-3 * np.abs(o["sum"]) + 1e-9) < 0.05
+    assert np.all(g["events"] == o["events"]) or np.mean(g["events"] != o["events"]) < 0.05
+
+
+def test_degenerate_media(msst, oracle):
+    announce("render degenerate media")
+    prims, cam, light, _ = c4_inputs(10.0, 24)
+    thin = dict(sigma_t=float(np.float32(1e-3)), g=0.0, albedo=1.0)
+    g = gpu_render(msst, prims, cam, light, thin, method=PLAIN, spp=2, seed=11)
+    o = oracle.render(oracle.Scene(prims), cam, light, thin, method=oracle.METHOD_PLAIN_NEE, spp=2, seed=11)
+    np.testing.assert_array_equal(g["events"], o["events"])
+    assert g["events"].sum() < 10
+    dense = f32_medium(dict(sigma_t=300.0, g=-0.5, albedo=0.9))
+    g = gpu_render(msst, prims, cam, light, dense, method=PLAIN, spp=1, seed=12)
+    o = oracle.render(oracle.Scene(prims), cam, light, dense, method=oracle.METHOD_PLAIN_NEE, spp=1, seed=12)
+    frac, _ = compare_paths(g, o)
+    assert frac < 5e-3
+
+
+def test_full_size_c4_sampled_pixels(msst, oracle):
+    """512 x 512 in the benchmark's launch shape; 300 sampled pixels against
+    the oracle path by path."""
+    announce("render C4 512^2 sampled parity")
+    prims, cam, light, med = c4_inputs(40.0, 512)
+    g = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=1, seed=13)
+    rng = np.random.default_rng(0)
+    lit = np.flatnonzero(g["events"] > 0)
+    pix = np.sort(rng.choice(lit, 300, replace=False)).astype(np.int32)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=1, seed=13,
+                      pixels=pix)
+    gs = g["sum"][pix].astype(np.float64) + g["comp"][pix]
+    bad = (np.abs(gs - o["sum"]) > 1e-3 * np.abs(o["sum"]) + 1e-9) | (g["events"][pix] != o["events"])
+    assert bad.mean() < 0.01
+
+
+def test_image_stats_fp64(msst):
+    announce("image stats")
+    rng = np.random.default_rng(3)
+    n, spp = 10007, 16
+    s = rng.uniform(0, 1, n).astype(np.float32)
+    c = (rng.normal(size=n) * 1e-8).astype(np.float32)
+    q = (s.astype(np.float64) ** 2 / spp + rng.uniform(0, 0.1, n)).astype(np.float32)
+    ref = rng.uniform(0, 0.1, n).astype(np.float32)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ws = torch.empty(msst.ms_image_stats_workspace_size(n), dtype=torch.uint8, device="cuda")
+    T = lambda a: torch.as_tensor(a).cuda()
+    msst.ms_image_stats(T(s), T(c), T(q), T(ref), n, spp, out, ws)
+    got = out.cpu().numpy()
+    m = (s.astype(np.float64) + c) / spp
+    np.testing.assert_allclose(got[0], m.mean(), rtol=1e-12)
+    np.testing.assert_allclose(got[1], np.sqrt(np.mean((m - ref) ** 2)), rtol=1e-12)
+    np.testing.assert_allclose(got[2], np.mean(q.astype(np.float64) / spp - m * m), rtol=1e-10)
+    np.testing.assert_allclose(got[3], ref.astype(np.float64).mean(), rtol=1e-12)

@@ -1,0 +1,147 @@
+"""GPU random walk vs the FP64 oracle on the same Philox streams (Sec. 3.1)."""
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+import workloads as W
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4       # relative error of exit position / direction per matched path
+DIVERGE_TOL = 1e-4   # fraction of paths whose event count or absorption differs
+
+
+def to_np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def rel_err(a, b):
+    return np.linalg.norm(a - b, axis=0) / np.maximum(np.linalg.norm(b, axis=0), 1e-12)
+
+
+def test_philox_block_for_block(msst, oracle):
+    announce("philox fill")
+    out = torch.empty((300, 7, 4), dtype=torch.int32, device="cuda")
+    seed, tag, id0 = 0xDEADBEEF12345678, 7, (3 << 32) + 4000000000
+    msst.ms_philox_fill(seed, tag, id0, 300, 2**32 - 3, 7, out)
+    got = out.cpu().numpy().view(np.uint32)
+    for i in range(0, 300, 7):
+        ref = np.stack([oracle.philox_blocks(seed, tag, id0 + i, (2**32 - 3 + j) % 2**32, 1)[0] for j in range(7)])
+        np.testing.assert_array_equal(got[i], ref)
+
+
+def analog_parity(msst, oracle, n, offset=0, **kw):
+    g = to_np(msst.random_walk(n, photon_offset=offset, **kw))
+    torch.cuda.synchronize()
+    o = oracle.random_walk(n, photon_offset=offset, **kw)
+    same = (g["n_scatter"].astype(np.int64) == o["n_scatter"]) & (g["absorbed"] == o["absorbed"])
+    return g, o, same
+
+
+def test_c1_path_by_path(msst, oracle):
+    """C1: 1e5 photons, sigma_t = 10, albedo 0.99, g = 0.8, seed 0."""
+    announce("walk C1 analog 1e5")
+    kw = {k: W.WALK_C1[k] for k in ("seed", "sigma_t", "g", "albedo", "radius")}
+    g, o, same = analog_parity(msst, oracle, W.WALK_C1["n_photons"], **kw)
+    assert 1 - same.mean() < DIVERGE_TOL, (1 - same.mean())
+    assert rel_err(g["exit_pos"][:, same], o["exit_pos"][:, same]).max() <= REL_TOL
+    assert rel_err(g["exit_dir"][:, same], o["exit_dir"][:, same]).max() <= REL_TOL
+    assert rel_err(g["exit_param"][:, same], o["exit_param"][:, same]).max() <= 10 * REL_TOL
+    np.testing.assert_allclose(g["params"][:, 0], [10.0, 0.8, 0.99], rtol=1e-7)
+    assert g["counters"][0] == g["n_scatter"].astype(np.int64).sum()
+    assert g["counters"][1] == g["absorbed"].sum()
+    assert g["counters"][3] == g["n_scatter"].max()
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 1000])
+def test_ragged_sizes(msst, oracle, n):
+    announce(f"walk ragged n={n}")
+    g, o, same = analog_parity(msst, oracle, n, offset=12345, seed=3, sigma_t=5.0, g=-0.3, albedo=0.9, radius=2.0)
+    assert same.all()
+    assert rel_err(g["exit_pos"], o["exit_pos"]).max() <= REL_TOL
+
+
+def test_degenerate_cases(msst, oracle):
+    announce("walk degenerate")
+    g = to_np(msst.random_walk(5000, seed=1, sigma_t=3.0, g=0.5, albedo=0.0))
+    assert np.all(g["absorbed"] == 1) and np.all(g["n_scatter"] == 1)
+    np.testing.assert_array_equal(g["exit_pos"], 0.0)
+    g = to_np(msst.random_walk(5000, seed=1, sigma_t=50.0, g=0.0, albedo=1.0, max_events=1))
+    o = oracle.random_walk(5000, seed=1, sigma_t=50.0, g=0.0, albedo=1.0, max_events=1)
+    np.testing.assert_array_equal(g["truncated"], o["truncated"])
+    assert np.all(g["n_scatter"] == 1)
+    g = to_np(msst.random_walk(20000, seed=2, sigma_t=10.0, g=0.8, albedo=1.0))
+    assert g["absorbed"].sum() == 0
+    np.testing.assert_allclose(np.linalg.norm(g["exit_pos"], axis=0), 1.0, atol=1e-5)
+
+
+def test_split_launch_is_bitwise_identical(msst):
+    announce("walk split launch")
+    kw = dict(seed=9, mode=1)
+    full = to_np(msst.random_walk(40000, **kw))
+    a = to_np(msst.random_walk(15000, **kw))
+    b = to_np(msst.random_walk(25000, photon_offset=15000, **kw))
+    for k in ("n_scatter", "exit_pos", "exit_param", "event_pos", "event_dir", "event_index", "params"):
+        np.testing.assert_array_equal(full[k][..., :15000], a[k])
+        np.testing.assert_array_equal(full[k][..., 15000:], b[k])
+
+
+def training_parity(msst, oracle, n, offset=0, **kw):
+    g = to_np(msst.random_walk(n, photon_offset=offset, mode=1, **kw))
+    o = oracle.random_walk(n, photon_offset=offset, mode=1, **kw)
+    return g, o
+
+
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_training_path_by_path(msst, oracle, weighting):
+    announce(f"walk training 2^16 weighting={weighting}")
+    n = 1 << 16
+    g, o = training_parity(msst, oracle, n, seed=0, event_weighting=weighting)
+    np.testing.assert_allclose(g["params"][0], o["params"][0], rtol=2e-6)
+    np.testing.assert_allclose(g["params"][1:], o["params"][1:], rtol=0, atol=1e-6)
+    st = o["params"][0]
+    same = (g["n_scatter"].astype(np.int64) == o["n_scatter"]) & (g["event_index"].astype(np.int64) == o["event_index"])
+    low = st < 20.0
+    div_low = 1 - same[low].mean()
+    assert div_low < 1e-3, div_low
+    ok = same & low
+    for k in ("exit_pos", "exit_dir", "event_dir"):
+        assert np.quantile(rel_err(g[k][:, ok], o[k][:, ok]), 0.999) <= REL_TOL, k
+    assert np.quantile(np.abs(g["event_pos"][:, ok] - o["event_pos"][:, ok]).max(axis=0), 0.999) <= REL_TOL
+    for lo, hi in [(0.1, 1), (1, 10), (10, 50), (50, 200)]:
+        sel = (st >= lo) & (st < hi)
+        print(f"sigma_t r in [{lo}, {hi}): diverged {1 - same[sel].mean():.2e} of {sel.sum()}")
+
+
+def test_training_full_size_sampled_and_ks(msst, oracle):
+    """C2 at full size (2^24 photons) in the benchmark's launch shape: sampled
+    photons against the oracle one by one, exit distributions by KS."""
+    announce("walk training 2^24")
+    n = W.WALK_C2["n_photons"]
+    out = msst.random_walk(n, seed=0, mode=1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    ids = np.sort(rng.choice(n, 300, replace=False))
+    st = out["params"][0].cpu().numpy()
+    nsc = out["n_scatter"].cpu().numpy()
+    ep = out["exit_param"].cpu().numpy()
+    matched = 0
+    for i in ids:
+        o = oracle.random_walk(1, photon_offset=int(i), seed=0, mode=1)
+        assert abs(st[i] - o["params"][0, 0]) <= 2e-6 * o["params"][0, 0]
+        if nsc[i] == o["n_scatter"][0]:
+            matched += 1
+            assert np.abs(ep[:, i] - o["exit_param"][:, 0]).max() < 1e-3
+    assert matched >= 0.9 * len(ids)
+    m = 1 << 20
+    o = oracle.random_walk(m, seed=777, mode=1)
+    sub = rng.choice(n, m, replace=False)
+    for k in range(3):
+        D = stats.ks_2samp(ep[k, sub], o["exit_param"][k]).statistic
+        assert D < 0.01, (k, D)
+    D = stats.ks_2samp(np.log(nsc[sub]), np.log(o["n_scatter"])).statistic
+    assert D < 0.01
+    c = out["counters"].cpu().numpy()
+    assert c[0] == nsc.astype(np.int64).sum() and c[2] == out["truncated"].sum().item()

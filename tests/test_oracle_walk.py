@@ -44,9 +44,16 @@ def test_hg_stable_form_identity():
     a = 2 * xi - 1
     s = (1 - g**2) / (1 - g + 2 * g * xi)
     textbook = (1 + g**2 - s**2) / (2 * g)
-    stable = (a + g / 2 * (a**2 + 3) + g**2 * a + g**3 / 2 * (a**2 - 1)) / (1 + g * a) ** 2
+    stable = (a + g) / (1 + g * a) + g * (1 - a**2) * (1 - g**2) / (2 * (1 + g * a) ** 2)
     assert sp.simplify(textbook - stable) == 0
     assert sp.simplify(stable.subs(g, 0) - a) == 0  # isotropic limit without a branch
+    assert sp.simplify(stable.subs(xi, 0) + 1) == 0 and sp.simplify(stable.subs(xi, 1) - 1) == 0
+    # the GPU evaluates mu and sin(theta) through 1 - mu and 1 + mu in these forms
+    q = 1 + g * a
+    one_minus = 2 * (1 - g) ** 2 * (1 - xi) * (1 + g * xi) / q**2
+    one_plus = 2 * (1 + g) ** 2 * xi * (1 - g + g * xi) / q**2
+    assert sp.simplify(1 - textbook - one_minus) == 0
+    assert sp.simplify(1 + textbook - one_plus) == 0
 
 
 def test_onb_orthonormal_right_handed(oracle):

@@ -116,3 +116,27 @@ def random_stats(model, seed):
     st[32:32 + p_out] = rng.normal(0, 0.5, p_out)
     st[48:48 + p_out] = rng.uniform(0.3, 1.5, p_out)
     return st
+
+
+def render_test_stats(model):
+    """Standardisation constants that make untrained (random) decoders emit
+    plausible outputs for render parity tests: N around 20, cos(theta) around
+    0.3, representative events inside the unit ball."""
+    st = np.zeros(64)
+    st[16:32] = 1.0
+    st[48:64] = 1.0
+    if model == 0:
+        st[0:2] = [2.0, 0.4]
+        st[16:18] = [1.5, 0.5]
+        st[32], st[48] = np.log(20.0), 0.5
+    elif model == 1:
+        st[0:3] = [2.0, 0.4, 3.0]
+        st[16:19] = [1.5, 0.5, 1.0]
+        st[32:35] = [0.3, 0.0, 0.0]
+        st[48:51] = [0.4, 0.3, 0.3]
+    else:
+        st[0:7] = [2.0, 0.4, 0.95, 0.3, 0.0, 0.0, 3.0]
+        st[16:23] = [1.5, 0.5, 0.03, 0.5, 0.3, 0.3, 1.0]
+        st[32:38] = [0.0, 0.0, 0.3, 0.0, 0.0, 0.5]
+        st[48:54] = [0.25, 0.25, 0.25, 0.4, 0.4, 0.4]
+    return st
