@@ -1,0 +1,286 @@
+"""Benchmark: sphere-traced camera paths/s with the learned CVAE step against
+plain random-walk (path tracing with next-event estimation) paths/s at
+matched image RMSE, on the synthetic sphere + box scene (512 x 512,
+256 samples per pixel, g = 0.8, albedo 0.995, sigma_t in {10, 20, 40, 80},
+one point light).
+
+One step = one sphere-traced render of the whole sweep (four images).  Before
+the timed region the script generates CVAE training data with the GPU random
+walk, trains the three CVAEs with the GPU forward/backward/AdamW kernels,
+packs them to bfloat16, renders a high-sample plain reference per density and
+times the plain tracer; after it, it reports the matched-RMSE speed-up,
+roofline figures of the render kernel and the CPU oracle's rate.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU work of the algorithm per unit, in 32-bit lane-operation slots
+# (quarter-rate instructions -- transcendentals, 32-bit integer multiplies --
+# count 4 slots).  Derivation in DESIGN.md ("Roofline").
+OPS_PER_PATH = 180.0         # camera ray, primary intervals, path bookkeeping
+OPS_PER_EVENT = 440.0        # one plain collision: Philox block, flight, NEE, roulette, HG, new ray
+OPS_PER_STEP = 2600.0        # one learned sphere step on VALU (the MFMA part is separate)
+MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
+PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
+PEAK_MFMA_BF16 = 2.5e15
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--train-steps", type=int, default=20000)
+    ap.add_argument("--train-samples", type=int, default=1 << 22)
+    ap.add_argument("--ref-spp", type=int, default=4096)
+    ap.add_argument("--width", type=int, default=512)
+    ap.add_argument("--spp", type=int, default=256)
+    ap.add_argument("--tau-min", type=float, default=2.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--batch-min", type=int, default=0)
+    ap.add_argument("--diagnostics", action="store_true",
+                    help="also render sphere tracing with exact in-sphere walks and a tau_min sweep (untimed)")
+    return ap.parse_args()
+
+
+def train_models(M, torch, n_samples, steps, batch=4096, seed=0):
+    """GPU walk -> features -> FP64 standardisation -> AdamW training -> BF16 pack."""
+    t0 = time.time()
+    walk = M.random_walk(n_samples, seed=seed, mode=1)
+    packed, losses = [], []
+    for model in range(3):
+        p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
+        cond = torch.empty((n_samples, p_in), dtype=torch.float32, device="cuda")
+        target = torch.empty((n_samples, p_out), dtype=torch.float32, device="cuda")
+        M.cvae_features(model, n_samples, walk, seed + 1, 0, None, cond, target)
+        stats = M.make_stats(cond, target)
+        M.cvae_features(model, n_samples, walk, seed + 1, 0, stats, cond, target)
+        n = M.cvae_param_count(model)
+        master = torch.empty(n, dtype=torch.float32, device="cuda")
+        M.cvae_init(model, seed + 10 + model, master)
+        m, v = torch.zeros_like(master), torch.zeros_like(master)
+        ws = torch.empty(M.cvae_workspace_size(model, batch), dtype=torch.uint8, device="cuda")
+        loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+        first = None
+        for step in range(1, steps + 1):
+            lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
+            M.cvae_train_step(model, master, m, v, M.adam_params(step, lr=lr), cond, target, n_samples, batch, 1,
+                              seed + 20 + model, step, 0, ws, loss)
+            if step == 1:
+                first = loss.cpu().numpy().copy()
+        last = loss.cpu().numpy().copy()
+        pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+        M.cvae_pack(model, master, stats, 1, pk)
+        packed.append(pk)
+        losses.append((float(first[0]), float(last[0])))
+        log(f"model {model}: loss {first[0]:.4f} -> {last[0]:.4f}")
+    torch.cuda.synchronize()
+    return packed, losses, time.time() - t0
+
+
+def image_moments(img, spp):
+    s = img["sum"].double() + img["comp"].double()
+    mean = s / spp
+    var = img["sumsq"].double() / spp - mean * mean
+    return mean, var.clamp_min(0)
+
+
+def cpu_baseline(oracle, W, seconds):
+    """Oracle sphere tracer with the CVAE step (FP64) on a pixel subset of the
+    sigma_t = 40 image, on all host cores."""
+    import numpy as np
+    cores = os.cpu_count() or 1
+    prims = W.scene_c4()
+    cam = W.camera_c4(512, 512)
+    light = W.light_c4()
+    med = W.medium_c4(40.0)
+    models = []
+    for m in range(3):
+        shape = W.SHAPE_LIST[m]
+        models.append(dict(shape=shape, params=oracle.cvae_init(shape, 900 + m), stats=W.render_test_stats(m)))
+    rng = np.random.default_rng(0)
+    npx, spp = 256, 4
+    total_paths, t_total = 0, 0.0
+    while t_total < seconds and npx <= 1 << 18:
+        pix = rng.choice(512 * 512, npx, replace=False).astype(np.int32)
+        t0 = time.time()
+        oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      models=models, spp=spp, pixels=pix, n_threads=cores)
+        dt = time.time() - t0
+        total_paths += npx * spp
+        t_total += dt
+        npx *= 2
+    return {"value": total_paths / t_total, "unit": "paths/s", "cores": cores, "kind": "oracle",
+            "sample": f"{total_paths} paths (random pixel subsets x {spp} spp) of the sigma_t = 40 image, "
+                      f"ST + CVAE decoders in FP64 with oracle-initialised weights, {t_total:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "
+              "design (id-range sharding), not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2011_03082_amd as M
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    M.lib()
+    width, spp = args.width, args.spp
+    sigmas = W.C4_SIGMAS
+    rend = M.Renderer(W.scene_c4(), W.camera_c4(width, width), W.light_c4())
+    npix = width * width
+    stream = torch.cuda.current_stream()
+    kw = dict(blocks_per_cu=args.blocks_per_cu, cvae_batch_min=args.batch_min)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / 1e3
+
+    def rmse(img, s):
+        mean, _ = image_moments(img, spp)
+        return float(torch.sqrt(((mean.float() - ref[s]) ** 2).mean()))
+
+    log("training CVAEs on GPU random-walk data")
+    packed, losses, t_train = train_models(M, torch, args.train_samples, args.train_steps)
+
+    # plain reference (debiased by its own noise) and plain timing per density
+    ref, ref_noise2, pt = {}, {}, {}
+    for s in sigmas:
+        med = W.medium_c4(s)
+        img = rend.render(med, method=1, spp=args.ref_spp, seed=1000, **kw)
+        mean, var = image_moments(img, args.ref_spp)
+        ref[s] = mean.float()
+        ref_noise2[s] = float(var.mean()) / args.ref_spp
+        img, t = timed(lambda: rend.render(med, method=1, spp=spp, seed=2000, **kw))
+        _, var = image_moments(img, spp)
+        c = img["counters"].cpu().numpy()
+        pt[s] = dict(time=t, paths=int(c[0]), events=int(c[1]), var=float(var.mean()), rmse=rmse(img, s))
+        log(f"PT sigma_t={s}: {t * 1e3:.1f} ms, {c[0] / t:.3e} paths/s, events/path {c[1] / c[0]:.2f}")
+
+    def st_render(s, seed, **extra):
+        opts = dict(method=2, sampler=0, packed=packed, spp=spp, seed=seed, tau_min=args.tau_min)
+        opts.update(kw)
+        opts.update(extra)
+        return rend.render(W.medium_c4(s), **opts)
+
+    for w in range(args.warmup):
+        for s in sigmas:
+            st_render(s, 3000 + w)
+    torch.cuda.synchronize()
+    mk = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    ev = [[mk() for _ in sigmas] for _ in range(args.steps)]
+    t_start = time.time()
+    last = {}
+    for k in range(args.steps):
+        for i, s in enumerate(sigmas):
+            ev[k][i][0].record(stream)
+            last[s] = st_render(s, 4000 + k)
+            ev[k][i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - t_start
+    t_sigma = {s: float(np.mean([ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)])) / 1e3
+               for i, s in enumerate(sigmas)}
+    ms_per_step = sum(t_sigma.values()) * 1e3
+    paths_per_step = npix * spp * len(sigmas)
+    value = paths_per_step / (ms_per_step / 1e3)
+
+    # matched RMSE: the plain tracer needs S* = mean per-pixel variance /
+    # RMSE_ST^2 samples per pixel (RMSE_ST with the reference's own noise
+    # removed) to reach the sphere tracer's error, at its measured rate
+    details, counters = {}, np.zeros(4)
+    tot_st, tot_pt = 0.0, 0.0
+    for s in sigmas:
+        img = last[s]
+        c = img["counters"].cpu().numpy()
+        counters += c
+        r_raw = rmse(img, s)
+        r_st = float(np.sqrt(max(r_raw**2 - ref_noise2[s], 1e-30)))
+        r_pt = float(np.sqrt(max(pt[s]["rmse"] ** 2 - ref_noise2[s], 1e-30)))
+        s_star = pt[s]["var"] / r_st**2
+        t_pt_match = s_star * npix / (pt[s]["paths"] / pt[s]["time"])
+        mean_st = float(image_moments(img, spp)[0].mean())
+        details[str(s)] = dict(
+            rmse_st=r_st, rmse_pt_same_spp=r_pt, ref_noise_rms=float(np.sqrt(ref_noise2[s])),
+            mean_st=mean_st, mean_ref=float(ref[s].double().mean()),
+            st_paths_per_s=float(c[0] / t_sigma[s]), st_steps_per_path=float(c[2] / c[0]),
+            st_events_per_path=float(c[1] / c[0]), pt_events_per_path=pt[s]["events"] / pt[s]["paths"],
+            pt_paths_per_s=pt[s]["paths"] / pt[s]["time"], matched_spp_pt=s_star,
+            speedup_matched_rmse=t_pt_match / t_sigma[s])
+        log(f"ST sigma_t={s}: {t_sigma[s] * 1e3:.1f} ms, rmse {r_st:.3e} (PT@{spp} {r_pt:.3e}), "
+            f"mean {mean_st:.4e} vs ref {details[str(s)]['mean_ref']:.4e}, matched PT spp {s_star:.1f}, "
+            f"speed-up {t_pt_match / t_sigma[s]:.2f}")
+        tot_st += t_sigma[s]
+        tot_pt += t_pt_match
+    pt_rate = sum(pt[s]["paths"] for s in sigmas) / sum(pt[s]["time"] for s in sigmas)
+
+    diag = None
+    if args.diagnostics:
+        diag = {}
+        for s in sigmas:
+            img, t = timed(lambda: st_render(s, 5000, sampler=1))
+            diag[f"exact_walk_{s}"] = dict(rmse=float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30))),
+                                           time_ms=t * 1e3)
+            for tau in (0.1, 1.0, 4.0, 8.0):
+                img, t = timed(lambda: st_render(s, 5000, tau_min=tau))
+                diag[f"tau_{tau}_{s}"] = dict(rmse=float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30))),
+                                              time_ms=t * 1e3)
+            log(f"diag sigma_t={s}: " + ", ".join(f"{k}: {v['rmse']:.3e} / {v['time_ms']:.1f} ms"
+                                                  for k, v in diag.items() if k.endswith(f"_{s}")))
+
+    # roofline of the render kernel from the algorithmic VALU work of the timed step
+    ops = counters[0] * OPS_PER_PATH + counters[1] * OPS_PER_EVENT + counters[2] * OPS_PER_STEP
+    achieved = ops / (ms_per_step / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANEOPS / 1e12,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_VALU_LANEOPS, "traffic": None,
+                "mfma_tflops": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / 1e12,
+                "mfma_frac": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / PEAK_MFMA_BF16}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(oracle, W, args.cpu_seconds)
+
+    result = {
+        "metric": "sphere-traced paths/s (CVAE) vs plain random-walk paths/s at matched RMSE",
+        "value": value, "unit": "paths/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": f"sphere+box SDF scene {width}x{width}, {spp} spp, g=0.8, albedo=0.995, "
+                               f"sigma_t in {list(sigmas)}, point light + NEE, CVAE decoders BF16 on MFMA, "
+                               f"tau_min={args.tau_min}",
+                   "paths_per_step": paths_per_step, "parallelism": "single GPU"},
+        "plain_paths_per_s": pt_rate,
+        "speedup_matched_rmse": tot_pt / tot_st,
+        "per_sigma": details,
+        "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "diagnostics": diag,
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,6 +59,12 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Natural log for free-flight lengths -log(u) / sigma_t.  The raw
+// v_log_f32 has an absolute rather than relative error near u = 1, which
+// turns into a relative error of short flights; the library logf keeps full
+// relative precision there.
+__device__ __forceinline__ float flight_ln(float u) { return logf(u); }
+
 // Box-Muller pair from two uniforms.
 __device__ __forceinline__ void box_muller(float ua, float ub, float& n0, float& n1) {
     const float r = __builtin_sqrtf(-2.0f * fast_ln(ua));

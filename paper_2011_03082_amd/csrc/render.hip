@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
             } else {
                 t = __builtin_fmaxf(t, ps);
                 const uint4 w = rng.block(c0++);
-                const float l = -fast_ln(u01(w.x)) * A.inv_sigma_t;
+                const float l = -flight_ln(u01(w.x)) * A.inv_sigma_t;
                 if (t + l >= pe) {
                     t = pe;
                 } else {
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
                                         }
                                         const HgSample h = hg_sample(A.g, u01(ww.y));
                                         dir = scatter(dir, h.mu, h.sin_t, u01(ww.z));
-                                        const float ll = -fast_ln(u01(ww.x)) * A.inv_sigma_t;
+                                        const float ll = -flight_ln(u01(ww.x)) * A.inv_sigma_t;
                                         const V3 rel = x - p;
                                         const V3 qn = fma3(ll, dir, rel);
                                         if (!(dot(qn, qn) < r2)) {

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void walk_kernel(const WalkArgs a) {
         if (!stop) {
             const HgSample h = hg_sample(g, u01(w.y));
             d = scatter(d, h.mu, h.sin_t, u01(w.z));
-            const float l = -fast_ln(u01(w.x)) * inv_st;
+            const float l = -flight_ln(u01(w.x)) * inv_st;
             const V3 xn = fma3(l, d, x);
             if (!(dot(xn, xn) < r2)) {
                 xe = fma3(sphere_exit(x, d, r2), d, x);

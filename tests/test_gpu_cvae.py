@@ -129,8 +129,9 @@ def test_adamw_step_matches_oracle(msst, oracle):
     p, mm, vv = master64.copy(), m0.copy(), v0.copy()
     oracle.adamw_step(p, mm, vv, grad.cpu().numpy().astype(np.float64), 5, lr=1e-3, weight_decay=0.01)
     np.testing.assert_allclose(master.cpu().numpy(), p, rtol=1e-6, atol=1e-8)
-    np.testing.assert_allclose(m.cpu().numpy(), mm, rtol=1e-5, atol=1e-10)
-    np.testing.assert_allclose(v.cpu().numpy(), vv, rtol=1e-5, atol=1e-14)
+    # FP32 moments: beta m + (1 - beta) g loses ~1e-7 of max(|m|, |g|) absolutely
+    np.testing.assert_allclose(m.cpu().numpy(), mm, rtol=1e-5, atol=1e-7 * np.abs(mm).max())
+    np.testing.assert_allclose(v.cpu().numpy(), vv, rtol=1e-5, atol=1e-7 * np.abs(vv).max())
 
 
 def test_training_reduces_loss_and_keeps_padding_zero(msst, oracle):
