@@ -62,11 +62,15 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0):
     packed, losses = [], []
     for model in range(3):
         p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
-        cond = torch.empty((n_samples, p_in), dtype=torch.float32, device="cuda")
-        target = torch.empty((n_samples, p_out), dtype=torch.float32, device="cuda")
-        M.cvae_features(model, n_samples, walk, seed + 1, 0, None, cond, target)
+        # PathGen learns N >= 2 records and EventGen k >= 2 records: the
+        # single-event cases are sampled exactly by the renderer
+        rows = None if model == 0 else M.select_rows(walk, 2, 2 if model == 2 else 0)
+        n_rows = n_samples if rows is None else rows.numel()
+        cond = torch.empty((n_rows, p_in), dtype=torch.float32, device="cuda")
+        target = torch.empty((n_rows, p_out), dtype=torch.float32, device="cuda")
+        M.cvae_features(model, n_rows, walk, seed + 1, 0, None, cond, target, rows=rows)
         stats = M.make_stats(cond, target)
-        M.cvae_features(model, n_samples, walk, seed + 1, 0, stats, cond, target)
+        M.cvae_features(model, n_rows, walk, seed + 1, 0, stats, cond, target, rows=rows)
         n = M.cvae_param_count(model)
         master = torch.empty(n, dtype=torch.float32, device="cuda")
         M.cvae_init(model, seed + 10 + model, master)
@@ -76,7 +80,7 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0):
         first = None
         for step in range(1, steps + 1):
             lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
-            M.cvae_train_step(model, master, m, v, M.adam_params(step, lr=lr), cond, target, n_samples, batch, 1,
+            M.cvae_train_step(model, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
                               seed + 20 + model, step, 0, ws, loss)
             if step == 1:
                 first = loss.cpu().numpy().copy()
@@ -84,8 +88,8 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0):
         pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
         M.cvae_pack(model, master, stats, 1, pk)
         packed.append(pk)
-        losses.append((float(first[0]), float(last[0])))
-        log(f"model {model}: loss {first[0]:.4f} -> {last[0]:.4f}")
+        losses.append(dict(rows=int(n_rows), first=first.tolist(), last=last.tolist()))
+        log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
     torch.cuda.synchronize()
     return packed, losses, time.time() - t0
 

@@ -163,15 +163,28 @@ ms_status cvae_param_count(const ms_cvae_shape* shape, size_t* n_floats);
 ms_status cvae_init(const ms_cvae_shape* shape, uint64_t seed, float* master_dev, void* stream);
 
 /* Condition / target rows of one model from TRAINING walk outputs, row-major
- * [n][p_in] and [n][p_out].  LengthGen's target is log(N + u - 1/2), u from
- * tag DEQUANT (id = id_offset + i, c0 = 0, word 0).  If stats_dev is not
+ * [n][p_in] and [n][p_out].  Output row i is built from walk record
+ * rows_dev[i] (or record i when rows_dev is NULL); n_records is the length of
+ * the walk arrays.  LengthGen's target is log(N + u - 1/2), u from tag
+ * DEQUANT (id = id_offset + record, c0 = 0, word 0).  If stats_dev is not
  * NULL ([64] doubles: mean_c[16], std_c[16], mean_y[16], std_y[16]) the rows
  * are standardised. */
-ms_status cvae_features(int32_t model, int64_t n, const float* params3_dev,
-                        const uint32_t* n_scatter_dev, const float* exit_param_dev,
-                        const float* event_pos_dev, const float* event_dir_dev, uint64_t seed,
-                        uint64_t id_offset, const double* stats_dev, float* cond_dev,
-                        float* target_dev, void* stream);
+ms_status cvae_features(int32_t model, int64_t n, const int64_t* rows_dev, int64_t n_records,
+                        const float* params3_dev, const uint32_t* n_scatter_dev,
+                        const float* exit_param_dev, const float* event_pos_dev,
+                        const float* event_dir_dev, uint64_t seed, uint64_t id_offset,
+                        const double* stats_dev, float* cond_dev, float* target_dev, void* stream);
+
+/* Deterministic stream compaction of walk records: rows_dev receives, in
+ * increasing order, the indices i < n with n_scatter[i] >= min_scatter and
+ * (event_index_dev NULL or event_index[i] >= min_event); *count_dev (device)
+ * their number.  Used to train PathGen on N >= 2 and EventGen on k >= 2
+ * records, whose single-event cases the renderer samples exactly. */
+ms_status ms_select_rows_workspace_size(int64_t n, size_t* bytes);
+ms_status ms_select_rows(int64_t n, const uint32_t* n_scatter_dev, const uint32_t* event_index_dev,
+                         uint32_t min_scatter, uint32_t min_event, int64_t* rows_dev,
+                         int64_t* count_dev, void* workspace_dev, size_t workspace_bytes,
+                         void* stream);
 
 /* FP64 column mean and standard deviation of a row-major [n][dim] matrix,
  * written to out_dev[0..dim) and out_dev[16..16+dim) (dim <= 16), by a
@@ -226,8 +239,13 @@ ms_status cvae_sample(const void* packed_dev, const float* cond_dev, int64_t n, 
  * distance, st_max / sigma_t); if sigma_t r >= tau_min one learned sphere
  * step (LengthGen, absorption with probability 1 - albedo^N, PathGen,
  * EventGen, NEE at the representative event with weight
- * sum_{i<=N} albedo^i / albedo^N), else a plain event.  sampler EXACT_WALK
- * replaces the learned step by the actual walk inside the sphere.
+ * sum_{i<=N} albedo^i / albedo^N), else a plain event.  The single-event
+ * parts of the step are sampled exactly: N = 1 is one HG scatter at the
+ * centre (no PathGen), and for N >= 2 the representative event is the
+ * centre with probability albedo / sum_{i<=N} albedo^i (no EventGen);
+ * PathGen and EventGen are trained on the remaining records (see
+ * ms_select_rows).  sampler EXACT_WALK replaces the learned step by the
+ * actual walk inside the sphere.
  * Path (pixel, s) uses Philox id pixel | (sample_offset + s) << 32.
  * Results are ADDED to the caller-zeroed image buffers, so renders can be
  * resumed with sample_offset.  Primitive record: 8 floats

@@ -272,32 +272,51 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
     }
     out->survived = 1;
     double psi = 2.0 * OR_PI * u[1];
-    /* PathGen */
-    double c_path[3] = {lst, g, log(N)};
-    or_draw_normals(rd, id, c0, rd->shapes[1].latent + rd->shapes[1].p_out, nrm);
-    or_model_sample(rd, 1, c_path, nrm, y);
-    double ct = fmin(1.0, fmax(-1.0, y[0]));
-    double al = y[1], be = y[2];
-    double ga = sqrt(fmax(0.0, 1.0 - al * al - be * be));
-    double nl = sqrt(al * al + be * be + ga * ga);
-    al /= nl;
-    be /= nl;
-    ga /= nl;
-    /* EventGen */
-    double c_ev[7] = {lst, g, phi, ct, al, be, log(N)};
-    or_draw_normals(rd, id, c0, rd->shapes[2].latent + rd->shapes[2].p_out, nrm);
-    or_model_sample(rd, 2, c_ev, nrm, y);
-    double X[3] = {y[0], y[1], y[2]}, W[3] = {y[3], y[4], y[5]};
-    double xl = sqrt(or_dot(X, X));
-    if (xl > 1.0)
-        for (int i = 0; i < 3; ++i) X[i] /= xl;
-    double wl = sqrt(or_dot(W, W));
-    if (wl > 0.0) {
-        for (int i = 0; i < 3; ++i) W[i] /= wl;
+    double ct, al = 0.0, be = 0.0, ga = 1.0;
+    double X[3] = {0.0, 0.0, 0.0}, W[3] = {0.0, 0.0, 1.0};
+    if (N < 2.0) {
+        /* A single event at the centre: the exit is one HG scatter of the
+         * incoming direction (Sec. 3.1), which is sampled exactly instead of
+         * asking PathGen for a point mass (alpha = beta = 0), and the
+         * representative event is the centre itself. */
+        ct = or_hg_sample(g, u[2]);
     } else {
-        W[0] = 0.0;
-        W[1] = 0.0;
-        W[2] = 1.0;
+        /* PathGen */
+        double c_path[3] = {lst, g, log(N)};
+        or_draw_normals(rd, id, c0, rd->shapes[1].latent + rd->shapes[1].p_out, nrm);
+        or_model_sample(rd, 1, c_path, nrm, y);
+        ct = fmin(1.0, fmax(-1.0, y[0]));
+        al = y[1];
+        be = y[2];
+        ga = sqrt(fmax(0.0, 1.0 - al * al - be * be));
+        double nl = sqrt(al * al + be * be + ga * ga);
+        al /= nl;
+        be /= nl;
+        ga /= nl;
+        /* The representative event is the first one (the centre, entered
+         * along w_in) with probability albedo / Lambda^(N) (Sec. 4.3); that
+         * case is taken exactly and EventGen samples the others. */
+        double p_first = phi >= 1.0 ? 1.0 / N : (1.0 - phi) / (-expm1(N * log(phi)));
+        if (!(u[3] <= p_first)) {
+            double c_ev[7] = {lst, g, phi, ct, al, be, log(N)};
+            or_draw_normals(rd, id, c0, rd->shapes[2].latent + rd->shapes[2].p_out, nrm);
+            or_model_sample(rd, 2, c_ev, nrm, y);
+            for (int i = 0; i < 3; ++i) {
+                X[i] = y[i];
+                W[i] = y[3 + i];
+            }
+            double xl = sqrt(or_dot(X, X));
+            if (xl > 1.0)
+                for (int i = 0; i < 3; ++i) X[i] /= xl;
+            double wl = sqrt(or_dot(W, W));
+            if (wl > 0.0) {
+                for (int i = 0; i < 3; ++i) W[i] /= wl;
+            } else {
+                W[0] = 0.0;
+                W[1] = 0.0;
+                W[2] = 1.0;
+            }
+        }
     }
     /* Eq. (transform): x = p + r R R_psi x~ with R = [e1 e2 d], plus the
      * exit-frame direction of Sec. 4.1 and (X, W) rotated the same way. */

@@ -87,7 +87,9 @@ SIGNATURES = {
     "ms_random_walk": ([_P(WalkDesc), _P(WalkOut), _vp, _sz, _vp], C.c_int32),
     "cvae_param_count": ([_P(CvaeShape), _P(_sz)], C.c_int32),
     "cvae_init": ([_P(CvaeShape), _u64, _vp, _vp], C.c_int32),
-    "cvae_features": ([_i32, _i64, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _vp, _vp, _vp, _vp], C.c_int32),
+    "cvae_features": ([_i32, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _vp, _vp, _vp, _vp], C.c_int32),
+    "ms_select_rows_workspace_size": ([_i64, _P(_sz)], C.c_int32),
+    "ms_select_rows": ([_i64, _vp, _vp, _u32, _u32, _vp, _vp, _vp, _sz, _vp], C.c_int32),
     "ms_column_moments_workspace_size": ([_i64, _i32, _P(_sz)], C.c_int32),
     "ms_column_moments": ([_vp, _i64, _i32, _vp, _vp, _sz, _vp], C.c_int32),
     "cvae_workspace_size": ([_P(CvaeShape), _i32, _P(_sz)], C.c_int32),

@@ -121,10 +121,33 @@ def cvae_init(shape, seed, master, stream=None):
     check(lib().cvae_init(C.byref(cvae_shape(shape)), seed, _ptr(master), _stream(stream)))
 
 
-def cvae_features(model, n, walk, seed, id_offset, stats, cond, target, stream=None):
-    check(lib().cvae_features(model, n, _ptr(walk["params"]), _ptr(walk["n_scatter"]), _ptr(walk.get("exit_param")),
-                              _ptr(walk.get("event_pos")), _ptr(walk.get("event_dir")), seed, id_offset,
-                              _ptr(stats), _ptr(cond), _ptr(target), _stream(stream)))
+def cvae_features(model, n, walk, seed, id_offset, stats, cond, target, rows=None, stream=None):
+    n_records = walk["n_scatter"].numel()
+    check(lib().cvae_features(model, n, _ptr(rows), n_records, _ptr(walk["params"]), _ptr(walk["n_scatter"]),
+                              _ptr(walk.get("exit_param")), _ptr(walk.get("event_pos")), _ptr(walk.get("event_dir")),
+                              seed, id_offset, _ptr(stats), _ptr(cond), _ptr(target), _stream(stream)))
+
+
+def ms_select_rows_workspace_size(n):
+    b = C.c_size_t()
+    check(lib().ms_select_rows_workspace_size(n, C.byref(b)))
+    return b.value
+
+
+def ms_select_rows(n, n_scatter, event_index, min_scatter, min_event, rows, count, workspace, stream=None):
+    check(lib().ms_select_rows(n, _ptr(n_scatter), _ptr(event_index), min_scatter, min_event, _ptr(rows), _ptr(count),
+                               _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def select_rows(walk, min_scatter, min_event=0):
+    """Indices (int64 device tensor) of walk records with N >= min_scatter and k >= min_event."""
+    n = walk["n_scatter"].numel()
+    rows = torch.empty(n, dtype=torch.int64, device=walk["n_scatter"].device)
+    count = torch.zeros(1, dtype=torch.int64, device=rows.device)
+    ws = torch.empty(ms_select_rows_workspace_size(n), dtype=torch.uint8, device=rows.device)
+    ms_select_rows(n, walk["n_scatter"], walk.get("event_index") if min_event > 0 else None, min_scatter, min_event,
+                   rows, count, ws)
+    return rows[: int(count.item())]
 
 
 def ms_column_moments_workspace_size(n, dim):

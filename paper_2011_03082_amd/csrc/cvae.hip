@@ -70,11 +70,13 @@ __global__ void cvae_init_kernel(Shape s, uint64_t seed, float* master, int n_pa
 // ---------------------------------------------------------------------------
 // features (Sec. 4.2 model inputs; LengthGen target dequantised)
 
-__global__ void cvae_features_kernel(int model, int64_t n, const float* params3, const uint32_t* n_scatter,
-                                     const float* exit_param, const float* event_pos, const float* event_dir,
-                                     uint64_t seed, uint64_t id_offset, const double* stats, float* cond,
-                                     float* target) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+__global__ void cvae_features_kernel(int model, int64_t n_out, const int64_t* rows, int64_t n, const float* params3,
+                                     const uint32_t* n_scatter, const float* exit_param, const float* event_pos,
+                                     const float* event_dir, uint64_t seed, uint64_t id_offset, const double* stats,
+                                     float* cond, float* target) {
+    for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n_out;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = rows ? rows[o] : o;
         const float lst = logf(params3[i]), g = params3[n + i], phi = params3[2 * n + i];
         const float N = (float)n_scatter[i];
         float c[7], y[6];
@@ -111,9 +113,71 @@ __global__ void cvae_features_kernel(int model, int64_t n, const float* params3,
             for (int k = 0; k < pc; ++k) c[k] = (float)((c[k] - stats[k]) / stats[16 + k]);
             for (int k = 0; k < py; ++k) y[k] = (float)((y[k] - stats[32 + k]) / stats[48 + k]);
         }
-        for (int k = 0; k < pc; ++k) cond[i * pc + k] = c[k];
-        for (int k = 0; k < py; ++k) target[i * py + k] = y[k];
+        for (int k = 0; k < pc; ++k) cond[o * pc + k] = c[k];
+        for (int k = 0; k < py; ++k) target[o * py + k] = y[k];
     }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic row selection (stream compaction in index order)
+
+constexpr int kSelPerBlock = 2048;  // 256 threads x 8 consecutive rows
+
+__device__ __forceinline__ bool row_selected(int64_t i, int64_t n, const uint32_t* ns, const uint32_t* ek,
+                                             uint32_t min_n, uint32_t min_k) {
+    return i < n && ns[i] >= min_n && (ek == nullptr || ek[i] >= min_k);
+}
+
+__global__ void select_count_kernel(int64_t n, const uint32_t* ns, const uint32_t* ek, uint32_t min_n,
+                                    uint32_t min_k, int64_t* block_count) {
+    __shared__ int red[256];
+    const int64_t base = blockIdx.x * (int64_t)kSelPerBlock + threadIdx.x * 8;
+    int c = 0;
+    for (int j = 0; j < 8; ++j) c += row_selected(base + j, n, ns, ek, min_n, min_k);
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_count[blockIdx.x] = red[0];
+}
+
+__global__ void select_scan_kernel(int64_t nb, int64_t* block_count, int64_t* total) {
+    if (threadIdx.x != 0) return;
+    int64_t acc = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const int64_t c = block_count[b];
+        block_count[b] = acc;
+        acc += c;
+    }
+    *total = acc;
+}
+
+__global__ void select_write_kernel(int64_t n, const uint32_t* ns, const uint32_t* ek, uint32_t min_n,
+                                    uint32_t min_k, const int64_t* block_offset, int64_t* rows) {
+    __shared__ int wave_sum[4];
+    const int64_t base = blockIdx.x * (int64_t)kSelPerBlock + threadIdx.x * 8;
+    bool f[8];
+    int c = 0;
+    for (int j = 0; j < 8; ++j) {
+        f[j] = row_selected(base + j, n, ns, ek, min_n, min_k);
+        c += f[j];
+    }
+    // exclusive prefix of c over the block: within the wave, then across waves
+    int incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane_id() >= off) incl += v;
+    }
+    const int wave = threadIdx.x >> 6;
+    if (lane_id() == 63) wave_sum[wave] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_sum[w];
+    int64_t pos = block_offset[blockIdx.x] + before + incl - c;
+    for (int j = 0; j < 8; ++j)
+        if (f[j]) rows[pos++] = base + j;
 }
 
 // ---------------------------------------------------------------------------
@@ -420,7 +484,7 @@ struct AdamArgs {
     float* grad_out;
     double* loss_out;
     int do_update;
-    float lr, beta1, beta2, eps, wd, bc1, bc2;
+    float lr, beta1, beta2, one_m_beta1, one_m_beta2, eps, wd, bc1, bc2;
 };
 
 __global__ void cvae_adam_kernel(const AdamArgs a) {
@@ -430,8 +494,8 @@ __global__ void cvae_adam_kernel(const AdamArgs a) {
         for (int b = 0; b < a.n_blocks; ++b) g += a.partial[(int64_t)b * a.n_params + p];
         if (a.grad_out) a.grad_out[p] = g;
         if (a.do_update) {
-            const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * g;
-            const float v = a.beta2 * a.v[p] + (1.0f - a.beta2) * g * g;
+            const float m = a.beta1 * a.m[p] + a.one_m_beta1 * g;
+            const float v = a.beta2 * a.v[p] + a.one_m_beta2 * g * g;
             a.m[p] = m;
             a.v[p] = v;
             const float mh = m / a.bc1, vh = v / a.bc2;
@@ -642,13 +706,14 @@ ms_status cvae_init(const ms_cvae_shape* shape, uint64_t seed, float* master_dev
     return MS_OK;
 }
 
-ms_status cvae_features(int32_t model, int64_t n, const float* params3_dev, const uint32_t* n_scatter_dev,
-                        const float* exit_param_dev, const float* event_pos_dev, const float* event_dir_dev,
-                        uint64_t seed, uint64_t id_offset, const double* stats_dev, float* cond_dev,
-                        float* target_dev, void* stream) {
+ms_status cvae_features(int32_t model, int64_t n, const int64_t* rows_dev, int64_t n_records,
+                        const float* params3_dev, const uint32_t* n_scatter_dev, const float* exit_param_dev,
+                        const float* event_pos_dev, const float* event_dir_dev, uint64_t seed, uint64_t id_offset,
+                        const double* stats_dev, float* cond_dev, float* target_dev, void* stream) {
     using namespace msst;
     MS_REQUIRE(model >= 0 && model <= 2, "cvae_features: model must be 0, 1 or 2");
-    MS_REQUIRE(n > 0, "cvae_features: n must be positive");
+    MS_REQUIRE(n > 0 && n_records > 0, "cvae_features: n and n_records must be positive");
+    MS_REQUIRE(rows_dev != nullptr || n <= n_records, "cvae_features: n > n_records without a row list");
     MS_REQUIRE(params3_dev && n_scatter_dev && cond_dev && target_dev, "cvae_features: NULL array");
     MS_REQUIRE(model == 0 || exit_param_dev, "cvae_features: exit_param is required for PathGen and EventGen");
     MS_REQUIRE(model != 2 || (event_pos_dev && event_dir_dev), "cvae_features: event arrays required for EventGen");
@@ -658,8 +723,39 @@ ms_status cvae_features(int32_t model, int64_t n, const float* params3_dev, cons
     int64_t blocks = (n + 255) / 256;
     if (blocks > cus * 8) blocks = cus * 8;
     hipLaunchKernelGGL(cvae_features_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, model, n,
-                       params3_dev, n_scatter_dev, exit_param_dev, event_pos_dev, event_dir_dev, seed, id_offset,
-                       stats_dev, cond_dev, target_dev);
+                       rows_dev, n_records, params3_dev, n_scatter_dev, exit_param_dev, event_pos_dev, event_dir_dev,
+                       seed, id_offset, stats_dev, cond_dev, target_dev);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}
+
+ms_status ms_select_rows_workspace_size(int64_t n, size_t* bytes) {
+    MS_REQUIRE(bytes != nullptr && n > 0, "ms_select_rows_workspace_size: need n > 0 and bytes");
+    *bytes = (size_t)((n + msst::kSelPerBlock - 1) / msst::kSelPerBlock) * sizeof(int64_t) + 256;
+    return MS_OK;
+}
+
+ms_status ms_select_rows(int64_t n, const uint32_t* n_scatter_dev, const uint32_t* event_index_dev,
+                         uint32_t min_scatter, uint32_t min_event, int64_t* rows_dev, int64_t* count_dev,
+                         void* workspace_dev, size_t workspace_bytes, void* stream) {
+    using namespace msst;
+    MS_REQUIRE(n > 0 && n < ((int64_t)1 << 40), "ms_select_rows: n must be in [1, 2^40)");
+    MS_REQUIRE(n_scatter_dev && rows_dev && count_dev && workspace_dev, "ms_select_rows: NULL array");
+    size_t need = 0;
+    ms_select_rows_workspace_size(n, &need);
+    if (workspace_bytes < need) return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "ms_select_rows: workspace needs %zu bytes", need);
+    int cus;
+    ms_status st = device_cu_count(&cus);
+    if (st != MS_OK) return st;
+    const int64_t nb = (n + kSelPerBlock - 1) / kSelPerBlock;
+    int64_t* bc = reinterpret_cast<int64_t*>(workspace_dev);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(select_count_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, n_scatter_dev, event_index_dev,
+                       min_scatter, min_event, bc);
+    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(64), 0, s, nb, bc, count_dev);
+    hipLaunchKernelGGL(select_write_kernel, dim3((unsigned)nb), dim3(256), 0, s, n, n_scatter_dev, event_index_dev,
+                       min_scatter, min_event, (const int64_t*)bc, rows_dev);
     MS_LAUNCHED();
     clear_error();
     return MS_OK;
@@ -771,6 +867,8 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
         aa.lr = (float)adam->lr;
         aa.beta1 = (float)adam->beta1;
         aa.beta2 = (float)adam->beta2;
+        aa.one_m_beta1 = (float)(1.0 - adam->beta1);  // 1 - beta in FP32 would lose ~1e-5 relative
+        aa.one_m_beta2 = (float)(1.0 - adam->beta2);
         aa.eps = (float)adam->eps;
         aa.wd = (float)adam->weight_decay;
         aa.bc1 = (float)(1.0 - pow(adam->beta1, (double)adam->step));

@@ -59,10 +59,8 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// Natural log for free-flight lengths -log(u) / sigma_t.  The raw
-// v_log_f32 has an absolute rather than relative error near u = 1, which
-// turns into a relative error of short flights; the library logf keeps full
-// relative precision there.
+// Natural log for free-flight lengths -log(u) / sigma_t: the library logf
+// (about 1 ulp relative over (0, 1]).
 __device__ __forceinline__ float flight_ln(float u) { return logf(u); }
 
 // Box-Muller pair from two uniforms.

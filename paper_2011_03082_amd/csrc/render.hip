@@ -57,29 +57,43 @@ struct RenderArgs {
     unsigned long long* counters;
 };
 
-// Primitives held in registers for the whole kernel.
+// Primitives held in registers for the whole kernel (NP slots).
+template <int NP>
 struct Prims {
-    float p[kMaxPrims][8];
+    float p[NP][8];
     int n;
 };
 
 struct RenderLds {
-    float x[64][kTile];
-    float o[64][kTile];
+    float x[64][kTile];  // decoder inputs of the compacted lanes
+    float o[64][kTile];  // decoder outputs
+    float eps[64][8];    // decoder posterior noise of each compacted lane
 };
+
+enum : int { kModePlain = 0, kModeStExact = 1, kModeStCvae = 2 };
 
 // ---------------------------------------------------------------- geometry
 
 __device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float& t0, float& t1) {
     const V3 q = v3(o.x - pr[1], o.y - pr[2], o.z - pr[3]);
     if (pr[0] == 0.0f) {  // sphere
+        // discriminant from the closest-approach vector (Haines, Guenther,
+        // Akenine-Moller, "Precision Improvements for Ray/Sphere
+        // Intersection", Ray Tracing Gems, 2019): r^2 - |q - (q.d) d|^2 does
+        // not cancel for distant origins the way b^2 - (|q|^2 - r^2) does;
+        // the roots come from the stable quadratic form.
         const float b = dot(q, d);
-        const float c = dot(q, q) - pr[4] * pr[4];
-        const float disc = b * b - c;
+        const V3 h = fma3(-b, d, q);
+        const float r = pr[4];
+        const float hl = __builtin_sqrtf(dot(h, h));
+        const float disc = (r - hl) * (r + hl);
         if (!(disc > 0.0f)) return false;
         const float s = __builtin_sqrtf(disc);
-        t0 = -b - s;
-        t1 = -b + s;
+        const float c = dot(q, q) - r * r;
+        const float qq = b > 0.0f ? -b - s : -b + s;  // same sign as -b, no cancellation
+        const float ta = c / qq, tb = qq;
+        t0 = __builtin_fminf(ta, tb);
+        t1 = __builtin_fmaxf(ta, tb);
         return true;
     }
     float lo = -INFINITY, hi = INFINITY;
@@ -91,14 +105,10 @@ __device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float
             if (qa[a] < -h || qa[a] > h) return false;
             continue;
         }
-        float ta = (-h - qa[a]) / da[a], tb = (h - qa[a]) / da[a];
-        if (ta > tb) {
-            const float tmp = ta;
-            ta = tb;
-            tb = tmp;
-        }
-        lo = __builtin_fmaxf(lo, ta);
-        hi = __builtin_fminf(hi, tb);
+        const float inv = 1.0f / da[a];
+        float ta = (-h - qa[a]) * inv, tb = (h - qa[a]) * inv;
+        lo = __builtin_fmaxf(lo, __builtin_fminf(ta, tb));
+        hi = __builtin_fminf(hi, __builtin_fmaxf(ta, tb));
     }
     if (!(lo < hi)) return false;
     t0 = lo;
@@ -107,13 +117,15 @@ __device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float
 }
 
 // Intervals of one ray in each primitive (unused slots: [+inf, -inf]).
+template <int NP>
 struct RayIv {
-    float a[kMaxPrims], b[kMaxPrims];
+    float a[NP], b[NP];
 };
 
-__device__ __forceinline__ void ray_intervals(const Prims& P, V3 o, V3 d, RayIv& iv) {
+template <int NP>
+__device__ __forceinline__ void ray_intervals(const Prims<NP>& P, V3 o, V3 d, RayIv<NP>& iv) {
 #pragma unroll
-    for (int i = 0; i < kMaxPrims; ++i) {
+    for (int i = 0; i < NP; ++i) {
         iv.a[i] = INFINITY;
         iv.b[i] = -INFINITY;
         float t0, t1;
@@ -126,17 +138,18 @@ __device__ __forceinline__ void ray_intervals(const Prims& P, V3 o, V3 d, RayIv&
 
 // The connected piece [s, e] of the union of primitive intervals that
 // contains t or starts first after it; false if the ray leaves for good.
-__device__ __forceinline__ bool union_piece(const RayIv& iv, float t, float& s, float& e) {
+template <int NP>
+__device__ __forceinline__ bool union_piece(const RayIv<NP>& iv, float t, float& s, float& e) {
     s = INFINITY;
 #pragma unroll
-    for (int i = 0; i < kMaxPrims; ++i)
+    for (int i = 0; i < NP; ++i)
         if (iv.b[i] > t) s = __builtin_fminf(s, __builtin_fmaxf(iv.a[i], t));
     if (s == INFINITY) return false;
     e = s;
 #pragma unroll
-    for (int pass = 0; pass < kMaxPrims; ++pass)
+    for (int pass = 0; pass < NP; ++pass)
 #pragma unroll
-        for (int i = 0; i < kMaxPrims; ++i)
+        for (int i = 0; i < NP; ++i)
             if (iv.a[i] <= e && iv.b[i] > e) e = iv.b[i];
     return true;
 }
@@ -157,7 +170,8 @@ __device__ __forceinline__ float fp16_value(uint16_t h) {
 // Radius of a sphere around p inside the body (see the C header): analytic
 // union distance shrunk by 0.1 %, or nearest grid voxel minus half a voxel
 // diagonal.
-__device__ __forceinline__ float conservative_radius(const RenderArgs& A, const Prims& P, V3 p) {
+template <int NP>
+__device__ __forceinline__ float conservative_radius(const RenderArgs& A, const Prims<NP>& P, V3 p) {
     if (A.grid) {
         const float fx = (p.x - A.grid_lo[0]) * A.grid_inv_h[0];
         const float fy = (p.y - A.grid_lo[1]) * A.grid_inv_h[1];
@@ -170,24 +184,25 @@ __device__ __forceinline__ float conservative_radius(const RenderArgs& A, const 
     }
     float s = INFINITY;
 #pragma unroll
-    for (int i = 0; i < kMaxPrims; ++i)
+    for (int i = 0; i < NP; ++i)
         if (i < P.n) s = __builtin_fminf(s, prim_sdf(P.p[i], p));
     return s < 0.0f ? -0.999f * s : 0.0f;
 }
 
 // Point-light next-event estimate at x for a path travelling along d:
 // I rho_g(d . w_{x->L}) exp(-sigma_t d_t) / |x_L - x|^2 (Sec. 4.3).
-__device__ __forceinline__ float nee(const RenderArgs& A, const Prims& P, V3 x, V3 d) {
+template <int NP>
+__device__ __forceinline__ float nee(const RenderArgs& A, const Prims<NP>& P, V3 x, V3 d) {
     V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
     const float dist2 = dot(wl, wl);
     const float inv_dist = fast_rsq(dist2);
     const float dist = dist2 * inv_dist;
     wl = inv_dist * wl;
-    RayIv iv;
+    RayIv<NP> iv;
     ray_intervals(P, x, wl, iv);
     float acc = 0.0f, t = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kMaxPrims; ++k) {
+    for (int k = 0; k < NP; ++k) {
         float s, e;
         if (t < dist && union_piece(iv, t, s, e) && s < dist) {
             acc += __builtin_fminf(e, dist) - s;
@@ -214,16 +229,35 @@ __device__ __forceinline__ float lambda_weight(const RenderArgs& A, float N) {
     return A.albedo * (fast_exp(-N * A.ln_albedo) - 1.0f) / (1.0f - A.albedo);
 }
 
-// Stages this lane's decoder input (if `mine`) at its compacted slot, runs
-// the decoder on the occupied 16-path tiles and returns the de-standardised
-// sample y[0..P) of this lane.
-template <int P>
-__device__ __forceinline__ void decode_compacted(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
-                                                 const float* in16, const float* eps, float* y) {
-    if (mine) {
+// Writes this lane's decoder input row: L latent normals (z) from Philox
+// blocks, then the standardised condition; keeps the posterior noise in LDS.
+template <int LAT, int PO, int PI>
+__device__ __forceinline__ void stage_input(const PackedModel* pm, RenderLds& L, int slot, const Rng& rng,
+                                            uint32_t& c0, const float* cond) {
+    float nrm[((LAT + PO + 3) / 4) * 4];
 #pragma unroll
-        for (int q = 0; q < kTile; ++q) L.x[slot][q] = in16[q];
+    for (int j = 0; j < (LAT + PO + 3) / 4; ++j) {
+        const uint4 w = rng.block(c0++);
+        box_muller(u01(w.x), u01(w.y), nrm[4 * j + 0], nrm[4 * j + 1]);
+        box_muller(u01(w.z), u01(w.w), nrm[4 * j + 2], nrm[4 * j + 3]);
     }
+    float* row = L.x[slot];
+#pragma unroll
+    for (int q = 0; q < LAT; ++q) row[q] = nrm[q];
+#pragma unroll
+    for (int k = 0; k < PI; ++k) row[LAT + k] = (cond[k] - pm->mean_c[k]) * pm->inv_std_c[k];
+#pragma unroll
+    for (int q = LAT + PI; q < kTile; ++q) row[q] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PO; ++k) L.eps[slot][k] = nrm[LAT + k];
+}
+
+// Runs one decoder over the first n compacted rows (16-path MFMA tiles) and
+// returns the de-standardised sample y[0..PO) of slot `slot` for lanes that
+// staged an input.
+template <int PO>
+__device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
+                                            float* y) {
     wave_sync();
     const int n_tiles = (n + 15) >> 4;
     for (int t = 0; t < n_tiles; ++t) {
@@ -235,31 +269,26 @@ __device__ __forceinline__ void decode_compacted(const PackedModel* pm, RenderLd
     wave_sync();
     if (mine) {
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
+        for (int k = 0; k < PO; ++k) {
             const float mu = L.o[slot][k];
-            const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.o[slot][P + k]));
-            const float ys = __builtin_fmaf(fast_exp(0.5f * lv), eps[k], mu);
+            const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.o[slot][PO + k]));
+            const float ys = __builtin_fmaf(fast_exp(0.5f * lv), L.eps[slot][k], mu);
             y[k] = __builtin_fmaf(ys, pm->std_y[k], pm->mean_y[k]);
         }
     }
     wave_sync();
 }
 
-__device__ __forceinline__ void draw_normals(const Rng& r, uint32_t& c0, int count, float* nrm) {
-    for (int j = 0; 4 * j < count; ++j) {
-        const uint4 w = r.block(c0++);
-        box_muller(u01(w.x), u01(w.y), nrm[4 * j + 0], nrm[4 * j + 1]);
-        box_muller(u01(w.z), u01(w.w), nrm[4 * j + 2], nrm[4 * j + 3]);
-    }
-}
-
-__global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
+// Four waves per SIMD: measured faster than the unconstrained allocation
+// (three waves) despite a few spilled registers.
+template <int MODE, int NP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
     __shared__ RenderLds lds_all[kRenderWaves];
     RenderLds& L = lds_all[threadIdx.x >> 6];
-    Prims P;
+    Prims<NP> P;
     P.n = A.n_prims;
 #pragma unroll
-    for (int i = 0; i < kMaxPrims; ++i)
+    for (int i = 0; i < NP; ++i)
 #pragma unroll
         for (int k = 0; k < 8; ++k) P.p[i][k] = i < A.n_prims ? A.prims[i * 8 + k] : 0.0f;
 
@@ -276,8 +305,8 @@ __global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
     V3 o = v3(0, 0, 0), d = v3(0, 0, 1);
     float t = 0.0f, Lp = 0.0f, r_step = 0.0f;
     uint32_t c0 = 0, iters = 0, p_ev = 0, p_st = 0;
-    RayIv iv;
-    uint64_t cnt_paths = 0, cnt_events = 0, cnt_steps = 0, cnt_trunc = 0;
+    RayIv<NP> iv;
+    uint32_t cnt_paths = 0, cnt_events = 0, cnt_steps = 0, cnt_trunc = 0;
 
     for (;;) {
         // ---- work units
@@ -340,11 +369,11 @@ __global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
                         truncated = true;
                     } else {
                         bool plain = true;
-                        if (A.method == MS_METHOD_ST) {
+                        if (MODE != kModePlain) {
                             const float r = __builtin_fminf(conservative_radius(A, P, p), A.st_max * A.inv_sigma_t);
                             if (A.sigma_t * r >= A.tau_min) {
                                 plain = false;
-                                if (A.sampler == MS_SAMPLER_EXACT_WALK) {
+                                if (MODE == kModeStExact) {
                                     // the actual walk inside the sphere (reference sampler)
                                     V3 x = p, dir = d, Xk = p, Wk = d;
                                     float resv = 0.0f;
@@ -408,85 +437,85 @@ __global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
         }
 
         // ---- MFMA phase: learned sphere steps for the waiting lanes
-        const uint64_t wmask = ballot(state == S_WAIT);
-        const uint64_t lmask = ballot(state == S_NEW || state == S_FLY || state == S_WAIT);
-        const int n_wait = __popcll(wmask);
-        if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask)) {
-            const bool mine = state == S_WAIT;
-            float nrm[12], in16[kTile], y[6];
-            float N = 1.0f, psi = 0.0f;
-            const float str = A.sigma_t * r_step;
-            const float lst = fast_ln(str);
-            // LengthGen (sigma_t r, g) -> N
-            const PackedModel* pl = A.pm[0];
-            if (mine) {
-                draw_normals(rng, c0, 5, nrm);
-#pragma unroll
-                for (int q = 0; q < kTile; ++q) in16[q] = 0.0f;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) in16[q] = nrm[q];
-                in16[4] = (lst - pl->mean_c[0]) * pl->inv_std_c[0];
-                in16[5] = (A.g - pl->mean_c[1]) * pl->inv_std_c[1];
-            }
-            decode_compacted<1>(pl, L, mine, rank_in(wmask), n_wait, in16, nrm + 4, y);
-            bool alive = false;
-            if (mine) {
-                ++p_st;
-                N = __builtin_fmaxf(1.0f, floorf(fast_exp(__builtin_fminf(y[0], 20.0f)) + 0.5f));
-                const uint4 wa = rng.block(c0++);
-                psi = u01(wa.y);
-                // absorption along the bypassed chain (Sec. 3.2)
-                alive = u01(wa.x) <= fast_exp(N * A.ln_albedo);
-                if (!alive) path_end = true;
-            }
-            const uint64_t amask = ballot(alive);
-            const int n_alive = __popcll(amask);
-            if (n_alive > 0) {
-                const int slot = rank_in(amask);
-                // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
-                const PackedModel* pp = A.pm[1];
-                const float lnN = fast_ln(N);
-                if (alive) {
-                    draw_normals(rng, c0, 7, nrm);
-#pragma unroll
-                    for (int q = 0; q < kTile; ++q) in16[q] = 0.0f;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) in16[q] = nrm[q];
-                    in16[4] = (lst - pp->mean_c[0]) * pp->inv_std_c[0];
-                    in16[5] = (A.g - pp->mean_c[1]) * pp->inv_std_c[1];
-                    in16[6] = (lnN - pp->mean_c[2]) * pp->inv_std_c[2];
+        if (MODE == kModeStCvae) {
+            const uint64_t wmask = ballot(state == S_WAIT);
+            const uint64_t lmask = ballot(state == S_NEW || state == S_FLY || state == S_WAIT);
+            const int n_wait = __popcll(wmask);
+            if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask)) {
+                const bool mine = state == S_WAIT;
+                float y[6];
+                float N = 1.0f, psi = 0.0f;
+                const float lst = fast_ln(A.sigma_t * r_step);
+                // LengthGen (sigma_t r, g) -> N
+                const int slot0 = rank_in(wmask);
+                if (mine) {
+                    const float c2[2] = {lst, A.g};
+                    stage_input<4, 1, 2>(A.pm[0], L, slot0, rng, c0, c2);
                 }
-                decode_compacted<3>(pp, L, alive, slot, n_alive, in16, nrm + 4, y);
+                decode_rows<1>(A.pm[0], L, mine, slot0, n_wait, y);
+                bool alive = false;
+                float u_hg = 0.5f, u_first = 1.0f, phiN = 1.0f;
+                if (mine) {
+                    ++p_st;
+                    N = __builtin_fmaxf(1.0f, floorf(fast_exp(__builtin_fminf(y[0], 20.0f)) + 0.5f));
+                    const uint4 wa = rng.block(c0++);
+                    psi = u01(wa.y);
+                    u_hg = u01(wa.z);
+                    u_first = u01(wa.w);
+                    // absorption along the bypassed chain (Sec. 3.2)
+                    phiN = fast_exp(N * A.ln_albedo);
+                    alive = u01(wa.x) <= phiN;
+                    if (!alive) path_end = true;
+                }
+                // N = 1: a single HG scatter at the centre, sampled exactly;
+                // N >= 2: PathGen, then the representative event is the centre
+                // with probability albedo / Lambda^(N), else EventGen.
+                const bool use_path = alive && N >= 2.0f;
+                const float wgt = lambda_weight(A, N);
+                const bool use_event = use_path && !(u_first * wgt * phiN <= A.albedo);
                 float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
-                if (alive) {
-                    ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
-                    al = y[1];
-                    be = y[2];
-                    ga = __builtin_sqrtf(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
-                    const float inl = fast_rsq(al * al + be * be + ga * ga);
-                    al *= inl;
-                    be *= inl;
-                    ga *= inl;
+                if (alive && !use_path) ct = hg_sample(A.g, u_hg).mu;
+                const uint64_t pmask = ballot(use_path);
+                const float lnN = fast_ln(N);
+                if (pmask) {
+                    const int slot = rank_in(pmask);
+                    // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
+                    if (use_path) {
+                        const float c3[3] = {lst, A.g, lnN};
+                        stage_input<4, 3, 3>(A.pm[1], L, slot, rng, c0, c3);
+                    }
+                    decode_rows<3>(A.pm[1], L, use_path, slot, __popcll(pmask), y);
+                    if (use_path) {
+                        ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
+                        al = y[1];
+                        be = y[2];
+                        ga = __builtin_sqrtf(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
+                        const float inl = fast_rsq(al * al + be * be + ga * ga);
+                        al *= inl;
+                        be *= inl;
+                        ga *= inl;
+                    }
                 }
-                // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
-                const PackedModel* pe = A.pm[2];
-                if (alive) {
-                    draw_normals(rng, c0, 10, nrm);
-                    const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-#pragma unroll
-                    for (int q = 0; q < kTile; ++q) in16[q] = 0.0f;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) in16[q] = nrm[q];
-#pragma unroll
-                    for (int k = 0; k < 7; ++k) in16[4 + k] = (c7[k] - pe->mean_c[k]) * pe->inv_std_c[k];
+                V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
+                const uint64_t emask = ballot(use_event);
+                if (emask) {
+                    const int slot = rank_in(emask);
+                    // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
+                    if (use_event) {
+                        const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
+                        stage_input<4, 6, 7>(A.pm[2], L, slot, rng, c0, c7);
+                    }
+                    decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
+                    if (use_event) {
+                        X = v3(y[0], y[1], y[2]);
+                        W = v3(y[3], y[4], y[5]);
+                        const float xl2 = dot(X, X);
+                        if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
+                        const float wl2 = dot(W, W);
+                        W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
+                    }
                 }
-                decode_compacted<6>(pe, L, alive, slot, n_alive, in16, nrm + 4, y);
                 if (alive) {
-                    V3 X = v3(y[0], y[1], y[2]), W = v3(y[3], y[4], y[5]);
-                    const float xl2 = dot(X, X);
-                    if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
-                    const float wl2 = dot(W, W);
-                    W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
                     // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
                     V3 e1, e2;
                     onb(d, e1, e2);
@@ -501,7 +530,7 @@ __global__ __launch_bounds__(256) void render_kernel(const RenderArgs A) {
                     const V3 ww = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
                     const V3 Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
                     const V3 Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
-                    Lp += lambda_weight(A, N) * nee(A, P, Xw, Ww);
+                    Lp += wgt * nee(A, P, Xw, Ww);
                     o = xw;
                     d = ww;
                     ray_intervals(P, o, d, iv);
@@ -741,7 +770,24 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     int64_t blocks = (int64_t)cus * bpc;
     const int64_t need_blocks = (A.n_units + 255) / 256;
     if (blocks > need_blocks) blocks = need_blocks;
-    hipLaunchKernelGGL(render_kernel, dim3((unsigned)blocks), dim3(64 * kRenderWaves), 0, hs, A);
+    const int mode = desc->method == MS_METHOD_PLAIN_NEE ? kModePlain
+                     : (desc->sampler == MS_SAMPLER_EXACT_WALK ? kModeStExact : kModeStCvae);
+    const dim3 grid((unsigned)blocks), block(64 * kRenderWaves);
+#define MS_RENDER_LAUNCH(M, N) hipLaunchKernelGGL((render_kernel<M, N>), grid, block, 0, hs, A)
+    if (A.n_prims <= 1) {
+        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 1);
+        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 1);
+        else MS_RENDER_LAUNCH(kModeStCvae, 1);
+    } else if (A.n_prims == 2) {
+        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 2);
+        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 2);
+        else MS_RENDER_LAUNCH(kModeStCvae, 2);
+    } else {
+        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 4);
+        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 4);
+        else MS_RENDER_LAUNCH(kModeStCvae, 4);
+    }
+#undef MS_RENDER_LAUNCH
     MS_LAUNCHED();
     int64_t rb = (A.npix + 255) / 256;
     if (rb > cus * 8) rb = cus * 8;

@@ -60,6 +60,19 @@ def test_features_and_moments(msst, oracle):
         np.testing.assert_allclose(cond.cpu().numpy(), (rc - st[:p_in]) / st[16:16 + p_in], rtol=1e-5, atol=1e-5)
 
 
+def test_select_rows_is_exact(msst):
+    announce("select rows")
+    walk = msst.random_walk(70001, seed=3, mode=1)
+    ns = walk["n_scatter"].cpu().numpy()
+    ek = walk["event_index"].cpu().numpy()
+    rows = msst.select_rows(walk, 2).cpu().numpy()
+    np.testing.assert_array_equal(rows, np.flatnonzero(ns >= 2))
+    rows = msst.select_rows(walk, 2, 2).cpu().numpy()
+    np.testing.assert_array_equal(rows, np.flatnonzero((ns >= 2) & (ek >= 2)))
+    rows = msst.select_rows(walk, 10**9).cpu().numpy()
+    assert rows.size == 0
+
+
 def grad_case(msst, oracle, model, B, sample_rows=0, n_rows=None):
     shape = W.SHAPE_LIST[model]
     master64 = oracle.cvae_init(shape, seed=31 + model).astype(np.float32).astype(np.float64)

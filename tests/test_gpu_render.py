@@ -122,7 +122,9 @@ def test_tau_above_all_radii_is_plain(msst):
     prims, cam, light, med = c4_inputs(10.0, 32)
     a = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=3, seed=6)
     b = gpu_render(msst, prims, cam, light, med, method=ST, sampler=EXACT, tau_min=1e30, spp=3, seed=6)
-    np.testing.assert_array_equal(a["sum"], b["sum"])
+    # separate kernel instantiations may contract floating point differently
+    np.testing.assert_allclose(a["sum"], b["sum"], rtol=1e-5, atol=1e-9)
+    np.testing.assert_array_equal(a["events"], b["events"])
     assert b["steps"].sum() == 0
 
 
