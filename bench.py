@@ -23,9 +23,9 @@ sys.path.insert(0, ROOT)
 # VALU work of the algorithm per unit, in 32-bit lane-operation slots
 # (quarter-rate instructions -- transcendentals, 32-bit integer multiplies --
 # count 4 slots).  Derivation in DESIGN.md ("Roofline").
-OPS_PER_PATH = 180.0         # camera ray, primary intervals, path bookkeeping
-OPS_PER_EVENT = 440.0        # one plain collision: Philox block, flight, NEE, roulette, HG, new ray
-OPS_PER_STEP = 2600.0        # one learned sphere step on VALU (the MFMA part is separate)
+OPS_PER_PATH = 220.0         # camera ray, primary intervals, path bookkeeping
+OPS_PER_EVENT = 380.0        # one plain collision: Philox block, flight, NEE, roulette, HG, new ray
+OPS_PER_STEP = 2750.0        # one learned sphere step on VALU (the MFMA part is separate)
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
 PEAK_MFMA_BF16 = 2.5e15
@@ -55,8 +55,11 @@ def parse():
     return ap.parse_args()
 
 
-def train_models(M, torch, n_samples, steps, batch=4096, seed=0):
-    """GPU walk -> features -> FP64 standardisation -> AdamW training -> BF16 pack."""
+def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.3, precision=1):
+    """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
+
+    The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
+    steps (a guard against decoders that ignore the latent)."""
     t0 = time.time()
     walk = M.random_walk(n_samples, seed=seed, mode=1)
     packed, losses = [], []
@@ -80,18 +83,24 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0):
         first = None
         for step in range(1, steps + 1):
             lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
+            beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
             M.cvae_train_step(model, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
-                              seed + 20 + model, step, 0, ws, loss)
+                              seed + 20 + model, step, 0, ws, loss, kl_weight=beta)
             if step == 1:
                 first = loss.cpu().numpy().copy()
         last = loss.cpu().numpy().copy()
         pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-        M.cvae_pack(model, master, stats, 1, pk)
+        M.cvae_pack(model, master, stats, precision, pk)
         packed.append(pk)
         losses.append(dict(rows=int(n_rows), first=first.tolist(), last=last.tolist()))
         log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
     torch.cuda.synchronize()
     return packed, losses, time.time() - t0
+
+
+def train_models_both(M, torch, n_samples, steps, **kw):
+    """As train_models, returning BF16 and FP8 packings of the same weights."""
+    return train_models(M, torch, n_samples, steps, **kw)
 
 
 def image_moments(img, spp):

@@ -202,8 +202,10 @@ ms_status ms_column_moments(const float* x_dev, int64_t n, int32_t dim, double* 
  *        CVAE_BATCH (id = b, c0 = step): uniform with replacement.
  *  noise: eps of sample b from tag CVAE_REPARAM, id = id_offset + b,
  *        c0 = 4 * step + j.
+ *  kl_weight: weight of the KL term in the gradient (1 = the ELBO; a
+ *        warm-up from 0 is the usual guard against an unused latent).
  *  adam == NULL computes the gradient without updating.
- *  loss_dev (nullable, [3] doubles): batch-mean total, KL, NLL.
+ *  loss_dev (nullable, [3] doubles): batch-mean KL + NLL, KL, NLL (unweighted).
  *  grad_dev (nullable, cvae_param_count floats): batch-mean gradient.
  * batch must be a positive multiple of 16, at most 2^20. */
 ms_status cvae_workspace_size(const ms_cvae_shape* shape, int32_t batch, size_t* bytes);
@@ -211,8 +213,8 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
                           float* adam_v_dev, const ms_adam* adam, const float* cond_dev,
                           const float* target_dev, int64_t n_rows, int32_t batch,
                           int32_t sample_rows, uint64_t seed, int64_t step, uint64_t id_offset,
-                          void* workspace_dev, size_t workspace_bytes, double* loss_dev,
-                          float* grad_dev, void* stream);
+                          double kl_weight, void* workspace_dev, size_t workspace_bytes,
+                          double* loss_dev, float* grad_dev, void* stream);
 
 /* Inference copy of one model's decoder: bfloat16 weights, or FP8 E4M3
  * weights with a per-layer scale max|W| / 448 (FP32 accumulation either
@@ -257,7 +259,7 @@ enum { MS_SAMPLER_CVAE = 0, MS_SAMPLER_EXACT_WALK = 1 };
 
 typedef struct {
     const float* prims;       /* device [n_prims][8] */
-    int32_t n_prims;          /* 1..4 */
+    int32_t n_prims;          /* 1..256 (up to 4 are held in registers) */
     const uint16_t* sdf_fp16; /* optional device grid [res^3], x fastest */
     int32_t res;
     float lo[3], hi[3];
@@ -305,6 +307,16 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                               const ms_medium* medium, const ms_render_desc* desc,
                               const ms_image_out* out, void* workspace_dev, size_t workspace_bytes,
                               void* stream);
+
+/* Conservative distance grid of a scene (the voxel-grid distance pre-process
+ * of Sec. 3, with a Euclidean lower bound in place of the Chebyshev
+ * distance): grid_dev[(k * res + j) * res + i] = binary16 bits of
+ * min_prims sdf(lo + (i + 1/2, j + 1/2, k + 1/2) h), evaluated in FP64 and
+ * rounded toward zero, h = (hi - lo) / res, over scene->lo .. scene->hi
+ * (scene->sdf_fp16 and scene->res are ignored).  Passing the grid back in
+ * ms_scene makes the renderer take sphere radii from the nearest voxel
+ * minus half a voxel diagonal.  1..256 primitives, res <= 4096. */
+ms_status ms_build_sdf_grid(const ms_scene* scene, int32_t res, uint16_t* grid_dev, void* stream);
 
 /* FP64 image statistics (deterministic): out_dev[0] mean radiance,
  * [1] RMSE against ref_dev (per-pixel means), [2] mean per-pixel variance

@@ -110,7 +110,7 @@ def lib():
         L.or_round_fp8_e4m3.argtypes = [dbl]
         L.or_round_fp8_e4m3.restype = dbl
         L.or_cvae_init.argtypes = [C.POINTER(_Shape), u64, vp]
-        L.or_cvae_loss_grad.argtypes = [C.POINTER(_Shape), vp, i32, vp, vp, u64, i64, u64, vp, vp, vp]
+        L.or_cvae_loss_grad.argtypes = [C.POINTER(_Shape), vp, i32, vp, vp, u64, i64, u64, dbl, vp, vp, vp]
         L.or_cvae_loss_grad.restype = dbl
         L.or_adamw_step.argtypes = [i32, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, i64]
         L.or_cvae_sample.argtypes = [C.POINTER(_Shape), vp, vp, i32, vp, vp, i64, u64, u64, vp]
@@ -233,7 +233,7 @@ def cvae_init(shape, seed):
     return p
 
 
-def cvae_loss_grad(shape, params, cond, target, seed, step, id_offset=0, want_grad=True):
+def cvae_loss_grad(shape, params, cond, target, seed, step, id_offset=0, want_grad=True, kl_weight=1.0):
     params = np.ascontiguousarray(params, dtype=np.float64)
     cond = np.ascontiguousarray(cond, dtype=np.float64)
     target = np.ascontiguousarray(target, dtype=np.float64)
@@ -242,7 +242,7 @@ def cvae_loss_grad(shape, params, cond, target, seed, step, id_offset=0, want_gr
     kl, nll = C.c_double(), C.c_double()
     s = _shape(shape)
     loss = lib().or_cvae_loss_grad(C.byref(s), _p(params), B, _p(cond), _p(target), seed, step,
-                                   id_offset, _p(grad), C.byref(kl), C.byref(nll))
+                                   id_offset, kl_weight, _p(grad), C.byref(kl), C.byref(nll))
     return loss, kl.value, nll.value, grad
 
 

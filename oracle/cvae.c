@@ -195,7 +195,8 @@ static double or_clamp_mask(double x) { return (x > OR_LV_MIN && x < OR_LV_MAX) 
 
 double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t batch,
                          const double* cond, const double* target, uint64_t seed, int64_t step,
-                         uint64_t id_offset, double* grad, double* kl_out, double* nll_out) {
+                         uint64_t id_offset, double kl_weight, double* grad, double* kl_out,
+                         double* nll_out) {
     const int nl = or_n_linear(s);
     const int P = s->p_out, L = s->latent, C = s->p_in;
     or_dims de, dd;
@@ -248,8 +249,8 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
         for (int i = 0; i < L; ++i) {
             double dz = ddin[i];
             double sd = exp(0.5 * lvz[i]);
-            dout_e[i] = dz + muz[i];
-            dout_e[L + i] = (0.5 * dz * eps[i] * sd + 0.5 * (exp(lvz[i]) - 1.0)) *
+            dout_e[i] = dz + kl_weight * muz[i];
+            dout_e[L + i] = (0.5 * dz * eps[i] * sd + kl_weight * 0.5 * (exp(lvz[i]) - 1.0)) *
                             or_clamp_mask(lvz_raw[i]);
         }
         or_mlp_backward(params, 0, nl, &de, &te, dout_e, grad, NULL);
@@ -261,6 +262,9 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
     if (nll_out) *nll_out = nll_sum * inv;
     return (kl_sum + nll_sum) * inv;
 }
+
+/* The gradient above is that of NLL + kl_weight * KL (kl_weight = 1 is the
+ * negative ELBO); the returned loss and kl_out / nll_out are unweighted. */
 
 /* AdamW (Loshchilov and Hutter), the optimiser named in Sec. 3.2, with bias
  * correction and decoupled weight decay applied to the pre-step value. */

@@ -101,10 +101,12 @@ double or_round_fp8_e4m3(double x);
 
 void or_cvae_init(const or_cvae_shape* s, uint64_t seed, double* params);
 
-/* Mean loss over the batch; grad (may be NULL) receives d loss / d params. */
+/* Mean KL + NLL over the batch; grad (may be NULL) receives the gradient of
+ * NLL + kl_weight * KL with respect to the parameters. */
 double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t batch,
                          const double* cond, const double* target, uint64_t seed, int64_t step,
-                         uint64_t id_offset, double* grad, double* kl_out, double* nll_out);
+                         uint64_t id_offset, double kl_weight, double* grad, double* kl_out,
+                         double* nll_out);
 
 void or_adamw_step(int32_t n, double* params, double* m, double* v, const double* grad,
                    double lr, double beta1, double beta2, double eps, double weight_decay,

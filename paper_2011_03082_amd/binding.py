@@ -171,11 +171,11 @@ def adam_params(step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.
 
 
 def cvae_train_step(shape, master, adam_m, adam_v, adam, cond, target, n_rows, batch, sample_rows, seed, step,
-                    id_offset, workspace, loss=None, grad=None, stream=None):
+                    id_offset, workspace, loss=None, grad=None, stream=None, kl_weight=1.0):
     check(lib().cvae_train_step(C.byref(cvae_shape(shape)), _ptr(master), _ptr(adam_m), _ptr(adam_v),
                                 None if adam is None else C.byref(adam), _ptr(cond), _ptr(target), n_rows, batch,
-                                sample_rows, seed, step, id_offset, _ptr(workspace), workspace.numel(), _ptr(loss),
-                                _ptr(grad), _stream(stream)))
+                                sample_rows, seed, step, id_offset, kl_weight, _ptr(workspace), workspace.numel(),
+                                _ptr(loss), _ptr(grad), _stream(stream)))
 
 
 def cvae_packed_bytes():
@@ -219,6 +219,18 @@ def render_desc(method, sampler=_abi.SAMPLER_CVAE, packed=(None, None, None), ta
 
 
 IMAGE_FIELDS = ("sum", "comp", "sumsq", "events", "steps", "counters")
+
+
+def ms_build_sdf_grid(scene, res, grid, stream=None):
+    check(lib().ms_build_sdf_grid(C.byref(scene), res, _ptr(grid), _stream(stream)))
+
+
+def build_sdf_grid(prims, res, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), device="cuda"):
+    """FP16 conservative distance grid (int16 device tensor of binary16 bits)."""
+    prims = torch.as_tensor(prims, dtype=torch.float32).reshape(-1, 8).to(device).contiguous()
+    grid = torch.empty(res ** 3, dtype=torch.int16, device=device)
+    ms_build_sdf_grid(make_scene(prims, None, lo, hi), res, grid)
+    return grid
 
 
 def sphere_trace_render_workspace_size(cam, desc):

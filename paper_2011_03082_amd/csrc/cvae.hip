@@ -234,6 +234,7 @@ struct TrainArgs {
     uint64_t seed;
     int64_t step;
     uint64_t id_offset;
+    float kl_weight;      // weight of the KL term in the gradient
     float* partial;       // [blocks][n_params]
     double* loss_partial; // [blocks][2]
 };
@@ -409,9 +410,10 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             for (int i = 0; i < Lt; ++i) {
                 const float dz = L.work[0][i * kTile + lane];
                 const float sd = fast_exp(0.5f * lv_z[i]);
-                L.work[1][i * kTile + lane] = dz + mu_z[i] * inv_b;
+                L.work[1][i * kTile + lane] = dz + a.kl_weight * mu_z[i] * inv_b;
                 L.work[1][(Lt + i) * kTile + lane] =
-                    (0.5f * dz * eps[i] * sd + 0.5f * (fast_exp(lv_z[i]) - 1.0f) * inv_b) * clamp_mask(lvr_z[i]);
+                    (0.5f * dz * eps[i] * sd + a.kl_weight * 0.5f * (fast_exp(lv_z[i]) - 1.0f) * inv_b) *
+                    clamp_mask(lvr_z[i]);
             }
         }
         wave_sync();
@@ -585,14 +587,12 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
         uint32_t w0 = 0, w1 = 0;
         if (real) {
             if (precision == MS_PREC_FP8) {
-                // K = 32 operand: lane holds K = 8 kg .. 8 kg + 7; real K < 16
-                uint32_t bytes[8];
-                for (int q = 0; q < 8; ++q) {
-                    const int k = 8 * kg + q;
-                    bytes[q] = k < kTile ? fp8_e4m3_bits(layer[r * kTile + k] / scale) : 0u;
-                }
+                // K = 32 operand in the permuted order of decoder_tile_fp8:
+                // bytes 0..3 = columns 4 kg .. 4 kg + 3, bytes 4..7 = 0
+                uint32_t bytes[4];
+                for (int q = 0; q < 4; ++q) bytes[q] = fp8_e4m3_bits(layer[r * kTile + 4 * kg + q] / scale);
                 w0 = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | (bytes[3] << 24);
-                w1 = bytes[4] | (bytes[5] << 8) | (bytes[6] << 16) | (bytes[7] << 24);
+                w1 = 0u;
             } else {
                 const float* row = layer + r * kTile + 4 * kg;
                 w0 = (uint32_t)bf16_bits(row[0]) | ((uint32_t)bf16_bits(row[1]) << 16);
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
         for (int t = 0; t < n_tiles; ++t) {
             const int path = 16 * t + frag_row();
             const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-            const f32x4 o = decoder_tile(pm, to_bf16x4(xin));
+            const f32x4 o = decoder_tile_any(pm, xin);
             *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
         }
         wave_sync();
@@ -807,8 +807,8 @@ ms_status cvae_workspace_size(const ms_cvae_shape* shape, int32_t batch, size_t*
 ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev, float* adam_v_dev,
                           const ms_adam* adam, const float* cond_dev, const float* target_dev, int64_t n_rows,
                           int32_t batch, int32_t sample_rows, uint64_t seed, int64_t step, uint64_t id_offset,
-                          void* workspace_dev, size_t workspace_bytes, double* loss_dev, float* grad_dev,
-                          void* stream) {
+                          double kl_weight, void* workspace_dev, size_t workspace_bytes, double* loss_dev,
+                          float* grad_dev, void* stream) {
     using namespace msst;
     Shape s;
     ms_status st = check_shape(shape, &s);
@@ -818,6 +818,7 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
     MS_REQUIRE(n_rows > 0 && n_rows < ((int64_t)1 << 32), "cvae_train_step: n_rows must be in [1, 2^32)");
     MS_REQUIRE(sample_rows || n_rows >= batch, "cvae_train_step: n_rows < batch without row sampling");
     MS_REQUIRE(step >= 0 && step < ((int64_t)1 << 30), "cvae_train_step: step must be in [0, 2^30)");
+    MS_REQUIRE(kl_weight >= 0.0 && kl_weight <= 1e6, "cvae_train_step: kl_weight must be in [0, 1e6]");
     if (adam) {
         MS_REQUIRE(adam_m_dev && adam_v_dev, "cvae_train_step: AdamW moments are NULL");
         MS_REQUIRE(adam->step >= 1, "cvae_train_step: AdamW step must be >= 1");
@@ -845,6 +846,7 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
     ta.seed = seed;
     ta.step = step;
     ta.id_offset = id_offset;
+    ta.kl_weight = (float)kl_weight;
     ta.partial = reinterpret_cast<float*>(workspace_dev);
     ta.loss_partial = reinterpret_cast<double*>(reinterpret_cast<char*>(workspace_dev) +
                                                 align_up((size_t)nb * n_params * sizeof(float), 256));

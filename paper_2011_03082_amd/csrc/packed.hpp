@@ -3,6 +3,7 @@
 #pragma once
 
 #include "mfma.hpp"
+#include "msst.h"
 
 namespace msst {
 
@@ -27,6 +28,47 @@ __device__ __forceinline__ bf16x4 load_frag_bf16(const PackedModel* pm, int laye
     return __builtin_bit_cast(bf16x4, u);
 }
 
+// FP8 E4M3 products on v_mfma_f32_16x16x32_fp8_fp8.  The contraction index
+// is permuted so that no data moves between layers: lane group q (lanes
+// 16q .. 16q+15) feeds K slots 8q .. 8q+3 with the four D rows 4q .. 4q+3 it
+// already holds and zeros in K slots 8q+4 .. 8q+7; the packed weights use
+// the same K order (half of K = 32 is padding, as for any 16-wide layer).
+typedef long fp8x8;
+
+__device__ __forceinline__ f32x4 mfma_fp8(fp8x8 a, fp8x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ fp8x8 to_fp8x4_lo(f32x4 v) {
+    // v_cvt_pk_fp8_f32: two floats to OCP E4M3, round to nearest even;
+    // clamped to the largest finite E4M3 value first
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = __builtin_fminf(448.0f, __builtin_fmaxf(-448.0f, v[q]));
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+    return (fp8x8)(uint32_t)w;
+}
+
+__device__ __forceinline__ f32x4 decoder_tile_fp8(const PackedModel* pm, f32x4 x) {
+    const int nl = pm->n_linear;
+    const int k0 = frag_k0();
+    f32x4 acc;
+    for (int j = 0; j < nl; ++j) {
+        const uint2 u = *reinterpret_cast<const uint2*>(pm->frag[j][lane_id()]);
+        const fp8x8 a = (fp8x8)(((uint64_t)u.y << 32) | u.x);
+        acc = mfma_fp8(a, to_fp8x4_lo(x), f32x4{0, 0, 0, 0});
+        const float sc = pm->w_scale[j];
+        const float* b = pm->bias[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(acc[q], sc, b[k0 + q]);
+        if (j < nl - 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = softplus(acc[q]);
+        }
+    }
+    return acc;
+}
+
 // Runs the decoder MLP on one 16-path tile whose inputs (z, standardised
 // condition; feature-major B operand) are `x`.  Returns the output layer in
 // D layout: rows k0..k0+3 of path column frag_row().
@@ -47,4 +89,12 @@ __device__ __forceinline__ f32x4 decoder_tile(const PackedModel* pm, bf16x4 x) {
     return acc;
 }
 
+}  // namespace msst
+
+namespace msst {
+// Decoder on one tile in the model's packed precision (uniform branch).
+__device__ __forceinline__ f32x4 decoder_tile_any(const PackedModel* pm, f32x4 xin) {
+    if (pm->precision == MS_PREC_FP8) return decoder_tile_fp8(pm, xin);
+    return decoder_tile(pm, to_bf16x4(xin));
+}
 }  // namespace msst

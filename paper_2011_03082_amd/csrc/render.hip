@@ -214,6 +214,122 @@ __device__ __forceinline__ float nee(const RenderArgs& A, const Prims<NP>& P, V3
     return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) / dist2;
 }
 
+// ---------------------------------------------------------------- geometry policies
+
+// Few primitives (NP <= 4) in registers; the intervals of the current ray
+// are computed once per ray and kept in registers.
+template <int NP>
+struct Geo {
+    Prims<NP> P;
+    RayIv<NP> iv;
+    __device__ __forceinline__ void init(const RenderArgs& A, const float*) {
+        P.n = A.n_prims;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) P.p[i][k] = i < A.n_prims ? A.prims[i * 8 + k] : 0.0f;
+    }
+    __device__ __forceinline__ void set_ray(V3 o, V3 d) { ray_intervals(P, o, d, iv); }
+    __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
+    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const { return conservative_radius(A, P, p); }
+    __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
+    __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const { return nee(A, P, x, d); }
+};
+
+// Many primitives (up to kMaxManyPrims) staged in LDS; ray intervals are
+// recomputed on demand, the hits of one query kept in registers (8 slots).
+// A flight shorter than the conservative radius at its start cannot leave
+// the body, so it needs no exact boundary query.
+constexpr int kMaxManyPrims = 256;
+constexpr int kHitSlots = 8;
+
+struct GeoMany {
+    const float* prim;  // LDS [n][8]
+    int n;
+    __device__ __forceinline__ void init(const RenderArgs& A, const float* lds_prims) {
+        prim = lds_prims;
+        n = A.n_prims;
+    }
+    __device__ __forceinline__ void set_ray(V3, V3) {}
+    __device__ __forceinline__ bool piece(V3 o, V3 d, float t, float& s, float& e) const {
+        float ca[kHitSlots], cb[kHitSlots];
+        int m = 0;
+        bool overflow = false;
+        s = INFINITY;
+        for (int i = 0; i < n; ++i) {
+            float a, b;
+            if (prim_interval(prim + 8 * i, o, d, a, b) && b > t) {
+                s = __builtin_fminf(s, __builtin_fmaxf(a, t));
+#pragma unroll
+                for (int j = 0; j < kHitSlots; ++j)
+                    if (j == m) {
+                        ca[j] = a;
+                        cb[j] = b;
+                    }
+                if (m < kHitSlots) ++m;
+                else overflow = true;
+            }
+        }
+        if (s == INFINITY) return false;
+        e = s;
+        if (!overflow) {
+#pragma unroll
+            for (int pass = 0; pass < kHitSlots; ++pass)
+#pragma unroll
+                for (int j = 0; j < kHitSlots; ++j)
+                    if (j < m && ca[j] <= e && cb[j] > e) e = cb[j];
+        } else {
+            for (int pass = 0; pass < n; ++pass) {
+                bool grew = false;
+                for (int i = 0; i < n; ++i) {
+                    float a, b;
+                    if (prim_interval(prim + 8 * i, o, d, a, b) && a <= e && b > e) {
+                        e = b;
+                        grew = true;
+                    }
+                }
+                if (!grew) break;
+            }
+        }
+        return true;
+    }
+    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const {
+        if (A.grid) {
+            Prims<1> none;
+            none.n = 0;
+            return conservative_radius(A, none, p);
+        }
+        float sd = INFINITY;
+        for (int i = 0; i < n; ++i) sd = __builtin_fminf(sd, prim_sdf(prim + 8 * i, p));
+        return sd < 0.0f ? -0.999f * sd : 0.0f;
+    }
+    __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
+    __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
+        V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
+        const float dist2 = dot(wl, wl);
+        const float inv_dist = fast_rsq(dist2);
+        const float dist = dist2 * inv_dist;
+        wl = inv_dist * wl;
+        float acc = 0.0f, t = 0.0f;
+        for (int k = 0; k < n && t < dist; ++k) {
+            float ps, pe;
+            if (!piece(x, wl, t, ps, pe) || ps >= dist) break;
+            acc += __builtin_fminf(pe, dist) - ps;
+            t = pe;
+        }
+        return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) / dist2;
+    }
+};
+
+template <int NP>
+struct GeoSel {
+    typedef Geo<NP> type;
+};
+template <>
+struct GeoSel<0> {
+    typedef GeoMany type;
+};
+
 // ---------------------------------------------------------------- kernel
 
 __device__ __forceinline__ void neumaier_add(float& sum, float& comp, float v) {
@@ -263,7 +379,7 @@ __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L,
     for (int t = 0; t < n_tiles; ++t) {
         const int path = 16 * t + frag_row();
         const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-        const f32x4 o = decoder_tile(pm, to_bf16x4(xin));
+        const f32x4 o = decoder_tile_any(pm, xin);
         *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
     }
     wave_sync();
@@ -284,13 +400,14 @@ __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L,
 template <int MODE, int NP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
     __shared__ RenderLds lds_all[kRenderWaves];
+    __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
     RenderLds& L = lds_all[threadIdx.x >> 6];
-    Prims<NP> P;
-    P.n = A.n_prims;
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) P.p[i][k] = i < A.n_prims ? A.prims[i * 8 + k] : 0.0f;
+    if (NP == 0) {
+        for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
+        __syncthreads();
+    }
+    typename GeoSel<NP>::type G;
+    G.init(A, lds_prims);
 
     TicketPool pool;
     pool.reset();
@@ -305,7 +422,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     V3 o = v3(0, 0, 0), d = v3(0, 0, 1);
     float t = 0.0f, Lp = 0.0f, r_step = 0.0f;
     uint32_t c0 = 0, iters = 0, p_ev = 0, p_st = 0;
-    RayIv<NP> iv;
     uint32_t cnt_paths = 0, cnt_events = 0, cnt_steps = 0, cnt_trunc = 0;
 
     for (;;) {
@@ -342,7 +458,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
             o = v3(A.eye[0], A.eye[1], A.eye[2]);
             d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0], A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
                              A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
-            ray_intervals(P, o, d, iv);
+            G.set_ray(o, d);
             t = 0.0f;
             Lp = 0.0f;
             c0 = 0;
@@ -352,13 +468,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
             state = S_FLY;
         }
         if (state == S_FLY) {
-            float ps, pe;
-            if (!union_piece(iv, t, ps, pe)) {
+            // one Philox block per flight; the boundary query (the medium
+            // piece of the ray containing or following t) is skipped when the
+            // flight is shorter than the conservative radius at its start
+            const uint4 w = rng.block(c0++);
+            const float l = -flight_ln(u01(w.x)) * A.inv_sigma_t;
+            float ps = t, pe = INFINITY;
+            bool inside = l < G.flight_bound(A, fma3(t, d, o));
+            if (!inside && !G.piece(o, d, t, ps, pe)) {
                 path_end = true;
             } else {
                 t = __builtin_fmaxf(t, ps);
-                const uint4 w = rng.block(c0++);
-                const float l = -flight_ln(u01(w.x)) * A.inv_sigma_t;
                 if (t + l >= pe) {
                     t = pe;
                 } else {
@@ -370,7 +490,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                     } else {
                         bool plain = true;
                         if (MODE != kModePlain) {
-                            const float r = __builtin_fminf(conservative_radius(A, P, p), A.st_max * A.inv_sigma_t);
+                            const float r = __builtin_fminf(G.radius(A, p), A.st_max * A.inv_sigma_t);
                             if (A.sigma_t * r >= A.tau_min) {
                                 plain = false;
                                 if (MODE == kModeStExact) {
@@ -405,10 +525,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                                     if (!(u01(wa.x) <= fast_exp(N * A.ln_albedo))) {
                                         path_end = true;
                                     } else {
-                                        Lp += lambda_weight(A, N) * nee(A, P, Xk, Wk);
+                                        Lp += lambda_weight(A, N) * G.light(A, Xk, Wk);
                                         o = x;
                                         d = dir;
-                                        ray_intervals(P, o, d, iv);
+                                        G.set_ray(o, d);
                                         t = 0.0f;
                                     }
                                 } else {
@@ -420,14 +540,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         }
                         if (plain) {
                             ++p_ev;
-                            Lp += A.albedo * nee(A, P, p, d);
+                            Lp += A.albedo * G.light(A, p, d);
                             if (u24(w.w) > A.surv_thr) {
                                 path_end = true;
                             } else {
                                 const HgSample h = hg_sample(A.g, u01(w.y));
                                 d = scatter(d, h.mu, h.sin_t, u01(w.z));
                                 o = p;
-                                ray_intervals(P, o, d, iv);
+                                G.set_ray(o, d);
                                 t = 0.0f;
                             }
                         }
@@ -530,10 +650,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                     const V3 ww = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
                     const V3 Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
                     const V3 Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
-                    Lp += wgt * nee(A, P, Xw, Ww);
+                    Lp += wgt * G.light(A, Xw, Ww);
                     o = xw;
                     d = ww;
-                    ray_intervals(P, o, d, iv);
+                    G.set_ray(o, d);
                     t = 0.0f;
                     state = S_FLY;
                 }
@@ -614,7 +734,8 @@ __global__ void render_check_models(const RenderArgs A, unsigned long long* flag
     for (int m = 0; m < 3; ++m) {
         const PackedModel* pm = A.pm[m];
         ok &= pm->magic == (int32_t)kPackedMagic && pm->model == m && pm->latent == 4 && pm->p_in == want_in[m] &&
-              pm->p_out == want_out[m] && pm->precision == MS_PREC_BF16 && pm->n_linear == 3;
+              pm->p_out == want_out[m] && (pm->precision == MS_PREC_BF16 || pm->precision == MS_PREC_FP8) &&
+              pm->n_linear == 3;
     }
     *flag = ok ? 0ull : 1ull;
 }
@@ -630,6 +751,44 @@ __global__ void render_zero_kernel(unsigned long long* ticket, unsigned long lon
 // render kernel does no work, and the reduction poisons the image.
 __global__ void render_gate_kernel(const unsigned long long* flag, unsigned long long* ticket, int64_t n_units) {
     if (threadIdx.x == 0) ticket[0] = flag[0] ? (unsigned long long)n_units : 0ull;
+}
+
+// Conservative FP16 distance grid (the voxel-grid distance pre-process of
+// Sec. 3): the union distance min_i sdf_i at voxel centres lo + (i + 1/2) h,
+// evaluated in FP64 and rounded toward zero to binary16, so that
+// |stored| <= |exact| and the renderer's nearest-voxel radius
+// max(0, -stored - half diagonal) never exceeds the true interior distance.
+__device__ __forceinline__ double prim_sdf64(const float* pr, double px, double py, double pz) {
+    const double qx = px - pr[1], qy = py - pr[2], qz = pz - pr[3];
+    if (pr[0] == 0.0f) return sqrt(qx * qx + qy * qy + qz * qz) - (double)pr[4];
+    const double ex = fabs(qx) - pr[4], ey = fabs(qy) - pr[5], ez = fabs(qz) - pr[6];
+    const double ox = fmax(ex, 0.0), oy = fmax(ey, 0.0), oz = fmax(ez, 0.0);
+    return sqrt(ox * ox + oy * oy + oz * oz) + fmin(fmax(ex, fmax(ey, ez)), 0.0);
+}
+
+__device__ __forceinline__ uint16_t fp16_bits_rtz(double x) {
+    const uint16_t sign = x < 0.0 ? 0x8000u : 0u;
+    const double a = fabs(x);
+    if (a >= 65504.0) return (uint16_t)(sign | 0x7bffu);
+    if (a < 0x1p-24) return sign;
+    int e;
+    frexp(a, &e);
+    const int ex = e - 1;  // a in [2^ex, 2^(ex+1))
+    if (ex < -14) return (uint16_t)(sign | (uint32_t)floor(a * 0x1p24));
+    const uint32_t mant = (uint32_t)floor((ldexp(a, -ex) - 1.0) * 1024.0);
+    return (uint16_t)(sign | ((uint32_t)(ex + 15) << 10) | mant);
+}
+
+__global__ void sdf_grid_kernel(const float* prims, int n_prims, int res, double lox, double loy, double loz,
+                                double hx, double hy, double hz, uint16_t* out) {
+    const int64_t total = (int64_t)res * res * res;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < total; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = v % res, j = (v / res) % res, k = v / ((int64_t)res * res);
+        const double px = lox + (i + 0.5) * hx, py = loy + (j + 0.5) * hy, pz = loz + (k + 0.5) * hz;
+        double sd = INFINITY;
+        for (int q = 0; q < n_prims; ++q) sd = fmin(sd, prim_sdf64(prims + 8 * q, px, py, pz));
+        out[v] = fp16_bits_rtz(sd);
+    }
 }
 
 static int default_chunk(int spp) {
@@ -660,8 +819,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                               void* workspace_dev, size_t workspace_bytes, void* stream) {
     using namespace msst;
     MS_REQUIRE(scene && cam && light && medium && desc && out, "sphere_trace_render: NULL descriptor");
-    MS_REQUIRE(scene->prims != nullptr && scene->n_prims >= 1 && scene->n_prims <= kMaxPrims,
-               "sphere_trace_render: need 1..4 primitives");
+    MS_REQUIRE(scene->prims != nullptr && scene->n_prims >= 1 && scene->n_prims <= kMaxManyPrims,
+               "sphere_trace_render: need 1..256 primitives");
     MS_REQUIRE(cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < ((int64_t)1 << 31),
                "sphere_trace_render: image size must be positive and below 2^31 pixels");
     MS_REQUIRE(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f, "sphere_trace_render: vfov must be in (0, 180)");
@@ -782,10 +941,14 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
         if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 2);
         else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 2);
         else MS_RENDER_LAUNCH(kModeStCvae, 2);
-    } else {
+    } else if (A.n_prims <= 4) {
         if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 4);
         else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 4);
         else MS_RENDER_LAUNCH(kModeStCvae, 4);
+    } else {
+        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 0);
+        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 0);
+        else MS_RENDER_LAUNCH(kModeStCvae, 0);
     }
 #undef MS_RENDER_LAUNCH
     MS_LAUNCHED();
@@ -800,3 +963,26 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
 }
 
 }  // extern "C"
+
+extern "C" ms_status ms_build_sdf_grid(const ms_scene* scene, int32_t res, uint16_t* grid_dev, void* stream) {
+    using namespace msst;
+    MS_REQUIRE(scene && scene->prims && grid_dev, "ms_build_sdf_grid: NULL argument");
+    MS_REQUIRE(scene->n_prims >= 1 && scene->n_prims <= kMaxManyPrims, "ms_build_sdf_grid: need 1..256 primitives");
+    MS_REQUIRE(res >= 1 && res <= 4096, "ms_build_sdf_grid: res must be in [1, 4096]");
+    MS_REQUIRE(scene->hi[0] > scene->lo[0] && scene->hi[1] > scene->lo[1] && scene->hi[2] > scene->lo[2],
+               "ms_build_sdf_grid: empty bounds");
+    int cus;
+    ms_status st = device_cu_count(&cus);
+    if (st != MS_OK) return st;
+    const int64_t total = (int64_t)res * res * res;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > (int64_t)cus * 16) blocks = (int64_t)cus * 16;
+    const double h[3] = {((double)scene->hi[0] - scene->lo[0]) / res, ((double)scene->hi[1] - scene->lo[1]) / res,
+                         ((double)scene->hi[2] - scene->lo[2]) / res};
+    hipLaunchKernelGGL(sdf_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, scene->prims,
+                       scene->n_prims, res, (double)scene->lo[0], (double)scene->lo[1], (double)scene->lo[2], h[0], h[1],
+                       h[2], grid_dev);
+    MS_LAUNCHED();
+    clear_error();
+    return MS_OK;
+}

@@ -73,7 +73,7 @@ def test_select_rows_is_exact(msst):
     assert rows.size == 0
 
 
-def grad_case(msst, oracle, model, B, sample_rows=0, n_rows=None):
+def grad_case(msst, oracle, model, B, sample_rows=0, n_rows=None, kl_weight=1.0):
     shape = W.SHAPE_LIST[model]
     master64 = oracle.cvae_init(shape, seed=31 + model).astype(np.float32).astype(np.float64)
     rng = np.random.default_rng(model)
@@ -87,7 +87,7 @@ def grad_case(msst, oracle, model, B, sample_rows=0, n_rows=None):
     loss = torch.zeros(3, dtype=torch.float64, device="cuda")
     ws = torch.empty(msst.cvae_workspace_size(model, B), dtype=torch.uint8, device="cuda")
     msst.cvae_train_step(model, master, None, None, None, dev(cond), dev(target), n_rows, B, sample_rows, seed, step,
-                         0, ws, loss, grad)
+                         0, ws, loss, grad, kl_weight=kl_weight)
     torch.cuda.synchronize()
     if sample_rows:
         words = np.array([oracle.philox_blocks(seed, oracle.TAG_CVAE_BATCH, b, step, 1)[0, 0] for b in range(B)],
@@ -96,7 +96,7 @@ def grad_case(msst, oracle, model, B, sample_rows=0, n_rows=None):
     else:
         rows = np.arange(B)
     l64, kl64, nll64, g64 = oracle.cvae_loss_grad(shape, master64, cond[rows].astype(np.float64),
-                                                  target[rows].astype(np.float64), seed, step)
+                                                  target[rows].astype(np.float64), seed, step, kl_weight=kl_weight)
     return grad.cpu().numpy().astype(np.float64), g64, loss.cpu().numpy(), (l64, kl64, nll64)
 
 
@@ -112,6 +112,13 @@ def test_gradient_parity_bf16(msst, oracle, model):
     assert rel < 10 * BF16_U and cos > 0.999
     np.testing.assert_allclose(loss, ref, rtol=10 * BF16_U, atol=1e-3)
     assert abs(loss[0] - loss[1] - loss[2]) < 1e-9 * abs(loss[0])
+
+
+def test_gradient_parity_kl_weight(msst, oracle):
+    announce("cvae grad kl weight")
+    g, g64, loss, ref = grad_case(msst, oracle, 1, B=128, kl_weight=0.3)
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    assert rel < 10 * BF16_U
 
 
 def test_gradient_parity_sampled_rows_and_ragged(msst, oracle):
@@ -218,3 +225,31 @@ def test_sample_matches_bf16_emulating_oracle(msst, oracle, model):
     err64 = np.abs(got - ref64).max(axis=1) / scale.max()
     print(f"model {model}: error against the FP64 decoder median {np.median(err64):.2e}, max {err64.max():.2e}")
     assert np.median(err64) < 0.05
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_sample_fp8_matches_fp8_emulating_oracle(msst, oracle, model):
+    """FP8 E4M3 decoders (per-layer weight scale max|W|/448, FP32 accumulation)
+    against the oracle rounding weights and layer inputs to E4M3 the same way.
+    E4M3 keeps 4 significant bits (unit roundoff 2^-4), so rounding flips from
+    FP32-vs-FP64 differences are rare but each moves an activation by ~6 %."""
+    announce(f"cvae sample fp8 model={model}")
+    shape = W.SHAPE_LIST[model]
+    master64 = oracle.cvae_init(shape, seed=70 + model).astype(np.float32).astype(np.float64)
+    stats = W.random_stats(model, seed=10 + model)
+    n = 3000 + 21
+    cond = W.random_conditions(model, n, seed=20 + model).astype(np.float32)
+    packed = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+    msst.cvae_pack(model, dev(master64), dev(stats, torch.float64), 2, packed)
+    out = torch.empty((n, shape["p_out"]), dtype=torch.float32, device="cuda")
+    msst.cvae_sample(packed, dev(cond), n, 5, 0, out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 5, 0, precision=oracle.PREC_FP8)
+    scale = stats[48:48 + shape["p_out"]].max()
+    err = np.abs(got - ref).max(axis=1) / scale
+    print(f"model {model}: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}, max {err.max():.2e}")
+    assert np.quantile(err, 0.99) < 1e-3
+    assert err.max() < 0.2
+    ref16 = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 5, 0, precision=oracle.PREC_BF16)
+    e16 = np.abs(got - ref16).max(axis=1) / scale
+    print(f"model {model}: FP8 against the BF16 decoder: median {np.median(e16):.2e}")

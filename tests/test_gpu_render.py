@@ -54,12 +54,12 @@ def models_for_test(oracle):
     return models, packed_src
 
 
-def pack_all(msst, packed_src):
+def pack_all(msst, packed_src, precision=1):
     out = []
     for m, (master, stats) in enumerate(packed_src):
         p = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
         msst.cvae_pack(m, torch.as_tensor(master, dtype=torch.float32).cuda(),
-                       torch.as_tensor(stats, dtype=torch.float64).cuda(), 1, p)
+                       torch.as_tensor(stats, dtype=torch.float64).cuda(), precision, p)
         out.append(p)
     return out
 
@@ -103,14 +103,16 @@ def test_exact_walk_sphere_tracing_path_by_path(msst, oracle):
     assert o["steps"].sum() > 100
 
 
-def test_learned_sphere_tracing_path_by_path(msst, oracle):
-    announce("render ST CVAE parity")
+@pytest.mark.parametrize("precision", [1, 2])
+def test_learned_sphere_tracing_path_by_path(msst, oracle, precision):
+    announce(f"render ST CVAE parity precision={precision}")
     prims, cam, light, med = c4_inputs(20.0, 40)
     models, src = models_for_test(oracle)
-    packed = pack_all(msst, src)
+    packed = pack_all(msst, src, precision)
     g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=5)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
-                      precision=oracle.PREC_BF16, models=models, spp=1, seed=5)
+                      precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8, models=models, spp=1,
+                      seed=5)
     frac, _ = compare_paths(g, o, rel=2e-3)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
     assert o["steps"].sum() > 100
@@ -228,3 +230,68 @@ def test_image_stats_fp64(msst):
     np.testing.assert_allclose(got[1], np.sqrt(np.mean((m - ref) ** 2)), rtol=1e-12)
     np.testing.assert_allclose(got[2], np.mean(q.astype(np.float64) / spp - m * m), rtol=1e-10)
     np.testing.assert_allclose(got[3], ref.astype(np.float64).mean(), rtol=1e-12)
+
+
+# ---------------------------------------------------------------- C5: 64 spheres + FP16 grid
+def c5_inputs(w):
+    prims = W.scene_c5(seed=0)
+    return prims, f32_camera(W.camera_c5(w, w)), f32_light(W.light_c5()), f32_medium(W.medium_c5())
+
+
+def test_sdf_grid_matches_oracle(msst, oracle):
+    announce("sdf grid build")
+    prims = W.scene_c5(seed=0)
+    res = 64
+    g = msst.build_sdf_grid(prims, res).cpu().numpy().view(np.uint16)
+    o = oracle.Scene(prims).build_grid(res)
+    gv = g.view(np.float16).astype(np.float64)
+    ov = o.view(np.float16).astype(np.float64)
+    # both round the FP64 union distance toward zero; FP64 evaluation order
+    # may differ by an ulp, which moves at most one binary16 step
+    diff = np.abs(g.astype(np.int64) - o.astype(np.int64))
+    assert (diff == 0).mean() > 0.999 and diff.max() <= 1
+    assert np.all(np.sign(gv) * np.sign(ov) >= 0)
+
+
+@pytest.mark.parametrize("method,sampler", [(PLAIN, CVAE), (ST, EXACT)])
+def test_c5_path_by_path(msst, oracle, method, sampler):
+    announce(f"render C5 parity method={method} sampler={sampler}")
+    prims, cam, light, med = c5_inputs(40)
+    res = 128
+    grid_g = msst.build_sdf_grid(prims, res)
+    grid_o = oracle.Scene(prims).build_grid(res)
+    r = msst.Renderer(prims, cam, light, grid=grid_g)
+    out = r.render(med, method=method, sampler=sampler, spp=1, seed=21)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med,
+                      method=oracle.METHOD_PLAIN_NEE if method == PLAIN else oracle.METHOD_ST,
+                      sampler=oracle.SAMPLER_EXACT_WALK, spp=1, seed=21)
+    frac, _ = compare_paths(g, o)
+    print(f"diverged {frac:.2e}; lit {(o['sum'] > 0).mean():.2f}, events {o['events'].sum()}, steps {o['steps'].sum()}")
+    assert (o["sum"] > 0).mean() > 0.1
+    assert frac < 1e-2
+    if method == ST:
+        assert o["steps"].sum() > 50
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_c5_learned_path_by_path(msst, oracle, precision):
+    announce(f"render C5 ST CVAE parity precision={precision}")
+    prims, cam, light, med = c5_inputs(32)
+    res = 128
+    grid_g = msst.build_sdf_grid(prims, res)
+    grid_o = oracle.Scene(prims).build_grid(res)
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src, precision)
+    r = msst.Renderer(prims, cam, light, grid=grid_g)
+    out = r.render(med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=22)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med, method=oracle.METHOD_ST,
+                      sampler=oracle.SAMPLER_CVAE, precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8,
+                      models=models, spp=1, seed=22)
+    frac, _ = compare_paths(g, o, rel=2e-3)
+    print(f"diverged {frac:.2e}; steps {o['steps'].sum()}")
+    assert o["steps"].sum() > 50
+    assert frac < 0.05
