@@ -290,7 +290,16 @@ typedef struct {
     uint32_t max_events;     /* per path; 0 = 2^20 */
     int32_t blocks_per_cu;   /* launch shape; 0 = default */
     int32_t cvae_batch_min;  /* waiting lanes that trigger a decoder pass; 0 = default */
+    int32_t nee_samples;     /* representative events per learned step, 1..16 (0 = 1) */
+    int32_t flags;           /* MS_RENDER_NEE_BEFORE_ABSORPTION */
 } ms_render_desc;
+
+/* Direct light of a learned step estimated before its absorption test, with
+ * weight sum_{i<=N} albedo^i, for every step (the paper's order rejects
+ * first and weights survivors by that sum / albedo^N); both are unbiased for
+ * sum_i albedo^i f_i.  K = nee_samples representative events average K
+ * independent EventGen samples (each its own first-event test). */
+enum { MS_RENDER_NEE_BEFORE_ABSORPTION = 1 };
 
 typedef struct {
     float* sum;          /* [width * height] sum of path radiance */

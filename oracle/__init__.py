@@ -23,6 +23,7 @@ EVENT_ALBEDO_POWER, EVENT_UNIFORM = 0, 1
 PREC_FP64, PREC_BF16, PREC_FP8 = 0, 1, 2
 METHOD_PLAIN_NEE, METHOD_ST = 1, 2
 SAMPLER_CVAE, SAMPLER_EXACT_WALK = 0, 1
+NEE_BEFORE_ABSORPTION = 1  # render flag: CVAE steps add direct light before the absorption test
 LAYER_FLOATS = 16 * 16 + 16
 
 
@@ -75,7 +76,7 @@ class _RenderDesc(C.Structure):
                 ("act_scales", C.c_void_p * 3), ("tau_min", C.c_double), ("st_max", C.c_double),
                 ("spp", C.c_int32), ("seed", C.c_uint64), ("sample_offset", C.c_uint64),
                 ("max_events", C.c_uint32), ("pixels", C.c_void_p), ("n_pixels", C.c_int64),
-                ("n_threads", C.c_int32)]
+                ("n_threads", C.c_int32), ("nee_samples", C.c_int32), ("flags", C.c_int32)]
 
 
 class _ImageOut(C.Structure):
@@ -323,7 +324,7 @@ class Scene:
 
 def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLER_CVAE,
            precision=PREC_FP64, models=None, tau_min=0.1, st_max=200.0, spp=1, seed=0,
-           sample_offset=0, max_events=1 << 20, pixels=None, n_threads=None):
+           sample_offset=0, max_events=1 << 20, pixels=None, n_threads=None, nee_samples=1, flags=0):
     """Renders (a pixel subset of) an image; returns per-pixel sums over spp.
 
     camera: dict(eye, look_at, up, vfov_deg, width, height); light: dict(pos,
@@ -364,6 +365,7 @@ def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLE
         rd.n_pixels = px.size
         npx = px.size
     rd.n_threads = n_threads if n_threads else default_threads()
+    rd.nee_samples, rd.flags = nee_samples, flags
     res = {k: np.zeros(npx) for k in ("sum", "sumsq", "events", "steps")}
     img = _ImageOut(*[_p(res[k]) for k in ("sum", "sumsq", "events", "steps")])
     lib().or_render(C.byref(scene.c), C.byref(cam), C.byref(lt), C.byref(md), C.byref(rd),

@@ -172,7 +172,14 @@ typedef struct {
     const int32_t* pixels; /* optional subset of pixel indices */
     int64_t n_pixels;      /* number of entries in pixels (or 0 = all) */
     int32_t n_threads;
+    int32_t nee_samples;   /* representative events per CVAE step (0 = 1), at most 16 */
+    int32_t flags;         /* OR_NEE_BEFORE_ABSORPTION */
 } or_render_desc;
+
+/* CVAE steps estimate their direct light before the absorption test, with
+ * weight sum_{i<=N} albedo^i, for every step (default: survivors only, with
+ * that sum divided by albedo^N). */
+enum { OR_NEE_BEFORE_ABSORPTION = 1 };
 
 typedef struct {
     double* sum;     /* per listed pixel */

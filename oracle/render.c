@@ -243,17 +243,35 @@ static double or_lambda_weight(double phi, double N) {
     return phi * expm1(-N * log(phi)) / (1.0 - phi);
 }
 
+#define OR_MAX_NEE 16
+
 typedef struct {
-    double x[3], w[3];  /* exit position and direction (world) */
-    double X[3], W[3];  /* representative event (world) */
+    double x[3], w[3];               /* exit position and direction (world) */
+    double X[OR_MAX_NEE][3];         /* representative events (world) */
+    double W[OR_MAX_NEE][3];
+    int n_rep;                       /* events whose direct light is added */
+    double nee_w;                    /* weight of each of them */
     double N;
     int survived;
 } or_step;
 
 /* Learned step in the sphere of radius r around p entered along d. */
+/* Learned sphere step (Sec. 3.2 with the models of Sec. 4): LengthGen gives
+ * N, the chain is absorbed with probability 1 - albedo^N, PathGen gives the
+ * exit, and the direct light at K representative events is averaged.  Each
+ * representative event is the first one (the centre, entered along w_in) with
+ * probability albedo / Lambda^(N) (Sec. 4.3), taken exactly; EventGen samples
+ * the others.  A single event (N = 1) is one HG scatter at the centre
+ * (Sec. 3.1), sampled exactly instead of asking PathGen for a point mass.
+ * Random numbers are drawn in a fixed order: LengthGen normals; one block
+ * (absorption, psi, HG, first-event test of sample 0); PathGen normals; then
+ * per sample k: a block for its first-event test (k > 0) and EventGen
+ * normals. */
 static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t id, uint32_t* c0,
                          const double p[3], const double d[3], double r, or_step* out) {
     double str = md->sigma_t * r, lst = log(str), g = md->g, phi = md->albedo;
+    int K = rd->nee_samples > 0 ? rd->nee_samples : 1;
+    int before = (rd->flags & OR_NEE_BEFORE_ABSORPTION) != 0;
     double nrm[16], y[8];
     /* LengthGen */
     double c_len[2] = {lst, g};
@@ -266,19 +284,17 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
     double u[4];
     or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, u);
     /* absorption along the bypassed chain: survive with probability albedo^N */
-    if (!(u[0] <= exp(N * log(phi)))) {
-        out->survived = 0;
-        return;
-    }
-    out->survived = 1;
+    double phiN = exp(N * log(phi));
+    out->survived = u[0] <= phiN;
+    int lit = before ? 1 : out->survived;
+    out->n_rep = lit ? K : 0;
+    /* Lambda^(N) = sum_{i=1..N} albedo^i; survivors carry Lambda / albedo^N */
+    double lam = phi >= 1.0 ? N : phi * -expm1(N * log(phi)) / (1.0 - phi);
+    out->nee_w = (before ? lam : or_lambda_weight(phi, N)) / K;
+    if (!lit) return;
     double psi = 2.0 * OR_PI * u[1];
     double ct, al = 0.0, be = 0.0, ga = 1.0;
-    double X[3] = {0.0, 0.0, 0.0}, W[3] = {0.0, 0.0, 1.0};
     if (N < 2.0) {
-        /* A single event at the centre: the exit is one HG scatter of the
-         * incoming direction (Sec. 3.1), which is sampled exactly instead of
-         * asking PathGen for a point mass (alpha = beta = 0), and the
-         * representative event is the centre itself. */
         ct = or_hg_sample(g, u[2]);
     } else {
         /* PathGen */
@@ -293,11 +309,20 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
         al /= nl;
         be /= nl;
         ga /= nl;
-        /* The representative event is the first one (the centre, entered
-         * along w_in) with probability albedo / Lambda^(N) (Sec. 4.3); that
-         * case is taken exactly and EventGen samples the others. */
-        double p_first = phi >= 1.0 ? 1.0 / N : (1.0 - phi) / (-expm1(N * log(phi)));
-        if (!(u[3] <= p_first)) {
+    }
+    double e1[3], e2[3];
+    or_onb(d, e1, e2);
+    double cp = cos(psi), sp = sin(psi);
+    double p_first = phi >= 1.0 ? 1.0 / N : (1.0 - phi) / (-expm1(N * log(phi)));
+    for (int k = 0; k < K; ++k) {
+        double uf = u[3];
+        if (k > 0) {
+            double v[4];
+            or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, v);
+            uf = v[0];
+        }
+        double X[3] = {0.0, 0.0, 0.0}, W[3] = {0.0, 0.0, 1.0};
+        if (N >= 2.0 && !(uf <= p_first)) {
             double c_ev[7] = {lst, g, phi, ct, al, be, log(N)};
             or_draw_normals(rd, id, c0, rd->shapes[2].latent + rd->shapes[2].p_out, nrm);
             or_model_sample(rd, 2, c_ev, nrm, y);
@@ -317,25 +342,27 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
                 W[2] = 1.0;
             }
         }
+        /* (X, W) rotated by psi about w_in, then into R = [e1 e2 d] */
+        double Xt[3] = {cp * X[0] - sp * X[1], sp * X[0] + cp * X[1], X[2]};
+        double Wt[3] = {cp * W[0] - sp * W[1], sp * W[0] + cp * W[1], W[2]};
+        for (int i = 0; i < 3; ++i) {
+            out->X[k][i] = p[i] + r * (Xt[0] * e1[i] + Xt[1] * e2[i] + Xt[2] * d[i]);
+            out->W[k][i] = Wt[0] * e1[i] + Wt[1] * e2[i] + Wt[2] * d[i];
+        }
+        or_normalize(out->W[k]);
     }
+    if (!out->survived) return;
     /* Eq. (transform): x = p + r R R_psi x~ with R = [e1 e2 d], plus the
-     * exit-frame direction of Sec. 4.1 and (X, W) rotated the same way. */
-    double e1[3], e2[3];
-    or_onb(d, e1, e2);
-    double cp = cos(psi), sp = sin(psi), st = sqrt(fmax(0.0, 1.0 - ct * ct));
+     * exit-frame direction of Sec. 4.1. */
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
     double xt[3] = {st * cp, st * sp, ct};
     double w0[3] = {be * ct + ga * st, al, -be * st + ga * ct};
     double wt[3] = {cp * w0[0] - sp * w0[1], sp * w0[0] + cp * w0[1], w0[2]};
-    double Xt[3] = {cp * X[0] - sp * X[1], sp * X[0] + cp * X[1], X[2]};
-    double Wt[3] = {cp * W[0] - sp * W[1], sp * W[0] + cp * W[1], W[2]};
     for (int i = 0; i < 3; ++i) {
         out->x[i] = p[i] + r * (xt[0] * e1[i] + xt[1] * e2[i] + xt[2] * d[i]);
         out->w[i] = wt[0] * e1[i] + wt[1] * e2[i] + wt[2] * d[i];
-        out->X[i] = p[i] + r * (Xt[0] * e1[i] + Xt[1] * e2[i] + Xt[2] * d[i]);
-        out->W[i] = Wt[0] * e1[i] + Wt[1] * e2[i] + Wt[2] * d[i];
     }
     or_normalize(out->w);
-    or_normalize(out->W);
 }
 
 /* Reference sphere step: the actual random walk inside the sphere (the
@@ -352,8 +379,8 @@ static void or_exact_step(const or_render_desc* rd, const or_medium* md, uint64_
         or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, u);
         resv = (nev == 1) ? 1.0 : 1.0 + resv / phi;
         if (u[3] * resv <= 1.0) {
-            memcpy(out->X, x, sizeof out->X);
-            memcpy(out->W, dir, sizeof out->W);
+            memcpy(out->X[0], x, sizeof out->X[0]);
+            memcpy(out->W[0], dir, sizeof out->W[0]);
         }
         double mu = or_hg_sample(md->g, u[1]);
         or_scatter_dir(dir, mu, 2.0 * OR_PI * u[2]);
@@ -373,6 +400,8 @@ static void or_exact_step(const or_render_desc* rd, const or_medium* md, uint64_
     double u[4];
     or_uniform4(rd->seed, OR_TAG_RENDER_PATH, id, (*c0)++, u);
     out->survived = u[0] <= exp(out->N * log(phi));
+    out->n_rep = out->survived;
+    out->nee_w = or_lambda_weight(phi, out->N);
 }
 
 /* ---------------- path ---------------- */
@@ -448,8 +477,8 @@ static or_path_result or_trace_path(const or_scene* sc, const or_camera* cam, co
                 else
                     or_cvae_step(rd, md, id, &c0, p, d, r, &st);
                 res.steps += 1.0;
+                for (int k = 0; k < st.n_rep; ++k) res.value += st.nee_w * or_nee(sc, lt, md, st.X[k], st.W[k]);
                 if (!st.survived) break;
-                res.value += or_lambda_weight(phi, st.N) * or_nee(sc, lt, md, st.X, st.W);
                 memcpy(o, st.x, sizeof o);
                 memcpy(d, st.w, sizeof d);
                 m = or_ray_intervals(sc, o, d, t0, t1, OR_MAX_IV);

@@ -48,6 +48,8 @@ struct RenderArgs {
     uint64_t seed, sample_offset;
     uint32_t max_events;
     int batch_min;
+    int nee_samples;
+    int flags;
     float* part_sum;
     float* part_comp;
     float* part_sq;
@@ -588,13 +590,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                     if (!alive) path_end = true;
                 }
                 // N = 1: a single HG scatter at the centre, sampled exactly;
-                // N >= 2: PathGen, then the representative event is the centre
-                // with probability albedo / Lambda^(N), else EventGen.
-                const bool use_path = alive && N >= 2.0f;
+                // N >= 2: PathGen, then each representative event is the centre
+                // with probability albedo / Lambda^(N), else EventGen.  With
+                // NEE before absorption the direct light of the step is
+                // estimated for every step (weight Lambda) and the absorption
+                // only ends the path; otherwise only surviving steps add it
+                // (weight Lambda / albedo^N, the order of Sec. 3.2).
+                const bool before = (A.flags & MS_RENDER_NEE_BEFORE_ABSORPTION) != 0;
+                const bool lit = before ? mine : alive;
+                const bool use_path = lit && N >= 2.0f;
                 const float wgt = lambda_weight(A, N);
-                const bool use_event = use_path && !(u_first * wgt * phiN <= A.albedo);
+                const float w_nee = (before ? wgt * phiN : wgt) / (float)A.nee_samples;
                 float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
-                if (alive && !use_path) ct = hg_sample(A.g, u_hg).mu;
+                if (lit && !use_path) ct = hg_sample(A.g, u_hg).mu;
                 const uint64_t pmask = ballot(use_path);
                 const float lnN = fast_ln(N);
                 if (pmask) {
@@ -616,43 +624,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         ga *= inl;
                     }
                 }
-                V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
-                const uint64_t emask = ballot(use_event);
-                if (emask) {
-                    const int slot = rank_in(emask);
-                    // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
-                    if (use_event) {
-                        const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-                        stage_input<4, 6, 7>(A.pm[2], L, slot, rng, c0, c7);
+                V3 e1 = v3(1, 0, 0), e2 = v3(0, 1, 0);
+                float cp = 1.0f, sp = 0.0f;
+                if (lit) {
+                    onb(d, e1, e2);
+                    cp = cos_rev(psi);
+                    sp = sin_rev(psi);
+                }
+                for (int k = 0; k < A.nee_samples; ++k) {
+                    float uf = u_first;
+                    if (k > 0 && lit) uf = u01(rng.block(c0++).x);
+                    const bool use_event = use_path && !(uf * wgt * phiN <= A.albedo);
+                    V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
+                    const uint64_t emask = ballot(use_event);
+                    if (emask) {
+                        const int slot = rank_in(emask);
+                        // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
+                        if (use_event) {
+                            const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
+                            stage_input<4, 6, 7>(A.pm[2], L, slot, rng, c0, c7);
+                        }
+                        decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
+                        if (use_event) {
+                            X = v3(y[0], y[1], y[2]);
+                            W = v3(y[3], y[4], y[5]);
+                            const float xl2 = dot(X, X);
+                            if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
+                            const float wl2 = dot(W, W);
+                            W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
+                        }
                     }
-                    decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
-                    if (use_event) {
-                        X = v3(y[0], y[1], y[2]);
-                        W = v3(y[3], y[4], y[5]);
-                        const float xl2 = dot(X, X);
-                        if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
-                        const float wl2 = dot(W, W);
-                        W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
+                    if (lit) {
+                        // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
+                        const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
+                        const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
+                        const V3 Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
+                        const V3 Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
+                        Lp += w_nee * G.light(A, Xw, Ww);
                     }
                 }
                 if (alive) {
                     // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
-                    V3 e1, e2;
-                    onb(d, e1, e2);
-                    const float cp = cos_rev(psi), sp = sin_rev(psi);
                     const float st = __builtin_sqrtf(__builtin_fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
                     const V3 xt = v3(st * cp, st * sp, ct);
                     const V3 w0 = v3(be * ct + ga * st, al, -be * st + ga * ct);
                     const V3 wt = v3(cp * w0.x - sp * w0.y, sp * w0.x + cp * w0.y, w0.z);
-                    const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
-                    const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
-                    const V3 xw = o + r_step * (xt.x * e1 + xt.y * e2 + xt.z * d);
-                    const V3 ww = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
-                    const V3 Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
-                    const V3 Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
-                    Lp += wgt * G.light(A, Xw, Ww);
-                    o = xw;
-                    d = ww;
+                    o = o + r_step * (xt.x * e1 + xt.y * e2 + xt.z * d);
+                    d = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
                     G.set_ray(o, d);
                     t = 0.0f;
                     state = S_FLY;
@@ -839,6 +857,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                    desc->cvae_batch_min <= 64,
                "sphere_trace_render: invalid launch parameters");
     MS_REQUIRE(desc->tau_min >= 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min >= 0, st_max > 0");
+    MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
+    MS_REQUIRE((desc->flags & ~MS_RENDER_NEE_BEFORE_ABSORPTION) == 0, "sphere_trace_render: unknown flags");
     MS_REQUIRE(out->sum && out->sumsq, "sphere_trace_render: sum and sumsq images are required");
     MS_REQUIRE(scene->sdf_fp16 == nullptr || (scene->res > 0 && scene->res <= 4096 && scene->hi[0] > scene->lo[0] &&
                                              scene->hi[1] > scene->lo[1] && scene->hi[2] > scene->lo[2]),
@@ -906,6 +926,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.sample_offset = desc->sample_offset;
     A.max_events = desc->max_events ? desc->max_events : (1u << 20);
     A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 32;
+    A.nee_samples = desc->nee_samples ? desc->nee_samples : 1;
+    A.flags = desc->flags;
     char* ws = reinterpret_cast<char*>(workspace_dev);
     A.ticket = reinterpret_cast<unsigned long long*>(ws);
     unsigned long long* flag = A.ticket + 1;

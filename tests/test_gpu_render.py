@@ -119,6 +119,26 @@ def test_learned_sphere_tracing_path_by_path(msst, oracle, precision):
     assert frac < 0.03
 
 
+@pytest.mark.parametrize("nee_samples,flags", [(2, 0), (3, 1)])
+def test_learned_steps_with_several_events_path_by_path(msst, oracle, nee_samples, flags):
+    """K representative events per learned step, optionally lit before the
+    absorption test: same draws, same per-path values as the oracle."""
+    announce(f"render ST CVAE parity K={nee_samples} flags={flags}")
+    prims, cam, light, med = c4_inputs(20.0, 40)
+    med["albedo"] = float(np.float32(0.97))
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src, 1)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=15,
+                   nee_samples=nee_samples, flags=flags)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      precision=oracle.PREC_BF16, models=models, spp=1, seed=15, nee_samples=nee_samples,
+                      flags=flags)
+    frac, _ = compare_paths(g, o, rel=2e-3)
+    print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
+    assert o["steps"].sum() > 100
+    assert frac < 0.03
+
+
 def test_tau_above_all_radii_is_plain(msst):
     announce("render ST with tau_min huge")
     prims, cam, light, med = c4_inputs(10.0, 32)

@@ -186,3 +186,34 @@ def test_exact_walk_sphere_steps_match_plain_path_tracing(oracle, c4, sigma_t):
     lit = (va + vb) > 0
     assert abs(z[lit].mean()) < 5 / np.sqrt(lit.sum())
     assert 0.7 < z[lit].std() < 1.3
+
+
+def test_learned_step_estimators_share_their_expectation(oracle, c4):
+    """Averaging K representative events, or adding the direct light of every
+    learned step before its absorption test with weight sum_i albedo^i instead
+    of survivors only with that sum over albedo^N, leaves the expectation of
+    the sphere-traced estimator unchanged (Sec. 3.2, Sec. 4.3); the models are
+    untrained but fixed, so all four variants estimate the same quantity."""
+    cam, light, _ = small_c4(40.0, 12)
+    med = dict(sigma_t=40.0, g=0.8, albedo=0.95)
+    models = [dict(shape=W.SHAPE_LIST[m], params=oracle.cvae_init(W.SHAPE_LIST[m], seed=70 + m),
+                   stats=W.render_test_stats(m)) for m in range(3)]
+    spp = 192
+    n = spp * cam["width"] * cam["height"]
+    res = []
+    for i, (k, flags) in enumerate([(1, 0), (3, 0), (1, oracle.NEE_BEFORE_ABSORPTION),
+                                     (2, oracle.NEE_BEFORE_ABSORPTION)]):
+        o = oracle.render(c4, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                          models=models, tau_min=1.0, spp=spp, seed=40 + i, nee_samples=k, flags=flags)
+        m = o["sum"].sum() / n
+        res.append((m, np.sqrt((o["sumsq"].sum() / n - m * m) / n), o["steps"].sum()))
+    m0, s0, st0 = res[0]
+    assert st0 > 1000
+    for m, s, _ in res[1:]:
+        assert abs(m - m0) < 5 * np.hypot(s, s0), res
+    # the default order with one sample is unchanged by the new fields
+    a = oracle.render(c4, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE, models=models,
+                      tau_min=1.0, spp=2, seed=40)
+    b = oracle.render(c4, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE, models=models,
+                      tau_min=1.0, spp=2, seed=40, nee_samples=0)
+    np.testing.assert_array_equal(a["sum"], b["sum"])
