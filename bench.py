@@ -50,19 +50,34 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--batch-min", type=int, default=0)
+    ap.add_argument("--nee-samples", type=int, default=2)
+    ap.add_argument("--nee-flags", type=int, default=1, help="1 = direct light of learned steps before absorption")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--c5-width", type=int, default=1024)
+    ap.add_argument("--c5-spp", type=int, default=1024)
+    ap.add_argument("--c5-ref-spp", type=int, default=4096)
     ap.add_argument("--diagnostics", action="store_true",
                     help="also render sphere tracing with exact in-sphere walks and a tau_min sweep (untimed)")
     return ap.parse_args()
 
 
-def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.3, precision=1):
+def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precision=1):
+    """Trains the three CVAEs (see train_and_pack) and returns (packed models
+    in `precision`, per-model losses, seconds)."""
+    packs, losses, t = train_and_pack(M, torch, n_samples, steps, batch, seed, kl_warmup, (precision,))
+    return packs[precision], losses, t
+
+
+def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,)):
     """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
 
     The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
-    steps (a guard against decoders that ignore the latent)."""
+    steps (a guard against decoders that ignore the latent).  Returns
+    ({precision: [three packed models]}, per-model losses, seconds)."""
     t0 = time.time()
     walk = M.random_walk(n_samples, seed=seed, mode=1)
-    packed, losses = [], []
+    packs, losses = {p: [] for p in precisions}, []
     for model in range(3):
         p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
         # PathGen learns N >= 2 records and EventGen k >= 2 records: the
@@ -89,18 +104,14 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.3, 
             if step == 1:
                 first = loss.cpu().numpy().copy()
         last = loss.cpu().numpy().copy()
-        pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-        M.cvae_pack(model, master, stats, precision, pk)
-        packed.append(pk)
+        for p in precisions:
+            pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+            M.cvae_pack(model, master, stats, p, pk)
+            packs[p].append(pk)
         losses.append(dict(rows=int(n_rows), first=first.tolist(), last=last.tolist()))
         log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
     torch.cuda.synchronize()
-    return packed, losses, time.time() - t0
-
-
-def train_models_both(M, torch, n_samples, steps, **kw):
-    """As train_models, returning BF16 and FP8 packings of the same weights."""
-    return train_models(M, torch, n_samples, steps, **kw)
+    return packs, losses, time.time() - t0
 
 
 def image_moments(img, spp):
@@ -110,13 +121,56 @@ def image_moments(img, spp):
     return mean, var.clamp_min(0)
 
 
-def cpu_baseline(oracle, W, seconds):
-    """Oracle sphere tracer with the CVAE step (FP64) on a pixel subset of the
-    sigma_t = 40 image, on all host cores."""
+def c5_section(M, W, torch, packs, args, timed):
+    """64-sphere scene over a 256^3 FP16 distance grid, 1024^2 x 1024 spp,
+    sigma_t = 100: sphere tracing with FP8 and BF16 decoders against the plain
+    tracer; image error against a high-sample plain render (whose own noise is
+    subtracted)."""
+    import numpy as np
+    width, spp, res = args.c5_width, args.c5_spp, 256
+    prims = W.scene_c5(seed=0)
+    grid = M.build_sdf_grid(prims, res)
+    cam, light, med = W.camera_c5(width, width), W.light_c5(), W.medium_c5()
+    rend = M.Renderer(prims, cam, light, grid=grid)
+    img, t_ref = timed(lambda: rend.render(med, method=1, spp=args.c5_ref_spp, seed=77))
+    ref, ref_var = image_moments(img, args.c5_ref_spp)
+    ref_noise2 = float(ref_var.mean()) / args.c5_ref_spp
+    out = {"workload": f"64 spheres (seed 0) over a {res}^3 FP16 distance grid, {width}x{width}, {spp} spp, "
+                       f"sigma_t=100, g=0.8, albedo=0.995, point light + NEE",
+           "reference": f"plain tracer at {args.c5_ref_spp} spp ({t_ref:.1f} s)"}
+    runs = [("pt", dict(method=1)), ("st_bf16", dict(method=2, packed=packs[1])),
+            ("st_fp8", dict(method=2, packed=packs[2]))]
+    for name, opt in runs:
+        if opt["method"] == 2:
+            opt.update(tau_min=args.tau_min, nee_samples=args.nee_samples, flags=args.nee_flags)
+        rend.render(med, spp=16, seed=5, **opt)  # warm-up
+        img, t = timed(lambda: rend.render(med, spp=spp, seed=6, **opt))
+        c = img["counters"].cpu().numpy()
+        mean, var = image_moments(img, spp)
+        err2 = float(((mean - ref) ** 2).mean())
+        rm = float(np.sqrt(max(err2 - ref_noise2, 1e-30)))
+        out[name] = dict(ms=t * 1e3, paths_per_s=float(c[0] / t), events_per_path=float(c[1] / c[0]),
+                         steps_per_path=float(c[2] / c[0]), rmse=rm, mean_var=float(var.mean()),
+                         mean=float(mean.mean()))
+        log(f"C5 {name}: {t * 1e3:.1f} ms, {c[0] / t:.3e} paths/s, RMSE {rm:.3e}")
+    out["ref_mean"] = float(ref.mean())
+    out["ref_noise_rms"] = float(np.sqrt(ref_noise2))
+    pt = out["pt"]
+    for name in ("st_bf16", "st_fp8"):
+        r = out[name]
+        s_star = pt["mean_var"] / max(r["rmse"] ** 2, 1e-30)
+        r["speedup_matched_rmse"] = s_star * width * width / pt["paths_per_s"] / (r["ms"] / 1e3)
+    return out
+
+
+def cpu_baseline(oracle, W, args):
+    """Oracle sphere tracer with the CVAE step (FP64) on random pixel subsets
+    of the sigma_t = 40 image, same estimator options, all host cores; runs
+    for about args.cpu_seconds."""
     import numpy as np
     cores = os.cpu_count() or 1
     prims = W.scene_c4()
-    cam = W.camera_c4(512, 512)
+    cam = W.camera_c4(args.width, args.width)
     light = W.light_c4()
     med = W.medium_c4(40.0)
     models = []
@@ -125,16 +179,18 @@ def cpu_baseline(oracle, W, seconds):
         models.append(dict(shape=shape, params=oracle.cvae_init(shape, 900 + m), stats=W.render_test_stats(m)))
     rng = np.random.default_rng(0)
     npx, spp = 256, 4
-    total_paths, t_total = 0, 0.0
-    while t_total < seconds and npx <= 1 << 18:
-        pix = rng.choice(512 * 512, npx, replace=False).astype(np.int32)
+    total_paths, t_total, it = 0, 0.0, 0
+    scene = oracle.Scene(prims)
+    while t_total < args.cpu_seconds:
+        pix = rng.choice(args.width * args.width, npx, replace=False).astype(np.int32)
         t0 = time.time()
-        oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
-                      models=models, spp=spp, pixels=pix, n_threads=cores)
-        dt = time.time() - t0
+        oracle.render(scene, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      models=models, tau_min=args.tau_min, spp=spp, seed=it, pixels=pix, n_threads=cores,
+                      nee_samples=args.nee_samples, flags=args.nee_flags)
+        t_total += time.time() - t0
         total_paths += npx * spp
-        t_total += dt
-        npx *= 2
+        npx = min(2 * npx, 1 << 16)
+        it += 1
     return {"value": total_paths / t_total, "unit": "paths/s", "cores": cores, "kind": "oracle",
             "sample": f"{total_paths} paths (random pixel subsets x {spp} spp) of the sigma_t = 40 image, "
                       f"ST + CVAE decoders in FP64 with oracle-initialised weights, {t_total:.1f} s"}
@@ -159,7 +215,7 @@ def main():
     rend = M.Renderer(W.scene_c4(), W.camera_c4(width, width), W.light_c4())
     npix = width * width
     stream = torch.cuda.current_stream()
-    kw = dict(blocks_per_cu=args.blocks_per_cu, cvae_batch_min=args.batch_min)
+    kw = dict(blocks_per_cu=args.blocks_per_cu, cvae_batch_min=args.batch_min, chunk=args.chunk)
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -174,7 +230,8 @@ def main():
         return float(torch.sqrt(((mean.float() - ref[s]) ** 2).mean()))
 
     log("training CVAEs on GPU random-walk data")
-    packed, losses, t_train = train_models(M, torch, args.train_samples, args.train_steps)
+    packs, losses, t_train = train_and_pack(M, torch, args.train_samples, args.train_steps, precisions=(1, 2))
+    packed = packs[1]
 
     # plain reference (debiased by its own noise) and plain timing per density
     ref, ref_noise2, pt = {}, {}, {}
@@ -191,7 +248,8 @@ def main():
         log(f"PT sigma_t={s}: {t * 1e3:.1f} ms, {c[0] / t:.3e} paths/s, events/path {c[1] / c[0]:.2f}")
 
     def st_render(s, seed, **extra):
-        opts = dict(method=2, sampler=0, packed=packed, spp=spp, seed=seed, tau_min=args.tau_min)
+        opts = dict(method=2, sampler=0, packed=packed, spp=spp, seed=seed, tau_min=args.tau_min,
+                    nee_samples=args.nee_samples, flags=args.nee_flags)
         opts.update(kw)
         opts.update(extra)
         return rend.render(W.medium_c4(s), **opts)
@@ -268,11 +326,16 @@ def main():
                 "mfma_tflops": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / 1e12,
                 "mfma_frac": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / PEAK_MFMA_BF16}
 
+    c5 = None
+    if not args.no_c5:
+        log("C5: 64-sphere grid scene, FP8 / BF16 / plain")
+        c5 = c5_section(M, W, torch, packs, args, timed)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         log("timing the CPU oracle")
-        cpu = cpu_baseline(oracle, W, args.cpu_seconds)
+        cpu = cpu_baseline(oracle, W, args)
 
     result = {
         "metric": "sphere-traced paths/s (CVAE) vs plain random-walk paths/s at matched RMSE",
@@ -281,7 +344,8 @@ def main():
         "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": f"sphere+box SDF scene {width}x{width}, {spp} spp, g=0.8, albedo=0.995, "
                                f"sigma_t in {list(sigmas)}, point light + NEE, CVAE decoders BF16 on MFMA, "
-                               f"tau_min={args.tau_min}",
+                               f"tau_min={args.tau_min}, {args.nee_samples} representative events per step"
+                               + (", direct light before absorption" if args.nee_flags & 1 else ""),
                    "paths_per_step": paths_per_step, "parallelism": "single GPU"},
         "plain_paths_per_s": pt_rate,
         "speedup_matched_rmse": tot_pt / tot_st,
@@ -289,6 +353,7 @@ def main():
         "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "c5": c5,
         "diagnostics": diag,
         "wall_s_timed": wall,
     }

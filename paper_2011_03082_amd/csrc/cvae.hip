@@ -623,6 +623,8 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
     const int64_t n_chunks = (n + 63) / 64;
     const int64_t wave_global = blockIdx.x * (int64_t)kSampleWaves + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * kSampleWaves;
+    const DecoderRegs w = load_decoder(pm);
+    const bool fp8 = pm->precision == MS_PREC_FP8;
     for (int64_t chunk = wave_global; chunk < n_chunks; chunk += n_waves) {
         const int64_t i = chunk * 64 + lane;
         const bool valid = i < n;
@@ -640,7 +642,7 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
         for (int t = 0; t < n_tiles; ++t) {
             const int path = 16 * t + frag_row();
             const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-            const f32x4 o = decoder_tile_any(pm, xin);
+            const f32x4 o = fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
             *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
         }
         wave_sync();

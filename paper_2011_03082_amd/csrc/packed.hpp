@@ -49,38 +49,39 @@ __device__ __forceinline__ fp8x8 to_fp8x4_lo(f32x4 v) {
     return (fp8x8)(uint32_t)w;
 }
 
-__device__ __forceinline__ f32x4 decoder_tile_fp8(const PackedModel* pm, f32x4 x) {
-    const int nl = pm->n_linear;
+// Decoder weights of one model held in registers for a pass over several
+// tiles: per layer the lane's A fragment (2 dwords: 4 BF16 or 8 FP8 values)
+// and the four biases of the output rows k0 .. k0+3 it produces.
+constexpr int kDecLayers = 3;
+
+struct DecoderRegs {
+    uint2 a[kDecLayers];
+    f32x4 b[kDecLayers];
+    float sc[kDecLayers];
+};
+
+__device__ __forceinline__ DecoderRegs load_decoder(const PackedModel* pm) {
+    DecoderRegs w;
     const int k0 = frag_k0();
-    f32x4 acc;
-    for (int j = 0; j < nl; ++j) {
-        const uint2 u = *reinterpret_cast<const uint2*>(pm->frag[j][lane_id()]);
-        const fp8x8 a = (fp8x8)(((uint64_t)u.y << 32) | u.x);
-        acc = mfma_fp8(a, to_fp8x4_lo(x), f32x4{0, 0, 0, 0});
-        const float sc = pm->w_scale[j];
-        const float* b = pm->bias[j];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(acc[q], sc, b[k0 + q]);
-        if (j < nl - 1) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = softplus(acc[q]);
-        }
+    for (int j = 0; j < kDecLayers; ++j) {
+        w.a[j] = *reinterpret_cast<const uint2*>(pm->frag[j][lane_id()]);
+        w.b[j] = *reinterpret_cast<const f32x4*>(&pm->bias[j][k0]);
+        w.sc[j] = pm->w_scale[j];
     }
-    return acc;
+    return w;
 }
 
-// Runs the decoder MLP on one 16-path tile whose inputs (z, standardised
-// condition; feature-major B operand) are `x`.  Returns the output layer in
-// D layout: rows k0..k0+3 of path column frag_row().
-__device__ __forceinline__ f32x4 decoder_tile(const PackedModel* pm, bf16x4 x) {
-    const int nl = pm->n_linear;
-    const int k0 = frag_k0();
+// Runs the three-layer decoder MLP on one 16-path tile whose inputs (z,
+// standardised condition; feature-major B operand) are `x`.  Returns the
+// output layer in D layout: rows k0..k0+3 of path column frag_row().
+__device__ __forceinline__ f32x4 decoder_tile(const DecoderRegs& w, f32x4 xin) {
+    bf16x4 x = to_bf16x4(xin);
     f32x4 acc;
-    for (int j = 0; j < nl; ++j) {
-        const float* b = pm->bias[j];
-        acc = f32x4{b[k0], b[k0 + 1], b[k0 + 2], b[k0 + 3]};
-        acc = mfma_bf16(load_frag_bf16(pm, j), x, acc);
-        if (j < nl - 1) {
+#pragma unroll
+    for (int j = 0; j < kDecLayers; ++j) {
+        acc = mfma_bf16(__builtin_bit_cast(bf16x4, w.a[j]), x, w.b[j]);
+        if (j < kDecLayers - 1) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = softplus(acc[q]);
             x = to_bf16x4(acc);
@@ -89,12 +90,21 @@ __device__ __forceinline__ f32x4 decoder_tile(const PackedModel* pm, bf16x4 x) {
     return acc;
 }
 
-}  // namespace msst
-
-namespace msst {
-// Decoder on one tile in the model's packed precision (uniform branch).
-__device__ __forceinline__ f32x4 decoder_tile_any(const PackedModel* pm, f32x4 xin) {
-    if (pm->precision == MS_PREC_FP8) return decoder_tile_fp8(pm, xin);
-    return decoder_tile(pm, to_bf16x4(xin));
+// The same on FP8 E4M3 weights and activations with per-layer weight scales.
+__device__ __forceinline__ f32x4 decoder_tile_fp8(const DecoderRegs& w, f32x4 x) {
+    f32x4 acc;
+#pragma unroll
+    for (int j = 0; j < kDecLayers; ++j) {
+        const fp8x8 a = (fp8x8)(((uint64_t)w.a[j].y << 32) | w.a[j].x);
+        acc = mfma_fp8(a, to_fp8x4_lo(x), f32x4{0, 0, 0, 0});
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(acc[q], w.sc[j], w.b[j][q]);
+        if (j < kDecLayers - 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = softplus(acc[q]);
+        }
+    }
+    return acc;
 }
+
 }  // namespace msst

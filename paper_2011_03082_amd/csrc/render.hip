@@ -376,12 +376,14 @@ __device__ __forceinline__ void stage_input(const PackedModel* pm, RenderLds& L,
 template <int PO>
 __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
                                             float* y) {
+    const DecoderRegs w = load_decoder(pm);
+    const bool fp8 = pm->precision == MS_PREC_FP8;
     wave_sync();
     const int n_tiles = (n + 15) >> 4;
     for (int t = 0; t < n_tiles; ++t) {
         const int path = 16 * t + frag_row();
         const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-        const f32x4 o = decoder_tile_any(pm, xin);
+        const f32x4 o = fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
         *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
     }
     wave_sync();
