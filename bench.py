@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--nee-flags", type=int, default=1, help="1 = direct light of learned steps before absorption")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--restart-min", type=int, default=0)
     ap.add_argument("--c5-width", type=int, default=1024)
     ap.add_argument("--c5-spp", type=int, default=1024)
     ap.add_argument("--c5-ref-spp", type=int, default=4096)
@@ -62,19 +64,20 @@ def parse():
     return ap.parse_args()
 
 
-def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precision=1):
+def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precision=1, shapes=None):
     """Trains the three CVAEs (see train_and_pack) and returns (packed models
     in `precision`, per-model losses, seconds)."""
-    packs, losses, t = train_and_pack(M, torch, n_samples, steps, batch, seed, kl_warmup, (precision,))
+    packs, losses, t = train_and_pack(M, torch, n_samples, steps, batch, seed, kl_warmup, (precision,), shapes)
     return packs[precision], losses, t
 
 
-def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,)):
+def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), shapes=None):
     """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
 
     The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
     steps (a guard against decoders that ignore the latent).  Returns
-    ({precision: [three packed models]}, per-model losses, seconds)."""
+    ({precision: [three packed models]}, per-model losses, seconds).  shapes:
+    three architecture dicts (default: width 16, three linear maps, latent 4)."""
     t0 = time.time()
     walk = M.random_walk(n_samples, seed=seed, mode=1)
     packs, losses = {p: [] for p in precisions}, []
@@ -89,24 +92,25 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
         M.cvae_features(model, n_rows, walk, seed + 1, 0, None, cond, target, rows=rows)
         stats = M.make_stats(cond, target)
         M.cvae_features(model, n_rows, walk, seed + 1, 0, stats, cond, target, rows=rows)
-        n = M.cvae_param_count(model)
+        shape = model if shapes is None else shapes[model]
+        n = M.cvae_param_count(shape)
         master = torch.empty(n, dtype=torch.float32, device="cuda")
-        M.cvae_init(model, seed + 10 + model, master)
+        M.cvae_init(shape, seed + 10 + model, master)
         m, v = torch.zeros_like(master), torch.zeros_like(master)
-        ws = torch.empty(M.cvae_workspace_size(model, batch), dtype=torch.uint8, device="cuda")
+        ws = torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda")
         loss = torch.zeros(3, dtype=torch.float64, device="cuda")
         first = None
         for step in range(1, steps + 1):
             lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
             beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
-            M.cvae_train_step(model, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
+            M.cvae_train_step(shape, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
                               seed + 20 + model, step, 0, ws, loss, kl_weight=beta)
             if step == 1:
                 first = loss.cpu().numpy().copy()
         last = loss.cpu().numpy().copy()
         for p in precisions:
             pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-            M.cvae_pack(model, master, stats, p, pk)
+            M.cvae_pack(shape, master, stats, p, pk)
             packs[p].append(pk)
         losses.append(dict(rows=int(n_rows), first=first.tolist(), last=last.tolist()))
         log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
@@ -215,7 +219,8 @@ def main():
     rend = M.Renderer(W.scene_c4(), W.camera_c4(width, width), W.light_c4())
     npix = width * width
     stream = torch.cuda.current_stream()
-    kw = dict(blocks_per_cu=args.blocks_per_cu, cvae_batch_min=args.batch_min, chunk=args.chunk)
+    kw = dict(blocks_per_cu=args.blocks_per_cu, cvae_batch_min=args.batch_min, chunk=args.chunk,
+              restart_min=args.restart_min)
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -304,6 +309,25 @@ def main():
         tot_pt += t_pt_match
     pt_rate = sum(pt[s]["paths"] for s in sigmas) / sum(pt[s]["time"] for s in sigmas)
 
+    # the paper's final architectures (Table 1) on the same data and images
+    table1 = None
+    if not args.no_table1:
+        log("Table 1 final architectures")
+        pk1, losses1, t1 = train_and_pack(M, torch, args.train_samples, args.train_steps,
+                                          shapes=W.TABLE1_SHAPES)
+        table1 = {"shapes": W.TABLE1_SHAPES, "train_seconds": t1,
+                  "loss_last": [l["last"] for l in losses1]}
+        for s in sigmas:
+            st_render(s, 6000, packed=pk1[1])
+            img, t = timed(lambda: st_render(s, 6001, packed=pk1[1]))
+            r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
+            s_star = pt[s]["var"] / r_st**2
+            t_pt_match = s_star * npix / (pt[s]["paths"] / pt[s]["time"])
+            table1[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, speedup_matched_rmse=t_pt_match / t,
+                                  rmse_st_default_arch=details[str(s)]["rmse_st"])
+            log(f"Table 1 sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default {details[str(s)]['rmse_st']:.3e}), "
+                f"speed-up {t_pt_match / t:.2f}")
+
     diag = None
     if args.diagnostics:
         diag = {}
@@ -354,6 +378,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "c5": c5,
+        "table1": table1,
         "diagnostics": diag,
         "wall_s_timed": wall,
     }

@@ -12,7 +12,7 @@ namespace msst {
 constexpr float kLvMin = -12.0f, kLvMax = 8.0f;
 constexpr float kLog2Pi = 1.83787706640934548f;
 constexpr int kTrainWaves = 4;  // waves per training block
-constexpr int kNL = 3;          // linear maps per network (two hidden layers)
+constexpr int kMaxNL = 4;       // linear maps per network: 2 .. 4 (one to three hidden layers)
 
 struct Shape {
     int model, p_in, p_out, latent, width, n_linear;
@@ -241,7 +241,7 @@ struct TrainArgs {
 
 // Per-wave LDS: inputs of the 6 layers and two work tiles.
 struct WaveLds {
-    float act[6][kTile * kTile];
+    float act[2 * kMaxNL][kTile * kTile];
     float work[2][kTile * kTile];
 };
 
@@ -260,10 +260,13 @@ __device__ __forceinline__ f32x4 bias_d(const float* layer) {
     return f32x4{b[k0], b[k0 + 1], b[k0 + 2], b[k0 + 3]};
 }
 
-// Forward of one net (NL layers starting at FIRST) from act[FIRST].
+// Forward of one net (NL layers starting at FIRST) from act[FIRST].  Hidden
+// units at or beyond `width` do not exist: their activations are forced to 0,
+// so their (zero-initialised) weights and biases receive zero gradients.
 template <int FIRST, int NL>
-__device__ __forceinline__ f32x4 net_forward(const float* master, WaveLds& L, f32x4* pre) {
+__device__ __forceinline__ f32x4 net_forward(const float* master, WaveLds& L, f32x4* pre, int width) {
     constexpr int first = FIRST, nl = NL;
+    const int k0 = frag_k0();
     f32x4 acc;
 #pragma unroll
     for (int j = 0; j < nl; ++j) {
@@ -274,7 +277,7 @@ __device__ __forceinline__ f32x4 net_forward(const float* master, WaveLds& L, f3
         if (j < nl - 1) {
             f32x4 a;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = bf16_round(softplus(acc[q]));
+            for (int q = 0; q < 4; ++q) a[q] = k0 + q < width ? bf16_round(softplus(acc[q])) : 0.0f;
             tile_store_d(L.act[first + j + 1], a);
             wave_sync();
         }
@@ -314,19 +317,20 @@ __device__ __forceinline__ f32x4 net_backward(const float* master, WaveLds& L, c
     return dx;
 }
 
+template <int NL>
 __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
     __shared__ WaveLds lds_all[kTrainWaves];
     const int wave = threadIdx.x >> 6;
     WaveLds& L = lds_all[wave];
     const Shape s = a.s;
-    constexpr int nl = kNL;
+    constexpr int nl = NL;
     const int P = s.p_out, Lt = s.latent, C = s.p_in;
     const int lane = lane_id();
     const float inv_b = 1.0f / (float)a.batch;
 
-    f32x4 dw[6], db[6], pre[6];
+    f32x4 dw[2 * NL], db[2 * NL], pre[2 * NL];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < 2 * NL; ++i) {
         dw[i] = f32x4{0, 0, 0, 0};
         db[i] = f32x4{0, 0, 0, 0};
     }
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
         }
         wave_sync();
         // encoder
-        const f32x4 oe = net_forward<0, kNL>(a.master, L, pre);
+        const f32x4 oe = net_forward<0, NL>(a.master, L, pre, s.width);
         tile_store_d(L.work[0], oe);
         wave_sync();
         if (lane < 16) {
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
         }
         wave_sync();
         // decoder
-        const f32x4 od = net_forward<kNL, kNL>(a.master, L, pre);
+        const f32x4 od = net_forward<NL, NL>(a.master, L, pre, s.width);
         tile_store_d(L.work[0], od);
         for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
         wave_sync();
@@ -402,7 +406,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             nll_acc += (double)nll;
         }
         wave_sync();
-        const f32x4 dzc = net_backward<kNL, kNL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
+        const f32x4 dzc = net_backward<NL, NL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
         tile_store_d(L.work[0], dzc);
         for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
         wave_sync();
@@ -417,7 +421,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             }
         }
         wave_sync();
-        net_backward<0, kNL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
+        net_backward<0, NL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
         wave_sync();
     }
 
@@ -623,6 +627,7 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
     const int64_t n_chunks = (n + 63) / 64;
     const int64_t wave_global = blockIdx.x * (int64_t)kSampleWaves + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * kSampleWaves;
+    const bool three = pm->n_linear == kDecLayers;
     const DecoderRegs w = load_decoder(pm);
     const bool fp8 = pm->precision == MS_PREC_FP8;
     for (int64_t chunk = wave_global; chunk < n_chunks; chunk += n_waves) {
@@ -642,7 +647,7 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
         for (int t = 0; t < n_tiles; ++t) {
             const int path = 16 * t + frag_row();
             const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-            const f32x4 o = fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
+            const f32x4 o = !three ? decoder_tile_layers(pm, xin) : fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
             *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
         }
         wave_sync();
@@ -665,10 +670,10 @@ static ms_status check_shape(const ms_cvae_shape* sh, Shape* out) {
     MS_REQUIRE(sh->model >= 0 && sh->model <= 2, "CVAE model must be 0, 1 or 2");
     MS_REQUIRE(sh->p_in >= 1 && sh->p_out >= 1 && sh->latent >= 1 && sh->width >= 1, "CVAE sizes must be positive");
     if (sh->width > 16 || sh->p_out + sh->p_in > 16 || sh->latent + sh->p_in > 16 || 2 * sh->p_out > 16 ||
-        2 * sh->latent > 16 || sh->n_linear != 3 || sh->width != 16 || sh->latent > 8)
+        2 * sh->latent > 16 || sh->n_linear < 2 || sh->n_linear > kMaxNL)
         return set_error(MS_ERR_UNSUPPORTED,
-                         "CVAE shape unsupported: needs width 16, n_linear 3, latent <= 8, "
-                         "p_out + p_in <= 16, latent + p_in <= 16, 2 p_out <= 16");
+                         "CVAE shape unsupported: needs width <= 16, 2 <= n_linear <= 4, "
+                         "p_out + p_in <= 16, latent + p_in <= 16, 2 p_out <= 16, 2 latent <= 16");
     *out = Shape{sh->model, sh->p_in, sh->p_out, sh->latent, sh->width, sh->n_linear};
     return MS_OK;
 }
@@ -853,7 +858,11 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
     ta.loss_partial = reinterpret_cast<double*>(reinterpret_cast<char*>(workspace_dev) +
                                                 align_up((size_t)nb * n_params * sizeof(float), 256));
     hipStream_t hs = (hipStream_t)stream;
-    hipLaunchKernelGGL(cvae_train_kernel, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta);
+    switch (s.n_linear) {
+        case 2: hipLaunchKernelGGL(cvae_train_kernel<2>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
+        case 3: hipLaunchKernelGGL(cvae_train_kernel<3>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
+        default: hipLaunchKernelGGL(cvae_train_kernel<4>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
+    }
     MS_LAUNCHED();
     AdamArgs aa{};
     aa.n_params = n_params;

@@ -58,6 +58,11 @@ __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf
 __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// Hardware square root and quotient through the reciprocal (1 ulp each)
+// where a correctly rounded result buys nothing: the IEEE sequences cost
+// about ten instructions apiece.
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // Natural log for free-flight lengths -log(u) / sigma_t: the library logf
 // (about 1 ulp relative over (0, 1]).
@@ -65,7 +70,7 @@ __device__ __forceinline__ float flight_ln(float u) { return logf(u); }
 
 // Box-Muller pair from two uniforms.
 __device__ __forceinline__ void box_muller(float ua, float ub, float& n0, float& n1) {
-    const float r = __builtin_sqrtf(-2.0f * fast_ln(ua));
+    const float r = fast_sqrt(-2.0f * fast_ln(ua));
     n0 = r * cos_rev(ub);
     n1 = r * sin_rev(ub);
 }
@@ -82,20 +87,20 @@ struct HgSample {
 };
 __device__ __forceinline__ HgSample hg_sample(float g, float xi) {
     const float q = __builtin_fmaf(g, 2.0f * xi - 1.0f, 1.0f);
-    const float iq2 = 1.0f / (q * q);
+    const float iq2 = fast_rcp(q * q);
     const float omg = 1.0f - g, opg = 1.0f + g;
     const float om = 2.0f * omg * omg * (1.0f - xi) * __builtin_fmaf(g, xi, 1.0f) * iq2;
     const float op = 2.0f * opg * opg * xi * __builtin_fmaf(g, xi, omg) * iq2;
     HgSample h;
     h.mu = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, 0.5f * (op - om)));
-    h.sin_t = __builtin_sqrtf(__builtin_fminf(1.0f, om * op));
+    h.sin_t = fast_sqrt(__builtin_fminf(1.0f, om * op));
     return h;
 }
 
 // HG phase function value (Eq. 1).
 __device__ __forceinline__ float hg_eval(float g, float cos_t) {
     const float den = __builtin_fmaf(-2.0f * g, cos_t, 1.0f + g * g);
-    return 0.0795774715459476679f * (1.0f - g * g) * fast_rsq(den) / den;
+    return 0.0795774715459476679f * (1.0f - g * g) * fast_rsq(den) * fast_rcp(den);
 }
 
 struct V3 {
@@ -118,7 +123,7 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
 // Orthonormal Basis, Revisited", JCGT 2017.
 __device__ __forceinline__ void onb(V3 n, V3& b1, V3& b2) {
     const float sign = __builtin_copysignf(1.0f, n.z);
-    const float a = -1.0f / (sign + n.z);
+    const float a = -fast_rcp(sign + n.z);
     const float b = n.x * n.y * a;
     b1 = v3(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
     b2 = v3(b, sign + n.y * n.y * a, -n.y);
@@ -139,8 +144,8 @@ __device__ __forceinline__ V3 scatter(V3 d, float mu, float s, float az_rev) {
 __device__ __forceinline__ float sphere_exit(V3 x, V3 d, float r2) {
     const float b = dot(x, d);
     const float delta = __builtin_fmaxf(0.0f, r2 - dot(x, x));
-    const float root = __builtin_sqrtf(__builtin_fmaf(b, b, delta));
-    return b >= 0.0f ? delta / (b + root) : root - b;
+    const float root = fast_sqrt(__builtin_fmaf(b, b, delta));
+    return b >= 0.0f ? fast_div(delta, b + root) : root - b;
 }
 
 // Softplus log(1 + e^x) = max(x, 0) + log(1 + e^-|x|) and its derivative.

@@ -107,4 +107,31 @@ __device__ __forceinline__ f32x4 decoder_tile_fp8(const DecoderRegs& w, f32x4 x)
     return acc;
 }
 
+// Any depth (2 .. kMaxLayers linear maps), weights read per layer: the
+// path for architectures other than the three-layer default.
+__device__ __forceinline__ f32x4 decoder_tile_layers(const PackedModel* pm, f32x4 xin) {
+    const int nl = pm->n_linear;
+    const int k0 = frag_k0();
+    const bool fp8 = pm->precision == MS_PREC_FP8;
+    f32x4 x = xin, acc;
+    for (int j = 0; j < nl; ++j) {
+        const uint2 u = *reinterpret_cast<const uint2*>(pm->frag[j][lane_id()]);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(&pm->bias[j][k0]);
+        if (fp8) {
+            const fp8x8 a = (fp8x8)(((uint64_t)u.y << 32) | u.x);
+            acc = mfma_fp8(a, to_fp8x4_lo(x), f32x4{0, 0, 0, 0});
+            const float sc = pm->w_scale[j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(acc[q], sc, b[q]);
+        } else {
+            acc = mfma_bf16(__builtin_bit_cast(bf16x4, u), to_bf16x4(x), b);
+        }
+        if (j < nl - 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = softplus(acc[q]);
+        }
+    }
+    return acc;
+}
+
 }  // namespace msst

@@ -26,7 +26,9 @@ constexpr int kMaxPrims = 4;
 constexpr int kRenderWaves = 4;
 constexpr float kTwoPiRev = 1.0f;  // angles are passed in revolutions
 
-enum : int { S_IDLE = 0, S_NEW = 1, S_FLY = 2, S_WAIT = 3, S_DONE = 4 };
+// Lane states: out of samples (IDLE), tracing (FLY), waiting for a learned
+// step (WAIT), path finished and not yet banked (END), no work left (DONE).
+enum : int { S_IDLE = 0, S_FLY = 2, S_WAIT = 3, S_DONE = 4, S_END = 5 };
 
 struct RenderArgs {
     const float* prims;  // device [n_prims][8]
@@ -48,6 +50,7 @@ struct RenderArgs {
     uint64_t seed, sample_offset;
     uint32_t max_events;
     int batch_min;
+    int restart_min;
     int nee_samples;
     int flags;
     float* part_sum;
@@ -87,13 +90,13 @@ __device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float
         const float b = dot(q, d);
         const V3 h = fma3(-b, d, q);
         const float r = pr[4];
-        const float hl = __builtin_sqrtf(dot(h, h));
+        const float hl = fast_sqrt(dot(h, h));
         const float disc = (r - hl) * (r + hl);
         if (!(disc > 0.0f)) return false;
-        const float s = __builtin_sqrtf(disc);
+        const float s = fast_sqrt(disc);
         const float c = dot(q, q) - r * r;
         const float qq = b > 0.0f ? -b - s : -b + s;  // same sign as -b, no cancellation
-        const float ta = c / qq, tb = qq;
+        const float ta = fast_div(c, qq), tb = qq;
         t0 = __builtin_fminf(ta, tb);
         t1 = __builtin_fmaxf(ta, tb);
         return true;
@@ -107,7 +110,7 @@ __device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float
             if (qa[a] < -h || qa[a] > h) return false;
             continue;
         }
-        const float inv = 1.0f / da[a];
+        const float inv = fast_rcp(da[a]);
         float ta = (-h - qa[a]) * inv, tb = (h - qa[a]) * inv;
         lo = __builtin_fmaxf(lo, __builtin_fminf(ta, tb));
         hi = __builtin_fminf(hi, __builtin_fmaxf(ta, tb));
@@ -158,11 +161,11 @@ __device__ __forceinline__ bool union_piece(const RayIv<NP>& iv, float t, float&
 
 __device__ __forceinline__ float prim_sdf(const float* pr, V3 p) {
     const V3 q = v3(p.x - pr[1], p.y - pr[2], p.z - pr[3]);
-    if (pr[0] == 0.0f) return __builtin_sqrtf(dot(q, q)) - pr[4];
+    if (pr[0] == 0.0f) return fast_sqrt(dot(q, q)) - pr[4];
     const float ex = __builtin_fabsf(q.x) - pr[4], ey = __builtin_fabsf(q.y) - pr[5], ez = __builtin_fabsf(q.z) - pr[6];
     const float ox = __builtin_fmaxf(ex, 0.0f), oy = __builtin_fmaxf(ey, 0.0f), oz = __builtin_fmaxf(ez, 0.0f);
     const float inside = __builtin_fminf(__builtin_fmaxf(ex, __builtin_fmaxf(ey, ez)), 0.0f);
-    return __builtin_sqrtf(ox * ox + oy * oy + oz * oz) + inside;
+    return fast_sqrt(ox * ox + oy * oy + oz * oz) + inside;
 }
 
 __device__ __forceinline__ float fp16_value(uint16_t h) {
@@ -213,7 +216,7 @@ __device__ __forceinline__ float nee(const RenderArgs& A, const Prims<NP>& P, V3
             t = dist;
         }
     }
-    return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) / dist2;
+    return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) * (inv_dist * inv_dist);
 }
 
 // ---------------------------------------------------------------- geometry policies
@@ -319,7 +322,7 @@ struct GeoMany {
             acc += __builtin_fminf(pe, dist) - ps;
             t = pe;
         }
-        return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) / dist2;
+        return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) * (inv_dist * inv_dist);
     }
 };
 
@@ -344,30 +347,35 @@ __device__ __forceinline__ void neumaier_add(float& sum, float& comp, float v) {
 // Sum_{i<=N} albedo^i / albedo^N = albedo (albedo^-N - 1) / (1 - albedo).
 __device__ __forceinline__ float lambda_weight(const RenderArgs& A, float N) {
     if (A.albedo >= 1.0f) return N;
-    return A.albedo * (fast_exp(-N * A.ln_albedo) - 1.0f) / (1.0f - A.albedo);
+    return fast_div(A.albedo * (fast_exp(-N * A.ln_albedo) - 1.0f), 1.0f - A.albedo);
 }
 
-// Writes this lane's decoder input row: L latent normals (z) from Philox
-// blocks, then the standardised condition; keeps the posterior noise in LDS.
-template <int LAT, int PO, int PI>
+// Writes this lane's decoder input row: `latent` normals (z) from Philox
+// blocks, then the standardised condition; keeps the posterior noise (the
+// next PO normals) in LDS.  Normals come four per block in Box-Muller pairs.
+template <int PO, int PI>
 __device__ __forceinline__ void stage_input(const PackedModel* pm, RenderLds& L, int slot, const Rng& rng,
                                             uint32_t& c0, const float* cond) {
-    float nrm[((LAT + PO + 3) / 4) * 4];
-#pragma unroll
-    for (int j = 0; j < (LAT + PO + 3) / 4; ++j) {
-        const uint4 w = rng.block(c0++);
-        box_muller(u01(w.x), u01(w.y), nrm[4 * j + 0], nrm[4 * j + 1]);
-        box_muller(u01(w.z), u01(w.w), nrm[4 * j + 2], nrm[4 * j + 3]);
-    }
+    const int lat = pm->latent;
+    const int n_norm = lat + PO;
     float* row = L.x[slot];
+    for (int j = 0; 4 * j < n_norm; ++j) {
+        const uint4 w = rng.block(c0++);
+        float nv[4];
+        box_muller(u01(w.x), u01(w.y), nv[0], nv[1]);
+        box_muller(u01(w.z), u01(w.w), nv[2], nv[3]);
 #pragma unroll
-    for (int q = 0; q < LAT; ++q) row[q] = nrm[q];
+        for (int q = 0; q < 4; ++q) {
+            const int i = 4 * j + q;
+            if (i < lat)
+                row[i] = nv[q];
+            else if (i < n_norm)
+                L.eps[slot][i - lat] = nv[q];
+        }
+    }
 #pragma unroll
-    for (int k = 0; k < PI; ++k) row[LAT + k] = (cond[k] - pm->mean_c[k]) * pm->inv_std_c[k];
-#pragma unroll
-    for (int q = LAT + PI; q < kTile; ++q) row[q] = 0.0f;
-#pragma unroll
-    for (int k = 0; k < PO; ++k) L.eps[slot][k] = nrm[LAT + k];
+    for (int k = 0; k < PI; ++k) row[lat + k] = (cond[k] - pm->mean_c[k]) * pm->inv_std_c[k];
+    for (int q = lat + PI; q < kTile; ++q) row[q] = 0.0f;
 }
 
 // Runs one decoder over the first n compacted rows (16-path MFMA tiles) and
@@ -376,15 +384,23 @@ __device__ __forceinline__ void stage_input(const PackedModel* pm, RenderLds& L,
 template <int PO>
 __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
                                             float* y) {
-    const DecoderRegs w = load_decoder(pm);
-    const bool fp8 = pm->precision == MS_PREC_FP8;
     wave_sync();
     const int n_tiles = (n + 15) >> 4;
-    for (int t = 0; t < n_tiles; ++t) {
-        const int path = 16 * t + frag_row();
-        const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-        const f32x4 o = fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
-        *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+    if (pm->n_linear == kDecLayers) {
+        const DecoderRegs w = load_decoder(pm);
+        const bool fp8 = pm->precision == MS_PREC_FP8;
+        for (int t = 0; t < n_tiles; ++t) {
+            const int path = 16 * t + frag_row();
+            const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
+            const f32x4 o = fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
+            *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+        }
+    } else {
+        for (int t = 0; t < n_tiles; ++t) {
+            const int path = 16 * t + frag_row();
+            const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
+            *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = decoder_tile_layers(pm, xin);
+        }
     }
     wave_sync();
     if (mine) {
@@ -417,7 +433,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     pool.reset();
     int state = S_IDLE;
     // unit state
-    int64_t pixel = 0, unit = 0;
+    int64_t unit = 0;
+    int px = 0, py = 0;
     int s = 0, s_end = 0;
     float acc_sum = 0.0f, acc_comp = 0.0f, acc_sq = 0.0f;
     uint32_t acc_ev = 0, acc_st = 0;
@@ -426,51 +443,84 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     V3 o = v3(0, 0, 0), d = v3(0, 0, 1);
     float t = 0.0f, Lp = 0.0f, r_step = 0.0f;
     uint32_t c0 = 0, iters = 0, p_ev = 0, p_st = 0;
+    bool p_trunc = false;
     uint32_t cnt_paths = 0, cnt_events = 0, cnt_steps = 0, cnt_trunc = 0;
 
     for (;;) {
-        // ---- work units
-        const bool need = state == S_IDLE;
-        const uint64_t tk = pool.take(need, A.ticket, 64);
-        if (need) {
-            if (tk < (uint64_t)A.n_units) {
-                unit = (int64_t)tk;
-                const int64_t ch = unit / A.npix;
-                pixel = unit - ch * A.npix;
-                s = (int)ch * A.chunk;
-                s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
-                acc_sum = acc_comp = acc_sq = 0.0f;
-                acc_ev = acc_st = 0;
-                state = S_NEW;
-            } else {
-                state = S_DONE;
+        // ---- restart phase, batched: lanes whose path ended bank it, lanes
+        // out of samples take a work unit, then every lane with a sample to
+        // trace starts its camera ray.  It runs once restart_min lanes wait
+        // or nothing else is in flight, so that its code is not issued for a
+        // handful of lanes on most iterations.
+        const uint64_t rmask = ballot(state == S_END || state == S_IDLE);
+        const uint64_t amask = ballot(state == S_FLY || state == S_WAIT);
+        if (rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0)) {
+            bool start = false;
+            if (state == S_END) {
+                neumaier_add(acc_sum, acc_comp, Lp);
+                acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
+                acc_ev += p_ev;
+                acc_st += p_st;
+                ++cnt_paths;
+                cnt_events += p_ev;
+                cnt_steps += p_st;
+                cnt_trunc += p_trunc;
+                ++s;
+                if (s >= s_end) {
+                    A.part_sum[unit] = acc_sum;
+                    A.part_comp[unit] = acc_comp;
+                    A.part_sq[unit] = acc_sq;
+                    A.part_events[unit] = acc_ev;
+                    A.part_steps[unit] = acc_st;
+                    state = S_IDLE;
+                } else {
+                    start = true;
+                }
+            }
+            const bool need = state == S_IDLE;
+            const uint64_t tk = pool.take(need, A.ticket, 64);
+            if (need) {
+                if (tk < (uint64_t)A.n_units) {
+                    unit = (int64_t)tk;
+                    const int64_t ch = unit / A.npix;
+                    const int pixel = (int)(unit - ch * A.npix);
+                    py = pixel / A.width;
+                    px = pixel - py * A.width;
+                    s = (int)ch * A.chunk;
+                    s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
+                    acc_sum = acc_comp = acc_sq = 0.0f;
+                    acc_ev = acc_st = 0;
+                    start = true;
+                } else {
+                    state = S_DONE;
+                }
+            }
+            if (start) {
+                const uint64_t sample = A.sample_offset + (uint64_t)s;
+                const uint64_t id = (uint64_t)(uint32_t)(py * A.width + px) | (sample << 32);
+                const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
+                const uint4 jw = rp.block(0);
+                rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
+                const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
+                const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
+                o = v3(A.eye[0], A.eye[1], A.eye[2]);
+                d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0],
+                                 A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
+                                 A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
+                G.set_ray(o, d);
+                t = 0.0f;
+                Lp = 0.0f;
+                c0 = 0;
+                iters = 0;
+                p_ev = 0;
+                p_st = 0;
+                state = S_FLY;
             }
         }
         if (ballot(state != S_DONE) == 0) break;
 
         // ---- VALU phase
         bool path_end = false, truncated = false;
-        if (state == S_NEW) {
-            const uint64_t sample = A.sample_offset + (uint64_t)s;
-            const uint64_t id = (uint64_t)pixel | (sample << 32);
-            const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
-            const uint4 jw = rp.block(0);
-            rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
-            const int64_t py = pixel / A.width, px = pixel - py * A.width;
-            const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
-            const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
-            o = v3(A.eye[0], A.eye[1], A.eye[2]);
-            d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0], A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
-                             A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
-            G.set_ray(o, d);
-            t = 0.0f;
-            Lp = 0.0f;
-            c0 = 0;
-            iters = 0;
-            p_ev = 0;
-            p_st = 0;
-            state = S_FLY;
-        }
         if (state == S_FLY) {
             // one Philox block per flight; the boundary query (the medium
             // piece of the ray containing or following t) is skipped when the
@@ -563,7 +613,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
         // ---- MFMA phase: learned sphere steps for the waiting lanes
         if (MODE == kModeStCvae) {
             const uint64_t wmask = ballot(state == S_WAIT);
-            const uint64_t lmask = ballot(state == S_NEW || state == S_FLY || state == S_WAIT);
+            const uint64_t lmask = ballot(state == S_FLY || state == S_WAIT);
             const int n_wait = __popcll(wmask);
             if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask)) {
                 const bool mine = state == S_WAIT;
@@ -574,7 +624,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 const int slot0 = rank_in(wmask);
                 if (mine) {
                     const float c2[2] = {lst, A.g};
-                    stage_input<4, 1, 2>(A.pm[0], L, slot0, rng, c0, c2);
+                    stage_input<1, 2>(A.pm[0], L, slot0, rng, c0, c2);
                 }
                 decode_rows<1>(A.pm[0], L, mine, slot0, n_wait, y);
                 bool alive = false;
@@ -612,14 +662,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                     // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
                     if (use_path) {
                         const float c3[3] = {lst, A.g, lnN};
-                        stage_input<4, 3, 3>(A.pm[1], L, slot, rng, c0, c3);
+                        stage_input<3, 3>(A.pm[1], L, slot, rng, c0, c3);
                     }
                     decode_rows<3>(A.pm[1], L, use_path, slot, __popcll(pmask), y);
                     if (use_path) {
                         ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
                         al = y[1];
                         be = y[2];
-                        ga = __builtin_sqrtf(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
+                        ga = fast_sqrt(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
                         const float inl = fast_rsq(al * al + be * be + ga * ga);
                         al *= inl;
                         be *= inl;
@@ -644,7 +694,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
                         if (use_event) {
                             const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-                            stage_input<4, 6, 7>(A.pm[2], L, slot, rng, c0, c7);
+                            stage_input<6, 7>(A.pm[2], L, slot, rng, c0, c7);
                         }
                         decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
                         if (use_event) {
@@ -667,7 +717,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 }
                 if (alive) {
                     // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
-                    const float st = __builtin_sqrtf(__builtin_fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+                    const float st = fast_sqrt(__builtin_fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
                     const V3 xt = v3(st * cp, st * sp, ct);
                     const V3 w0 = v3(be * ct + ga * st, al, -be * st + ga * ct);
                     const V3 wt = v3(cp * w0.x - sp * w0.y, sp * w0.x + cp * w0.y, w0.z);
@@ -680,27 +730,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
             }
         }
 
-        // ---- path and unit ends
         if (path_end) {
-            neumaier_add(acc_sum, acc_comp, Lp);
-            acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
-            acc_ev += p_ev;
-            acc_st += p_st;
-            ++cnt_paths;
-            cnt_events += p_ev;
-            cnt_steps += p_st;
-            cnt_trunc += truncated;
-            ++s;
-            if (s >= s_end) {
-                A.part_sum[unit] = acc_sum;
-                A.part_comp[unit] = acc_comp;
-                A.part_sq[unit] = acc_sq;
-                A.part_events[unit] = acc_ev;
-                A.part_steps[unit] = acc_st;
-                state = S_IDLE;
-            } else {
-                state = S_NEW;
-            }
+            p_trunc = truncated;
+            state = S_END;
         }
     }
     if (A.counters) {
@@ -753,9 +785,10 @@ __global__ void render_check_models(const RenderArgs A, unsigned long long* flag
     int ok = 1;
     for (int m = 0; m < 3; ++m) {
         const PackedModel* pm = A.pm[m];
-        ok &= pm->magic == (int32_t)kPackedMagic && pm->model == m && pm->latent == 4 && pm->p_in == want_in[m] &&
-              pm->p_out == want_out[m] && (pm->precision == MS_PREC_BF16 || pm->precision == MS_PREC_FP8) &&
-              pm->n_linear == 3;
+        ok &= pm->magic == (int32_t)kPackedMagic && pm->model == m && pm->latent >= 1 && pm->latent <= 8 &&
+              pm->latent + pm->p_in <= 16 && pm->p_in == want_in[m] && pm->p_out == want_out[m] &&
+              (pm->precision == MS_PREC_BF16 || pm->precision == MS_PREC_FP8) && pm->n_linear >= 2 &&
+              pm->n_linear <= kMaxLayers;
     }
     *flag = ok ? 0ull : 1ull;
 }
@@ -811,11 +844,15 @@ __global__ void sdf_grid_kernel(const float* prims, int n_prims, int res, double
     }
 }
 
-static int default_chunk(int spp) {
-    int c = 16;
-    if (spp >= 1024) c = 64;
+// Samples per work unit: small units balance the end of the persistent
+// kernel (a lane's last unit is its tail), large ones bound the partial
+// buffers.  About 2^24 units (64 per resident lane of a 256-CU device at
+// four 256-thread blocks per CU), and at least 2 samples per unit.
+static int default_chunk(int64_t npix, int spp) {
+    int64_t c = (npix * spp + (1 << 24) - 1) >> 24;
+    if (c < 2) c = 2;
     if (c > spp) c = spp;
-    return c;
+    return (int)c;
 }
 
 }  // namespace msst
@@ -827,7 +864,8 @@ ms_status sphere_trace_render_workspace_size(const ms_camera* cam, const ms_rend
     MS_REQUIRE(cam && desc && bytes, "sphere_trace_render_workspace_size: NULL argument");
     MS_REQUIRE(cam->width > 0 && cam->height > 0, "sphere_trace_render_workspace_size: empty image");
     MS_REQUIRE(desc->spp > 0, "sphere_trace_render_workspace_size: spp must be positive");
-    const int chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(desc->spp);
+    const int chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp)
+                                      : default_chunk((int64_t)cam->width * cam->height, desc->spp);
     const int64_t n_chunks = (desc->spp + chunk - 1) / chunk;
     const int64_t n_units = (int64_t)cam->width * cam->height * n_chunks;
     *bytes = 256 + align_up((size_t)n_units * 4, 256) * 5;
@@ -860,6 +898,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                "sphere_trace_render: invalid launch parameters");
     MS_REQUIRE(desc->tau_min >= 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min >= 0, st_max > 0");
     MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
+    MS_REQUIRE(desc->restart_min >= 0 && desc->restart_min <= 64, "sphere_trace_render: restart_min must be in [0, 64]");
     MS_REQUIRE((desc->flags & ~MS_RENDER_NEE_BEFORE_ABSORPTION) == 0, "sphere_trace_render: unknown flags");
     MS_REQUIRE(out->sum && out->sumsq, "sphere_trace_render: sum and sumsq images are required");
     MS_REQUIRE(scene->sdf_fp16 == nullptr || (scene->res > 0 && scene->res <= 4096 && scene->hi[0] > scene->lo[0] &&
@@ -921,7 +960,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.tau_min = desc->tau_min;
     A.st_max = desc->st_max;
     A.spp = desc->spp;
-    A.chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(desc->spp);
+    A.chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(A.npix, desc->spp);
     A.n_chunks = (desc->spp + A.chunk - 1) / A.chunk;
     A.n_units = A.npix * A.n_chunks;
     A.seed = desc->seed;
@@ -929,6 +968,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.max_events = desc->max_events ? desc->max_events : (1u << 20);
     A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 32;
     A.nee_samples = desc->nee_samples ? desc->nee_samples : 1;
+    A.restart_min = desc->restart_min ? desc->restart_min : 16;
     A.flags = desc->flags;
     char* ws = reinterpret_cast<char*>(workspace_dev);
     A.ticket = reinterpret_cast<unsigned long long*>(ws);

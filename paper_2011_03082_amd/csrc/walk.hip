@@ -39,11 +39,18 @@ __device__ __forceinline__ void put3(float* base, uint64_t n, uint64_t i, V3 v) 
     base[2 * n + i] = v.z;
 }
 
+// A photon's end (writing its record) and the start of the next one run in
+// one pass per wave once this many lanes wait, or when no lane is walking, so
+// that the code is not issued every iteration for a few lanes.
+constexpr int kWalkRestartMin = 16;
+
 template <int MODE>
 __global__ __launch_bounds__(256) void walk_kernel(const WalkArgs a) {
     TicketPool pool;
     pool.reset();
-    bool active = false, done = false;
+    // lane state: walking, ended (record not yet written), idle, done
+    bool active = false, ended = false, done = false;
+    bool absorbed = false, truncated = false;
     uint64_t i = 0;
     Rng rng = make_rng(a.seed, MS_TAG_WALK_EVENT, 0);
     V3 x = v3(0, 0, 0), d = v3(0, 0, 1), xk = v3(0, 0, 0), wk = v3(0, 0, 1);
@@ -54,40 +61,82 @@ __global__ __launch_bounds__(256) void walk_kernel(const WalkArgs a) {
     uint64_t n_events = 0, n_abs = 0, n_trunc = 0, n_max = 0;
 
     for (;;) {
-        const bool need = !active && !done;
-        const uint64_t t = pool.take(need, a.ticket, 64);
-        if (need) {
-            if (t < a.n) {
-                i = t;
-                active = true;
-                const uint64_t id = a.photon_offset + i;
-                rng = make_rng(a.seed, MS_TAG_WALK_EVENT, id);
-                if (MODE == MS_WALK_TRAINING) {
-                    const uint4 pw = philox(0u, (uint32_t)id, (uint32_t)(id >> 32), MS_TAG_WALK_PARAM, rng.k0, rng.k1);
-                    st = a.st_lo * __builtin_amdgcn_exp2f(u01(pw.x) * a.st_log2_ratio);
-                    g = __builtin_fmaf(a.g_span, u01(pw.y), a.g_lo);
-                    phi = __builtin_fmaf(a.a_span, u01(pw.z), a.a_lo);
-                    inv_st = 1.0f / st;
-                    inv_phi = 1.0f / phi;
+        const uint64_t rmask = ballot(!active && !done);
+        if (rmask != 0 && (__popcll(rmask) >= kWalkRestartMin || ballot(active) == 0)) {
+            if (ended) {
+                // the record of the finished photon; x holds its exit point
+                ended = false;
+                n_events += nev;
+                n_abs += absorbed;
+                n_trunc += truncated;
+                n_max = nev > n_max ? nev : n_max;
+                const uint64_t n = a.n;
+                if (a.params) {
+                    put3(a.params, n, i, v3(MODE == MS_WALK_ANALOG ? a.st_report : st, g, phi));
                 }
-                x = v3(0, 0, 0);
-                d = v3(0, 0, 1);
-                xk = x;
-                wk = d;
-                nev = 0;
-                c0 = 0;
-                k = 1;
-                resv = 0.0f;
-            } else {
-                done = true;
+                if (a.n_scatter) a.n_scatter[i] = nev;
+                if (a.absorbed) a.absorbed[i] = (uint8_t)absorbed;
+                if (a.truncated) a.truncated[i] = (uint8_t)truncated;
+                put3(a.exit_pos, n, i, x);
+                put3(a.exit_dir, n, i, d);
+                // exit frame of Sec. 4.1 after rotating by -psi about w_in = z
+                const float ir = 1.0f / r;
+                const V3 xh = ir * x;
+                const float sin_t = __builtin_sqrtf(xh.x * xh.x + xh.y * xh.y);
+                float cp = 1.0f, sp = 0.0f;
+                if (sin_t > 0.0f) {
+                    cp = xh.x / sin_t;
+                    sp = xh.y / sin_t;
+                }
+                if (a.exit_param) {
+                    const V3 wp = v3(cp * d.x + sp * d.y, -sp * d.x + cp * d.y, d.z);
+                    put3(a.exit_param, n, i, v3(xh.z, wp.y, wp.x * xh.z - wp.z * sin_t));
+                }
+                if (MODE == MS_WALK_TRAINING) {
+                    if (a.event_index) a.event_index[i] = k;
+                    const V3 xs = ir * xk;
+                    put3(a.event_pos, n, i, v3(cp * xs.x + sp * xs.y, -sp * xs.x + cp * xs.y, xs.z));
+                    put3(a.event_dir, n, i, v3(cp * wk.x + sp * wk.y, -sp * wk.x + cp * wk.y, wk.z));
+                }
+            }
+            const bool need = !active && !done;
+            const uint64_t t = pool.take(need, a.ticket, 64);
+            if (need) {
+                if (t < a.n) {
+                    i = t;
+                    active = true;
+                    const uint64_t id = a.photon_offset + i;
+                    rng = make_rng(a.seed, MS_TAG_WALK_EVENT, id);
+                    if (MODE == MS_WALK_TRAINING) {
+                        const uint4 pw =
+                            philox(0u, (uint32_t)id, (uint32_t)(id >> 32), MS_TAG_WALK_PARAM, rng.k0, rng.k1);
+                        st = a.st_lo * __builtin_amdgcn_exp2f(u01(pw.x) * a.st_log2_ratio);
+                        g = __builtin_fmaf(a.g_span, u01(pw.y), a.g_lo);
+                        phi = __builtin_fmaf(a.a_span, u01(pw.z), a.a_lo);
+                        inv_st = 1.0f / st;
+                        inv_phi = 1.0f / phi;
+                    }
+                    x = v3(0, 0, 0);
+                    d = v3(0, 0, 1);
+                    xk = x;
+                    wk = d;
+                    nev = 0;
+                    c0 = 0;
+                    k = 1;
+                    resv = 0.0f;
+                } else {
+                    done = true;
+                }
             }
         }
-        if (ballot(active) == 0) break;
+        if (ballot(!done) == 0) break;
         if (!active) continue;
 
         ++nev;
         const uint4 w = rng.block(c0++);
-        bool stop = false, absorbed = false, truncated = false;
+        bool stop = false;
+        absorbed = false;
+        truncated = false;
         V3 xe = x;
         if (MODE == MS_WALK_ANALOG) {
             if (u24(w.w) > a.surv_thr) {
@@ -127,38 +176,8 @@ __global__ __launch_bounds__(256) void walk_kernel(const WalkArgs a) {
         }
         if (stop) {
             active = false;
-            n_events += nev;
-            n_abs += absorbed;
-            n_trunc += truncated;
-            n_max = nev > n_max ? nev : n_max;
-            const uint64_t n = a.n;
-            if (a.params) {
-                put3(a.params, n, i, v3(MODE == MS_WALK_ANALOG ? a.st_report : st, g, phi));
-            }
-            if (a.n_scatter) a.n_scatter[i] = nev;
-            if (a.absorbed) a.absorbed[i] = (uint8_t)absorbed;
-            if (a.truncated) a.truncated[i] = (uint8_t)truncated;
-            put3(a.exit_pos, n, i, xe);
-            put3(a.exit_dir, n, i, d);
-            // exit frame of Sec. 4.1 after rotating by -psi about w_in = z
-            const float ir = 1.0f / r;
-            const V3 xh = ir * xe;
-            const float sin_t = __builtin_sqrtf(xh.x * xh.x + xh.y * xh.y);
-            float cp = 1.0f, sp = 0.0f;
-            if (sin_t > 0.0f) {
-                cp = xh.x / sin_t;
-                sp = xh.y / sin_t;
-            }
-            if (a.exit_param) {
-                const V3 wp = v3(cp * d.x + sp * d.y, -sp * d.x + cp * d.y, d.z);
-                put3(a.exit_param, n, i, v3(xh.z, wp.y, wp.x * xh.z - wp.z * sin_t));
-            }
-            if (MODE == MS_WALK_TRAINING) {
-                if (a.event_index) a.event_index[i] = k;
-                const V3 xs = ir * xk;
-                put3(a.event_pos, n, i, v3(cp * xs.x + sp * xs.y, -sp * xs.x + cp * xs.y, xs.z));
-                put3(a.event_dir, n, i, v3(cp * wk.x + sp * wk.y, -sp * wk.x + cp * wk.y, wk.z));
-            }
+            ended = true;
+            x = xe;
         }
     }
     if (a.counters) {

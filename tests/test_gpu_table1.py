@@ -1,0 +1,145 @@
+"""The architectures of Table 1 on the GPU: hidden-layer counts D in {1, 2,
+3}, widths below 16 and latent sizes 2 / 5 / 6, against the FP64 oracle --
+initialisation, bfloat16 gradients, AdamW keeping non-existent units at zero,
+BF16 / FP8 decoder sampling and the sphere tracer with such decoders."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from conftest import announce
+
+pytestmark = pytest.mark.gpu
+
+BF16_U = 2.0**-8
+
+CASES = {f"final-{m}": W.TABLE1_SHAPES[m] for m in range(3)}
+CASES["D1-length-W4-L6"] = W.table1_shape(0, 1, 4, 6)
+CASES["D3-path-W12-L5"] = W.table1_shape(1, 3, 12, 5)
+CASES["D3-event-W16-L5"] = W.table1_shape(2, 3, 16, 5)
+CASES["D1-event-W12-L5"] = W.table1_shape(2, 1, 12, 5)
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda().contiguous()
+
+
+def real_mask(shape):
+    nl = shape["n_linear"]
+    mask = np.zeros((2 * nl, 272), bool)
+    for net in range(2):
+        in0 = shape["latent"] + shape["p_in"] if net else shape["p_out"] + shape["p_in"]
+        outl = 2 * shape["p_out"] if net else 2 * shape["latent"]
+        for j in range(nl):
+            n_in = in0 if j == 0 else shape["width"]
+            n_out = outl if j == nl - 1 else shape["width"]
+            Wm = np.zeros((16, 16), bool)
+            Wm[:n_out, :n_in] = True
+            b = np.zeros(16, bool)
+            b[:n_out] = True
+            mask[net * nl + j] = np.concatenate([Wm.ravel(), b])
+    return mask.ravel()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_init_and_gradient_parity(msst, oracle, name):
+    announce(f"table1 init + grad {name}")
+    shape = CASES[name]
+    n = msst.cvae_param_count(shape)
+    assert n == 2 * shape["n_linear"] * 272
+    master = torch.empty(n, dtype=torch.float32, device="cuda")
+    msst.cvae_init(shape, 41, master)
+    np.testing.assert_allclose(master.cpu().numpy(), oracle.cvae_init(shape, 41), rtol=1e-6, atol=1e-7)
+    master64 = oracle.cvae_init(shape, seed=7).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(3)
+    B = 256
+    cond = rng.normal(size=(B, shape["p_in"])).astype(np.float32)
+    target = rng.normal(size=(B, shape["p_out"])).astype(np.float32)
+    grad = torch.zeros(n, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    ws = torch.empty(msst.cvae_workspace_size(shape, B), dtype=torch.uint8, device="cuda")
+    msst.cvae_train_step(shape, dev(master64), None, None, None, dev(cond), dev(target), B, B, 0, 99, 3, 0, ws, loss,
+                         grad)
+    torch.cuda.synchronize()
+    l64, kl64, nll64, g64 = oracle.cvae_loss_grad(shape, master64, cond.astype(np.float64),
+                                                  target.astype(np.float64), 99, 3)
+    g = grad.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    cos = g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64))
+    print(f"{name}: grad rel-L2 {rel:.3e}, cosine {cos:.6f}")
+    assert rel < 10 * BF16_U and cos > 0.999
+    assert np.all(g[~real_mask(shape)] == 0)
+    np.testing.assert_allclose(loss.cpu().numpy(), (l64, kl64, nll64), rtol=10 * BF16_U, atol=1e-3)
+
+
+def test_training_keeps_missing_units_at_zero(msst):
+    announce("table1 training W=8")
+    shape = CASES["final-0"]
+    n_rows, B = 1 << 14, 512
+    rng = np.random.default_rng(1)
+    cond = rng.normal(size=(n_rows, 2)).astype(np.float32)
+    target = (0.5 * cond[:, :1] + 0.1 * rng.normal(size=(n_rows, 1))).astype(np.float32)
+    master = torch.empty(msst.cvae_param_count(shape), dtype=torch.float32, device="cuda")
+    msst.cvae_init(shape, 3, master)
+    m, v = torch.zeros_like(master), torch.zeros_like(master)
+    ws = torch.empty(msst.cvae_workspace_size(shape, B), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    first = None
+    for step in range(1, 201):
+        msst.cvae_train_step(shape, master, m, v, msst.adam_params(step, lr=3e-3, weight_decay=0.01), dev(cond),
+                             dev(target), n_rows, B, 1, 5, step, 0, ws, loss)
+        if step == 1:
+            first = float(loss[0])
+    assert float(loss[0]) < first
+    assert np.all(master.cpu().numpy()[~real_mask(shape)] == 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", [1, 2])
+def test_sampling_parity(msst, oracle, name, precision):
+    announce(f"table1 sample {name} precision={precision}")
+    shape = CASES[name]
+    model = shape["model"]
+    master64 = oracle.cvae_init(shape, seed=60 + model).astype(np.float32).astype(np.float64)
+    stats = W.random_stats(model, seed=model)
+    n = 2000 + 13
+    cond = W.random_conditions(model, n, seed=model).astype(np.float32)
+    packed = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+    msst.cvae_pack(shape, dev(master64), dev(stats, torch.float64), precision, packed)
+    out = torch.empty((n, shape["p_out"]), dtype=torch.float32, device="cuda")
+    msst.cvae_sample(packed, dev(cond), n, 17, 0, out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 17, 0,
+                             precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8)
+    err = np.abs(got - ref).max(axis=1) / stats[48:48 + shape["p_out"]].max()
+    print(f"{name} p{precision}: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}, max {err.max():.2e}")
+    # same bars as the default architecture (bfloat16: 1e-4 / 5e-2; E4M3: 1e-3 / 0.2)
+    assert np.quantile(err, 0.99) < (1e-4 if precision == 1 else 1e-3)
+    assert err.max() < (0.05 if precision == 1 else 0.2)
+
+
+@pytest.mark.parametrize("arch", ["final", "deep"])
+def test_sphere_tracing_with_table1_decoders(msst, oracle, arch):
+    """Path-by-path render parity (spp = 1) with Table 1 decoders: the latent
+    size and depth change the number of normals each decoder draws."""
+    announce(f"table1 render parity {arch}")
+    from test_gpu_render import c4_inputs, compare_paths, gpu_render
+    shapes = list(W.TABLE1_SHAPES) if arch == "final" else [W.table1_shape(0, 3, 8, 6), W.table1_shape(1, 1, 16, 5),
+                                                            W.table1_shape(2, 3, 12, 5)]
+    prims, cam, light, med = c4_inputs(20.0, 40)
+    models, packed = [], []
+    for m, shape in enumerate(shapes):
+        master = oracle.cvae_init(shape, seed=500 + m).astype(np.float32).astype(np.float64)
+        stats = W.render_test_stats(m)
+        models.append(dict(shape=shape, params=master, stats=stats))
+        p = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+        msst.cvae_pack(shape, dev(master), dev(stats, torch.float64), 1, p)
+        packed.append(p)
+    g = gpu_render(msst, prims, cam, light, med, method=2, sampler=0, packed=packed, spp=1, seed=25,
+                   nee_samples=2, flags=1)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      precision=oracle.PREC_BF16, models=models, spp=1, seed=25, nee_samples=2, flags=1)
+    frac, _ = compare_paths(g, o, rel=2e-3)
+    print(f"{arch}: diverged {frac:.2e}; sphere steps {o['steps'].sum()}")
+    assert o["steps"].sum() > 100
+    assert frac < 0.03

@@ -33,9 +33,25 @@ def batch(shape, B, seed):
     return rng.normal(size=(B, shape["p_in"])), rng.normal(size=(B, shape["p_out"]))
 
 
-@pytest.mark.parametrize("name", ["length", "path", "event"])
+def table1_cases():
+    import workloads as W
+    out = {f"table1-final-{m}": W.TABLE1_SHAPES[m] for m in range(3)}
+    out["table1-D1-length-W4-L6"] = W.table1_shape(0, 1, 4, 6)
+    out["table1-D3-path-W12-L5"] = W.table1_shape(1, 3, 12, 5)
+    out["table1-D3-event-W16-L5"] = W.table1_shape(2, 3, 16, 5)
+    return out
+
+
+ARCH_CASES = ["length", "path", "event"] + list(table1_cases())
+
+
+def arch_shape(oracle, name):
+    return oracle.SHAPES[name] if name in oracle.SHAPES else table1_cases()[name]
+
+
+@pytest.mark.parametrize("name", ARCH_CASES)
 def test_gradient_central_differences(oracle, name):
-    shape = oracle.SHAPES[name]
+    shape = arch_shape(oracle, name)
     p = oracle.cvae_init(shape, seed=3)
     cond, target = batch(shape, 8, 4)
     loss, kl, nll, grad = oracle.cvae_loss_grad(shape, p, cond, target, seed=9, step=2)
@@ -208,3 +224,31 @@ def test_training_reduces_loss(oracle):
         loss, _, _, g = oracle.cvae_loss_grad(shape, p, cond, target, 5, t)
         oracle.adamw_step(p, m, v, g, t, lr=3e-3)
     assert loss < first - 0.3
+
+
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_narrow_network_equals_wide_network_with_silent_units(oracle, model):
+    """A width-W network is the 16-wide network whose extra hidden units have
+    zero outgoing weights, whatever their incoming weights (Table 1 widths):
+    same loss and the same gradient on every real parameter."""
+    import workloads as W
+    narrow = dict(W.TABLE1_SHAPES[model], width=8 if model else 4)
+    wide = dict(narrow, width=16)
+    p = oracle.cvae_init(narrow, seed=11)
+    q = p.copy().reshape(2 * narrow["n_linear"], 272)
+    rng = np.random.default_rng(model)
+    nl, w = narrow["n_linear"], narrow["width"]
+    for net in range(2):
+        for j in range(nl - 1):  # hidden layers: give the extra units incoming weights and biases
+            layer = q[net * nl + j]
+            Wm = layer[:256].reshape(16, 16)
+            n_in = (narrow["latent"] + narrow["p_in"] if net else narrow["p_out"] + narrow["p_in"]) if j == 0 else w
+            Wm[w:, :n_in] = rng.normal(size=(16 - w, n_in))
+            layer[256 + w:] = rng.normal(size=16 - w)
+    q = q.ravel()
+    cond, target = batch(narrow, 8, 3)
+    ln, kln, nlln, gn = oracle.cvae_loss_grad(narrow, p, cond, target, seed=4, step=1)
+    lw, klw, nllw, gw = oracle.cvae_loss_grad(wide, q, cond, target, seed=4, step=1)
+    assert abs(ln - lw) < 1e-12 * max(1.0, abs(ln))
+    real = real_param_mask(narrow)
+    np.testing.assert_allclose(gw[real], gn[real], rtol=1e-10, atol=1e-13)

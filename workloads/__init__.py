@@ -26,6 +26,30 @@ SHAPES = {
     "event": dict(model=2, p_in=7, p_out=6, latent=4, width=16, n_linear=3),
 }
 SHAPE_LIST = [SHAPES["length"], SHAPES["path"], SHAPES["event"]]
+
+# Table 1: the hidden-layer counts D, widths W and latent sizes L examined
+# per model, and the final (highlighted) setting; n_linear = D + 1.
+TABLE1_GRID = {
+    0: dict(p_in=2, p_out=1, D=(1, 2, 3), W=(4, 8, 12), L=(2, 6)),
+    1: dict(p_in=3, p_out=3, D=(1, 2, 3), W=(8, 12, 16), L=(5, 9)),
+    2: dict(p_in=7, p_out=6, D=(1, 2, 3), W=(12, 16, 20), L=(5, 9)),
+}
+TABLE1_FINAL = {0: dict(D=2, W=8, L=2), 1: dict(D=2, W=16, L=5), 2: dict(D=2, W=16, L=5)}
+
+
+def table1_shape(model, D, W, L):
+    g = TABLE1_GRID[model]
+    return dict(model=model, p_in=g["p_in"], p_out=g["p_out"], latent=L, width=W, n_linear=D + 1)
+
+
+def table1_fits(shape):
+    """One 16-wide MFMA tile per layer: width <= 16, both networks' inputs
+    and outputs (p_out + p_in, latent + p_in, 2 p_out, 2 latent) <= 16."""
+    return (shape["width"] <= 16 and shape["p_out"] + shape["p_in"] <= 16 and shape["latent"] + shape["p_in"] <= 16
+            and 2 * shape["p_out"] <= 16 and 2 * shape["latent"] <= 16)
+
+
+TABLE1_SHAPES = [table1_shape(m, **TABLE1_FINAL[m]) for m in range(3)]
 TRAIN_C3 = dict(batch=4096, n_samples=1 << 22, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                 weight_decay=0.0)
 
