@@ -55,7 +55,13 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--no-absorption", action="store_true")
+    ap.add_argument("--no-focus", action="store_true")
+    ap.add_argument("--absorption-sigma", type=float, default=80.0)
+    ap.add_argument("--absorption-points", type=int, default=6)
     ap.add_argument("--restart-min", type=int, default=0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (the reference kernel for HBM counters)")
     ap.add_argument("--c5-width", type=int, default=1024)
     ap.add_argument("--c5-spp", type=int, default=1024)
     ap.add_argument("--c5-ref-spp", type=int, default=4096)
@@ -64,22 +70,26 @@ def parse():
     return ap.parse_args()
 
 
-def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precision=1, shapes=None):
+def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precision=1, shapes=None,
+                 walk_kw=None):
     """Trains the three CVAEs (see train_and_pack) and returns (packed models
     in `precision`, per-model losses, seconds)."""
-    packs, losses, t = train_and_pack(M, torch, n_samples, steps, batch, seed, kl_warmup, (precision,), shapes)
+    packs, losses, t = train_and_pack(M, torch, n_samples, steps, batch, seed, kl_warmup, (precision,), shapes,
+                                      walk_kw)
     return packs[precision], losses, t
 
 
-def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), shapes=None):
+def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), shapes=None,
+                   walk_kw=None):
     """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
 
     The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
     steps (a guard against decoders that ignore the latent).  Returns
     ({precision: [three packed models]}, per-model losses, seconds).  shapes:
-    three architecture dicts (default: width 16, three linear maps, latent 4)."""
+    three architecture dicts (default: width 16, three linear maps, latent 4);
+    walk_kw: extra training-walk options (e.g. a focus region)."""
     t0 = time.time()
-    walk = M.random_walk(n_samples, seed=seed, mode=1)
+    walk = M.random_walk(n_samples, seed=seed, mode=1, **(walk_kw or {}))
     packs, losses = {p: [] for p in precisions}, []
     for model in range(3):
         p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
@@ -116,6 +126,42 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
         log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
     torch.cuda.synchronize()
     return packs, losses, time.time() - t0
+
+
+RENDER_SOURCES = ("paper_2011_03082_amd/csrc/render.hip", "paper_2011_03082_amd/csrc/device.hpp",
+                  "paper_2011_03082_amd/csrc/packed.hpp", "paper_2011_03082_amd/csrc/mfma.hpp")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "render_kernel_hbm_traffic.md")
+
+
+def render_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in RENDER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per render launch of the timed workload from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that summary is
+    missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source digest") != render_source_digest():
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def image_moments(img, spp):
@@ -234,6 +280,15 @@ def main():
         mean, _ = image_moments(img, spp)
         return float(torch.sqrt(((mean.float() - ref[s]) ** 2).mean()))
 
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     log("training CVAEs on GPU random-walk data")
     packs, losses, t_train = train_and_pack(M, torch, args.train_samples, args.train_steps, precisions=(1, 2))
     packed = packs[1]
@@ -328,6 +383,51 @@ def main():
             log(f"Table 1 sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default {details[str(s)]['rmse_st']:.3e}), "
                 f"speed-up {t_pt_match / t:.2f}")
 
+    # (sigma_t r, g)-weighted training data: half the walks from the region
+    # the renders use (g near 0.8, sigma_t r above tau_min)
+    focus = None
+    if not args.no_focus:
+        log("focus-weighted training data")
+        fkw = dict(focus_fraction=0.5, focus_st_range=(args.tau_min, 200.0), focus_g_range=(0.7, 0.9))
+        pkf, _, tf = train_and_pack(M, torch, args.train_samples, args.train_steps, walk_kw=fkw)
+        focus = dict(fkw, train_seconds=tf)
+        for s in sigmas:
+            img, t = timed(lambda: st_render(s, 6101, packed=pkf[1]))
+            r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
+            s_star = pt[s]["var"] / r_st**2
+            focus[str(s)] = dict(ms=t * 1e3, rmse_st=r_st,
+                                 speedup_matched_rmse=s_star * npix / (pt[s]["paths"] / pt[s]["time"]) / t)
+            log(f"focus sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e}, speed-up "
+                f"{focus[str(s)]['speedup_matched_rmse']:.2f}")
+
+    # absorption sweep (the paper's absorption experiment): one density, the
+    # absorption 1 - albedo doubled from 2e-4; rendering time and error of
+    # both tracers at the same spp, matched-RMSE speed-up
+    absorption = None
+    if not args.no_absorption:
+        absorption = []
+        s_abs = args.absorption_sigma
+        for k in range(args.absorption_points):
+            a = 2e-4 * 2 ** k
+            med = dict(W.medium_c4(s_abs), albedo=1.0 - a)
+            img = rend.render(med, method=1, spp=args.ref_spp // 2, seed=7000 + k, **kw)
+            r_mean, r_var = image_moments(img, args.ref_spp // 2)
+            r_noise2 = float(r_var.mean()) / (args.ref_spp // 2)
+            img_pt, t_pt = timed(lambda: rend.render(med, method=1, spp=spp, seed=7100 + k, **kw))
+            pm, pv = image_moments(img_pt, spp)
+            img_st, t_st = timed(lambda: rend.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=7200 + k,
+                                                     tau_min=args.tau_min, nee_samples=args.nee_samples,
+                                                     flags=args.nee_flags, **kw))
+            sm, _ = image_moments(img_st, spp)
+            e_st = float(np.sqrt(max(float(((sm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+            e_pt = float(np.sqrt(max(float(((pm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+            s_star = float(pv.mean()) / e_st**2
+            row = dict(absorption=a, pt_ms=t_pt * 1e3, st_ms=t_st * 1e3, rmse_pt=e_pt, rmse_st=e_st,
+                       speedup_matched_rmse=s_star / spp * t_pt / t_st)
+            absorption.append(row)
+            log(f"absorption {a:.1e}: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {e_pt:.2e} / {e_st:.2e}, "
+                f"speed-up {row['speedup_matched_rmse']:.2f}")
+
     diag = None
     if args.diagnostics:
         diag = {}
@@ -345,8 +445,9 @@ def main():
     # roofline of the render kernel from the algorithmic VALU work of the timed step
     ops = counters[0] * OPS_PER_PATH + counters[1] * OPS_PER_EVENT + counters[2] * OPS_PER_STEP
     achieved = ops / (ms_per_step / 1e3)
+    traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANEOPS / 1e12,
-                "unit": "T lane-op/s", "frac": achieved / PEAK_VALU_LANEOPS, "traffic": None,
+                "unit": "T lane-op/s", "frac": achieved / PEAK_VALU_LANEOPS, "traffic": traffic,
                 "mfma_tflops": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / 1e12,
                 "mfma_frac": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / PEAK_MFMA_BF16}
 
@@ -379,6 +480,8 @@ def main():
         "cpu_baseline": cpu,
         "c5": c5,
         "table1": table1,
+        "absorption_sweep": absorption,
+        "focus_training": focus,
         "diagnostics": diag,
         "wall_s_timed": wall,
     }

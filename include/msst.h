@@ -104,6 +104,13 @@ typedef struct {
     double st_range[2], g_range[2], albedo_range[2];   /* TRAINING */
     uint32_t max_events;                               /* 0 = 2^20 */
     int32_t blocks_per_cu;                             /* launch shape, 0 = default */
+    /* TRAINING: (sigma_t r, g)-weighted data (Sec. 5.3 names over-weighting
+     * parameter regions as a lever for quality).  With probability
+     * focus_fraction (decided by the fourth uniform of the photon's parameter
+     * block) sigma_t r and g are drawn from the focus ranges instead, with
+     * the same uniforms; 0 disables it. */
+    double focus_fraction;
+    double focus_st_range[2], focus_g_range[2];
 } ms_walk_desc;
 
 /* Any pointer may be NULL.  Planar [3][n] for the 3-vectors. */

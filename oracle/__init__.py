@@ -42,7 +42,8 @@ class _WalkDesc(C.Structure):
                 ("sigma_t", C.c_double), ("g", C.c_double), ("albedo", C.c_double),
                 ("radius", C.c_double), ("st_range", C.c_double * 2), ("g_range", C.c_double * 2),
                 ("albedo_range", C.c_double * 2), ("max_events", C.c_uint32),
-                ("n_threads", C.c_int32)]
+                ("n_threads", C.c_int32), ("focus_fraction", C.c_double),
+                ("focus_st_range", C.c_double * 2), ("focus_g_range", C.c_double * 2)]
 
 
 class _WalkOut(C.Structure):
@@ -182,7 +183,8 @@ def scatter_dir(d, mu, azimuth):
 def random_walk(n_photons, seed=0, photon_offset=0, mode=WALK_ANALOG, sigma_t=10.0, g=0.8,
                 albedo=0.99, radius=1.0, st_range=(0.1, 200.0), g_range=(-0.9, 0.95),
                 albedo_range=(0.9, 1.0), event_weighting=EVENT_ALBEDO_POWER,
-                max_events=1 << 20, n_threads=None):
+                max_events=1 << 20, n_threads=None, focus_fraction=0.0, focus_st_range=(1.0, 1.0),
+                focus_g_range=(0.0, 0.0)):
     """Random walks from the centre of a sphere (Sec. 3.1); planar outputs."""
     n = int(n_photons)
     out = {
@@ -195,7 +197,8 @@ def random_walk(n_photons, seed=0, photon_offset=0, mode=WALK_ANALOG, sigma_t=10
     d = _WalkDesc(seed, photon_offset, n, mode, event_weighting, sigma_t, g, albedo, radius,
                   (C.c_double * 2)(*st_range), (C.c_double * 2)(*g_range),
                   (C.c_double * 2)(*albedo_range), max_events,
-                  n_threads if n_threads else default_threads())
+                  n_threads if n_threads else default_threads(), focus_fraction,
+                  (C.c_double * 2)(*focus_st_range), (C.c_double * 2)(*focus_g_range))
     o = _WalkOut(*[_p(out[k]) for k in ("params", "n_scatter", "event_index", "absorbed",
                                          "truncated", "exit_pos", "exit_dir", "exit_param",
                                          "event_pos", "event_dir")])

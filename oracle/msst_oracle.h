@@ -65,6 +65,10 @@ typedef struct {
     double st_range[2], g_range[2], albedo_range[2];
     uint32_t max_events;
     int32_t n_threads;
+    /* TRAINING: with probability focus_fraction (fourth uniform of the
+     * parameter block) sigma_t r and g come from the focus ranges */
+    double focus_fraction;
+    double focus_st_range[2], focus_g_range[2];
 } or_walk_desc;
 
 /* Planar (component-major) outputs, any pointer may be NULL. */

@@ -103,8 +103,17 @@ static void or_walk_one(const or_walk_desc* d, const or_walk_out* o, uint64_t i)
     if (d->mode == OR_WALK_TRAINING) {
         double u[4];
         or_uniform4(d->seed, OR_TAG_WALK_PARAM, id, 0, u);
-        st = d->st_range[0] * pow(d->st_range[1] / d->st_range[0], u[0]);
-        g = d->g_range[0] + (d->g_range[1] - d->g_range[0]) * u[1];
+        /* (sigma_t r, g)-weighted data (Sec. 5.3): the focus region with
+         * probability focus_fraction, decided exactly on the 24-bit integer
+         * k = U 2^24 against floor(focus_fraction 2^24) */
+        const double* sr = d->st_range;
+        const double* gr = d->g_range;
+        if (u[3] * 16777216.0 <= floor(d->focus_fraction * 16777216.0)) {
+            sr = d->focus_st_range;
+            gr = d->focus_g_range;
+        }
+        st = sr[0] * pow(sr[1] / sr[0], u[0]);
+        g = gr[0] + (gr[1] - gr[0]) * u[1];
         phi = d->albedo_range[0] + (d->albedo_range[1] - d->albedo_range[0]) * u[2];
         r = 1.0;
     } else {

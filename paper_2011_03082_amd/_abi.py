@@ -29,7 +29,8 @@ class WalkDesc(C.Structure):
                 ("mode", C.c_int32), ("event_weighting", C.c_int32),
                 ("sigma_t", C.c_double), ("g", C.c_double), ("albedo", C.c_double), ("radius", C.c_double),
                 ("st_range", C.c_double * 2), ("g_range", C.c_double * 2), ("albedo_range", C.c_double * 2),
-                ("max_events", C.c_uint32), ("blocks_per_cu", C.c_int32)]
+                ("max_events", C.c_uint32), ("blocks_per_cu", C.c_int32), ("focus_fraction", C.c_double),
+                ("focus_st_range", C.c_double * 2), ("focus_g_range", C.c_double * 2)]
 
 
 class WalkOut(C.Structure):

@@ -44,10 +44,12 @@ def ms_philox_fill(seed, tag, id0, n_ids, c0, n_draws, out, stream=None):
 # ---------------------------------------------------------------- walk
 def walk_desc(n_photons, seed=0, photon_offset=0, mode=_abi.WALK_ANALOG, sigma_t=10.0, g=0.8, albedo=0.99,
               radius=1.0, st_range=(0.1, 200.0), g_range=(-0.9, 0.95), albedo_range=(0.9, 1.0),
-              event_weighting=_abi.EVENT_ALBEDO_POWER, max_events=1 << 20, blocks_per_cu=0):
+              event_weighting=_abi.EVENT_ALBEDO_POWER, max_events=1 << 20, blocks_per_cu=0, focus_fraction=0.0,
+              focus_st_range=(1.0, 1.0), focus_g_range=(0.0, 0.0)):
     return _abi.WalkDesc(seed, photon_offset, n_photons, mode, event_weighting, sigma_t, g, albedo, radius,
                          (C.c_double * 2)(*st_range), (C.c_double * 2)(*g_range),
-                         (C.c_double * 2)(*albedo_range), max_events, blocks_per_cu)
+                         (C.c_double * 2)(*albedo_range), max_events, blocks_per_cu, focus_fraction,
+                         (C.c_double * 2)(*focus_st_range), (C.c_double * 2)(*focus_g_range))
 
 
 WALK_FIELDS = ("params", "n_scatter", "event_index", "absorbed", "truncated", "exit_pos", "exit_dir",
@@ -293,6 +295,17 @@ class Renderer:
         sphere_trace_render(self.scene, self.cam, self.light, make_medium(medium), desc, out, self.workspace(desc),
                             stream)
         return out
+
+    def render_rgb(self, media, method, seed=0, stream=None, **kw):
+        """RGB media: one medium (sigma_t, g, albedo) per colour channel.  Each
+        channel is traced with its own coefficients and Philox key seed + c,
+        so the three channels are independent estimates; the learned models
+        are shared (their conditions carry sigma_t r and the albedo).
+        Returns per-channel image planes stacked on a leading axis of 3."""
+        if len(media) != 3:
+            raise ValueError("render_rgb needs three media (R, G, B)")
+        planes = [self.render(media[c], method, seed=seed + c, stream=stream, **kw) for c in range(3)]
+        return {k: torch.stack([p[k] for p in planes]) for k in planes[0]}
 
 
 def column_moments(x):

@@ -16,6 +16,8 @@ struct WalkArgs {
     float sigma_t, g, albedo, radius, r2, st_report;
     uint32_t surv_thr;  // survive iff u24 <= floor(albedo 2^24)
     float st_lo, st_log2_ratio, g_lo, g_span, a_lo, a_span;
+    uint32_t focus_thr;  // focus iff u24 <= floor(focus_fraction 2^24); 0 = never
+    float fst_lo, fst_log2_ratio, fg_lo, fg_span;
     int32_t weighting;
     uint32_t max_events;
     float* params;
@@ -110,8 +112,10 @@ __global__ __launch_bounds__(256) void walk_kernel(const WalkArgs a) {
                     if (MODE == MS_WALK_TRAINING) {
                         const uint4 pw =
                             philox(0u, (uint32_t)id, (uint32_t)(id >> 32), MS_TAG_WALK_PARAM, rng.k0, rng.k1);
-                        st = a.st_lo * __builtin_amdgcn_exp2f(u01(pw.x) * a.st_log2_ratio);
-                        g = __builtin_fmaf(a.g_span, u01(pw.y), a.g_lo);
+                        const bool focus = u24(pw.w) <= a.focus_thr;
+                        st = (focus ? a.fst_lo : a.st_lo) *
+                             __builtin_amdgcn_exp2f(u01(pw.x) * (focus ? a.fst_log2_ratio : a.st_log2_ratio));
+                        g = __builtin_fmaf(focus ? a.fg_span : a.g_span, u01(pw.y), focus ? a.fg_lo : a.g_lo);
                         phi = __builtin_fmaf(a.a_span, u01(pw.z), a.a_lo);
                         inv_st = 1.0f / st;
                         inv_phi = 1.0f / phi;
@@ -229,6 +233,14 @@ ms_status ms_random_walk(const ms_walk_desc* desc, const ms_walk_out* out, void*
                    "ms_random_walk: g_range must satisfy -1 < lo <= hi < 1");
         MS_REQUIRE(d.albedo_range[0] > 0.0 && d.albedo_range[1] >= d.albedo_range[0] && d.albedo_range[1] <= 1.0,
                    "ms_random_walk: albedo_range must satisfy 0 < lo <= hi <= 1");
+        MS_REQUIRE(d.focus_fraction >= 0.0 && d.focus_fraction <= 1.0, "ms_random_walk: focus_fraction must be in [0, 1]");
+        if (d.focus_fraction > 0.0) {
+            MS_REQUIRE(d.focus_st_range[0] > 0.0 && d.focus_st_range[1] >= d.focus_st_range[0] &&
+                           d.focus_st_range[1] < 1e30,
+                       "ms_random_walk: focus_st_range must satisfy 0 < lo <= hi");
+            MS_REQUIRE(d.focus_g_range[0] > -1.0 && d.focus_g_range[1] >= d.focus_g_range[0] && d.focus_g_range[1] < 1.0,
+                       "ms_random_walk: focus_g_range must satisfy -1 < lo <= hi < 1");
+        }
     }
     MS_REQUIRE(workspace_dev != nullptr && workspace_bytes >= 256,
                "ms_random_walk: workspace of at least 256 bytes required");
@@ -255,6 +267,13 @@ ms_status ms_random_walk(const ms_walk_desc* desc, const ms_walk_out* out, void*
     a.g_span = (float)(d.g_range[1] - d.g_range[0]);
     a.a_lo = (float)d.albedo_range[0];
     a.a_span = (float)(d.albedo_range[1] - d.albedo_range[0]);
+    a.focus_thr = (uint32_t)floor(d.focus_fraction * 16777216.0);
+    if (d.focus_fraction > 0.0) {
+        a.fst_lo = (float)d.focus_st_range[0];
+        a.fst_log2_ratio = (float)log2(d.focus_st_range[1] / d.focus_st_range[0]);
+        a.fg_lo = (float)d.focus_g_range[0];
+        a.fg_span = (float)(d.focus_g_range[1] - d.focus_g_range[0]);
+    }
     a.weighting = d.event_weighting;
     a.max_events = d.max_events ? d.max_events : (1u << 20);
     a.params = out->params;

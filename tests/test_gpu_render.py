@@ -315,3 +315,25 @@ def test_c5_learned_path_by_path(msst, oracle, precision):
     print(f"diverged {frac:.2e}; steps {o['steps'].sum()}")
     assert o["steps"].sum() > 50
     assert frac < 0.05
+
+
+def test_rgb_media_channel_by_channel(msst, oracle):
+    """RGB media: each channel traced with its own sigma_t and albedo and the
+    Philox key seed + c, path by path against the oracle with the same keys."""
+    announce("render RGB media")
+    prims, cam, light, _ = c4_inputs(20.0, 24)
+    media = [f32_medium(dict(sigma_t=s, g=0.8, albedo=a)) for s, a in ((10.0, 0.999), (20.0, 0.995), (40.0, 0.99))]
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src, 1)
+    r = msst.Renderer(prims, cam, light)
+    out = r.render_rgb(media, method=ST, sampler=CVAE, packed=packed, spp=1, seed=31, tau_min=2.0)
+    torch.cuda.synchronize()
+    assert out["sum"].shape[0] == 3
+    for c in range(3):
+        g = {k: v[c].cpu().numpy() for k, v in out.items() if k != "counters"}
+        o = oracle.render(oracle.Scene(prims), cam, light, media[c], method=oracle.METHOD_ST,
+                          sampler=oracle.SAMPLER_CVAE, precision=oracle.PREC_BF16, models=models, spp=1,
+                          seed=31 + c, tau_min=2.0)
+        frac, _ = compare_paths(g, o, rel=2e-3)
+        print(f"channel {c}: diverged {frac:.2e}, mean {o['sum'].mean():.4e}")
+        assert frac < 0.03

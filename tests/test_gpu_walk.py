@@ -154,3 +154,19 @@ def test_training_full_size_sampled_and_ks(msst, oracle):
     assert D < 0.01
     c = out["counters"].cpu().numpy()
     assert c[0] == nsc.astype(np.int64).sum() and c[2] == out["truncated"].sum().item()
+
+
+def test_focus_weighted_parameters_and_paths(msst, oracle):
+    """(sigma_t r, g)-weighted training data: the same focus decisions and
+    parameters as the oracle, and the walks that follow them."""
+    announce("walk training with a focus region")
+    n = 1 << 14
+    kw = dict(focus_fraction=0.4, focus_st_range=(2.0, 8.0), focus_g_range=(0.6, 0.9))
+    g, o = training_parity(msst, oracle, n, seed=4, event_weighting=0, **kw)
+    np.testing.assert_allclose(g["params"][0], o["params"][0], rtol=2e-6)
+    np.testing.assert_allclose(g["params"][1:], o["params"][1:], rtol=0, atol=1e-6)
+    st, gg = o["params"][0], o["params"][1]
+    inside = (st >= 2.0) & (st <= 8.0) & (gg >= 0.6) & (gg <= 0.9)
+    assert inside.mean() > 0.4
+    same = (g["n_scatter"].astype(np.int64) == o["n_scatter"]) & (g["event_index"].astype(np.int64) == o["event_index"])
+    assert 1 - same[st < 20].mean() < 1e-3

@@ -217,3 +217,29 @@ def test_training_parameter_ranges(oracle):
     assert stats.kstest((g + 0.9) / 1.85, "uniform").pvalue > 1e-4
     assert stats.kstest((phi - 0.9) / 0.1, "uniform").pvalue > 1e-4
     assert st.min() > 0.1 and st.max() <= 200.0
+
+
+def test_focus_weighted_training_parameters(oracle):
+    """(sigma_t r, g)-weighted data: with probability f the parameters come
+    from the focus box, so the box holds a fraction f + (1 - f) P_main(box)
+    of the photons; f = 0 leaves the draws unchanged; f = 1 is the focus
+    ranges' own log-uniform / uniform law."""
+    n = 40000
+    kw = dict(seed=23, mode=oracle.WALK_TRAINING, focus_st_range=(10.0, 20.0), focus_g_range=(0.7, 0.9),
+              max_events=64)
+    base = oracle.random_walk(n, **dict(kw, focus_fraction=0.0))
+    plain = oracle.random_walk(n, seed=23, mode=oracle.WALK_TRAINING, max_events=64)
+    np.testing.assert_array_equal(base["params"], plain["params"])
+    f = 0.3
+    t = oracle.random_walk(n, **dict(kw, focus_fraction=f))
+    st, g, phi = t["params"]
+    inside = (st >= 10.0) & (st <= 20.0) & (g >= 0.7) & (g <= 0.9)
+    p_main = np.log(2.0) / np.log(2000.0) * 0.2 / 1.85
+    p = f + (1 - f) * p_main
+    z = (inside.mean() - p) / np.sqrt(p * (1 - p) / n)
+    assert abs(z) < 5, (inside.mean(), p)
+    np.testing.assert_array_equal(phi, base["params"][2])  # the albedo draw is untouched
+    full = oracle.random_walk(n, **dict(kw, focus_fraction=1.0))
+    st1, g1, _ = full["params"]
+    assert stats.kstest(np.log(st1 / 10.0) / np.log(2.0), "uniform").pvalue > 1e-4
+    assert stats.kstest((g1 - 0.7) / 0.2, "uniform").pvalue > 1e-4
