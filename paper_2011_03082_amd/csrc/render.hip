@@ -30,6 +30,14 @@ constexpr float kTwoPiRev = 1.0f;  // angles are passed in revolutions
 // step (WAIT), path finished and not yet banked (END), no work left (DONE).
 enum : int { S_IDLE = 0, S_FLY = 2, S_WAIT = 3, S_DONE = 4, S_END = 5 };
 
+// Result of one work unit (one pixel, `chunk` consecutive samples): the
+// compensated radiance sum folded to binary32, the sum of squares and the
+// event / learned-step counts, written with one 16-byte store.
+struct alignas(16) UnitRecord {
+    float sum, sumsq;
+    uint32_t events, steps;
+};
+
 struct RenderArgs {
     const float* prims;  // device [n_prims][8]
     int n_prims;
@@ -53,11 +61,7 @@ struct RenderArgs {
     int restart_min;
     int nee_samples;
     int flags;
-    float* part_sum;
-    float* part_comp;
-    float* part_sq;
-    uint32_t* part_events;
-    uint32_t* part_steps;
+    UnitRecord* part;  // [n_units], unit = pixel * n_chunks + chunk
     unsigned long long* ticket;
     unsigned long long* counters;
 };
@@ -70,9 +74,9 @@ struct Prims {
 };
 
 struct RenderLds {
-    float x[64][kTile];  // decoder inputs of the compacted lanes
-    float o[64][kTile];  // decoder outputs
-    float eps[64][8];    // decoder posterior noise of each compacted lane
+    float x[64][kTile];  // decoder input rows of the compacted lanes; outputs overwrite them
+    float eps[64][8];    // decoder posterior noise of each row
+    uint4 rid[64];       // Philox stream (id_lo, id_hi) and first block of each row's normals
 };
 
 enum : int { kModePlain = 0, kModeStExact = 1, kModeStCvae = 2 };
@@ -350,17 +354,43 @@ __device__ __forceinline__ float lambda_weight(const RenderArgs& A, float N) {
     return fast_div(A.albedo * (fast_exp(-N * A.ln_albedo) - 1.0f), 1.0f - A.albedo);
 }
 
-// Writes this lane's decoder input row: `latent` normals (z) from Philox
-// blocks, then the standardised condition; keeps the posterior noise (the
-// next PO normals) in LDS.  Normals come four per block in Box-Muller pairs.
+// Writes this lane's part of its decoder input row -- the standardised
+// condition after `latent` slots, zero padding -- and the Philox stream and
+// first block of its normals; advances the lane's block counter past them.
 template <int PO, int PI>
-__device__ __forceinline__ void stage_input(const PackedModel* pm, RenderLds& L, int slot, const Rng& rng,
-                                            uint32_t& c0, const float* cond) {
+__device__ __forceinline__ void stage_row(const PackedModel* pm, RenderLds& L, int slot, const Rng& rng,
+                                          uint32_t& c0, const float* cond) {
     const int lat = pm->latent;
-    const int n_norm = lat + PO;
     float* row = L.x[slot];
-    for (int j = 0; 4 * j < n_norm; ++j) {
-        const uint4 w = rng.block(c0++);
+#pragma unroll
+    for (int k = 0; k < PI; ++k) row[lat + k] = (cond[k] - pm->mean_c[k]) * pm->inv_std_c[k];
+    for (int q = lat + PI; q < kTile; ++q) row[q] = 0.0f;
+    L.rid[slot] = make_uint4(rng.id_lo, rng.id_hi, c0, 0u);
+    c0 += (uint32_t)((lat + PO + 3) >> 2);
+}
+
+// q / nb for q < 2^15 and nb in 1 .. 4.
+__device__ __forceinline__ int div_small(int q, int nb) {
+    return nb == 1 ? q : nb == 2 ? q >> 1 : nb == 4 ? q >> 2 : (q * 0xAAAB) >> 17;
+}
+
+// The normals of the n staged rows, drawn by the whole wave: row s needs
+// blocks rid[s].z .. rid[s].z + nb - 1 of its own Philox stream; the
+// (row, block) tasks are spread over the 64 lanes.  Box-Muller pairs give
+// four normals per block: the first `latent` are the row's z, the next PO its
+// posterior noise -- the same values, in the same order, as if each lane drew
+// its own.
+template <int PO>
+__device__ __forceinline__ void stage_normals(const RenderArgs& A, const PackedModel* pm, RenderLds& L, int n) {
+    wave_sync();
+    const int lat = pm->latent, n_norm = lat + PO, nb = (n_norm + 3) >> 2;
+    const int total = n * nb;
+    const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+    for (int task = lane_id(); task < total; task += 64) {
+        const int slot = div_small(task, nb);
+        const int j = task - slot * nb;
+        const uint4 r = L.rid[slot];
+        const uint4 w = philox(r.z + (uint32_t)j, r.x, r.y, MS_TAG_RENDER_PATH, k0, k1);
         float nv[4];
         box_muller(u01(w.x), u01(w.y), nv[0], nv[1]);
         box_muller(u01(w.z), u01(w.w), nv[2], nv[3]);
@@ -368,14 +398,11 @@ __device__ __forceinline__ void stage_input(const PackedModel* pm, RenderLds& L,
         for (int q = 0; q < 4; ++q) {
             const int i = 4 * j + q;
             if (i < lat)
-                row[i] = nv[q];
+                L.x[slot][i] = nv[q];
             else if (i < n_norm)
                 L.eps[slot][i - lat] = nv[q];
         }
     }
-#pragma unroll
-    for (int k = 0; k < PI; ++k) row[lat + k] = (cond[k] - pm->mean_c[k]) * pm->inv_std_c[k];
-    for (int q = lat + PI; q < kTile; ++q) row[q] = 0.0f;
 }
 
 // Runs one decoder over the first n compacted rows (16-path MFMA tiles) and
@@ -392,22 +419,23 @@ __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L,
         for (int t = 0; t < n_tiles; ++t) {
             const int path = 16 * t + frag_row();
             const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
+            // each lane rewrites exactly the 16 bytes it read (B and D layouts coincide)
             const f32x4 o = fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
-            *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+            *reinterpret_cast<f32x4*>(&L.x[path][frag_k0()]) = o;
         }
     } else {
         for (int t = 0; t < n_tiles; ++t) {
             const int path = 16 * t + frag_row();
             const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-            *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = decoder_tile_layers(pm, xin);
+            *reinterpret_cast<f32x4*>(&L.x[path][frag_k0()]) = decoder_tile_layers(pm, xin);
         }
     }
     wave_sync();
     if (mine) {
 #pragma unroll
         for (int k = 0; k < PO; ++k) {
-            const float mu = L.o[slot][k];
-            const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.o[slot][PO + k]));
+            const float mu = L.x[slot][k];
+            const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.x[slot][PO + k]));
             const float ys = __builtin_fmaf(fast_exp(0.5f * lv), L.eps[slot][k], mu);
             y[k] = __builtin_fmaf(ys, pm->std_y[k], pm->mean_y[k]);
         }
@@ -467,11 +495,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 cnt_trunc += p_trunc;
                 ++s;
                 if (s >= s_end) {
-                    A.part_sum[unit] = acc_sum;
-                    A.part_comp[unit] = acc_comp;
-                    A.part_sq[unit] = acc_sq;
-                    A.part_events[unit] = acc_ev;
-                    A.part_steps[unit] = acc_st;
+                    UnitRecord rec;
+                    rec.sum = acc_sum + acc_comp;
+                    rec.sumsq = acc_sq;
+                    rec.events = acc_ev;
+                    rec.steps = acc_st;
+                    A.part[unit] = rec;
                     state = S_IDLE;
                 } else {
                     start = true;
@@ -482,11 +511,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
             if (need) {
                 if (tk < (uint64_t)A.n_units) {
                     unit = (int64_t)tk;
-                    const int64_t ch = unit / A.npix;
-                    const int pixel = (int)(unit - ch * A.npix);
+                    // pixel-major: a wave's block of tickets covers few pixels
+                    const int pixel = (int)(unit / A.n_chunks);
+                    const int ch = (int)(unit - (int64_t)pixel * A.n_chunks);
                     py = pixel / A.width;
                     px = pixel - py * A.width;
-                    s = (int)ch * A.chunk;
+                    s = ch * A.chunk;
                     s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
                     acc_sum = acc_comp = acc_sq = 0.0f;
                     acc_ev = acc_st = 0;
@@ -624,8 +654,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 const int slot0 = rank_in(wmask);
                 if (mine) {
                     const float c2[2] = {lst, A.g};
-                    stage_input<1, 2>(A.pm[0], L, slot0, rng, c0, c2);
+                    stage_row<1, 2>(A.pm[0], L, slot0, rng, c0, c2);
                 }
+                stage_normals<1>(A, A.pm[0], L, n_wait);
                 decode_rows<1>(A.pm[0], L, mine, slot0, n_wait, y);
                 bool alive = false;
                 float u_hg = 0.5f, u_first = 1.0f, phiN = 1.0f;
@@ -662,8 +693,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                     // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
                     if (use_path) {
                         const float c3[3] = {lst, A.g, lnN};
-                        stage_input<3, 3>(A.pm[1], L, slot, rng, c0, c3);
+                        stage_row<3, 3>(A.pm[1], L, slot, rng, c0, c3);
                     }
+                    stage_normals<3>(A, A.pm[1], L, __popcll(pmask));
                     decode_rows<3>(A.pm[1], L, use_path, slot, __popcll(pmask), y);
                     if (use_path) {
                         ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
@@ -694,8 +726,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
                         if (use_event) {
                             const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-                            stage_input<6, 7>(A.pm[2], L, slot, rng, c0, c7);
+                            stage_row<6, 7>(A.pm[2], L, slot, rng, c0, c7);
                         }
+                        stage_normals<6>(A, A.pm[2], L, __popcll(emask));
                         decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
                         if (use_event) {
                             X = v3(y[0], y[1], y[2]);
@@ -749,33 +782,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 
 // Per-pixel fixed-order reduction of the unit partials, added to the image
 // with the compensation carried in the comp buffer.
-__global__ void render_reduce_kernel(int64_t npix, int n_chunks, const float* part_sum, const float* part_comp,
-                                     const float* part_sq, const uint32_t* part_events, const uint32_t* part_steps,
-                                     float* sum, float* comp, float* sumsq, uint32_t* events, uint32_t* steps,
+// One wave per pixel: lane c adds the records of chunks c, c + 64, ... in
+// order (coalesced 16-byte loads), then a fixed butterfly combines the lanes,
+// so the result depends only on n_chunks.
+__global__ void render_reduce_kernel(int64_t npix, int n_chunks, const UnitRecord* part, float* sum, float* comp,
+                                     float* sumsq, uint32_t* events, uint32_t* steps,
                                      const unsigned long long* bad_models) {
+    const int64_t wave0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = lane_id();
     if (*bad_models) {
         // invalid packed models: no path was traced; poison the image
-        for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
-            sum[p] = __builtin_nanf("");
+        for (int64_t p = wave0; p < npix; p += n_waves)
+            if (lane == 0) sum[p] = __builtin_nanf("");
         return;
     }
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x) {
-        double s = (double)sum[p] + (comp ? (double)comp[p] : 0.0);
-        double q = sumsq ? (double)sumsq[p] : 0.0;
-        uint32_t ev = events ? events[p] : 0u, st = steps ? steps[p] : 0u;
-        for (int c = 0; c < n_chunks; ++c) {
-            const int64_t u = (int64_t)c * npix + p;
-            s += (double)part_sum[u] + (double)part_comp[u];
-            q += (double)part_sq[u];
-            ev += part_events[u];
-            st += part_steps[u];
+    for (int64_t p = wave0; p < npix; p += n_waves) {
+        const UnitRecord* r = part + p * n_chunks;
+        double s = 0.0, q = 0.0;
+        uint32_t ev = 0, st = 0;
+        for (int c = lane; c < n_chunks; c += 64) {
+            const UnitRecord u = r[c];
+            s += (double)u.sum;
+            q += (double)u.sumsq;
+            ev += u.events;
+            st += u.steps;
         }
-        const float sf = (float)s;
-        sum[p] = sf;
-        if (comp) comp[p] = (float)(s - (double)sf);
-        if (sumsq) sumsq[p] = (float)q;
-        if (events) events[p] = ev;
-        if (steps) steps[p] = st;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            s += __shfl_xor(s, off);
+            q += __shfl_xor(q, off);
+            ev += __shfl_xor(ev, off);
+            st += __shfl_xor(st, off);
+        }
+        if (lane == 0) {
+            s += (double)sum[p] + (comp ? (double)comp[p] : 0.0);
+            if (sumsq) q += (double)sumsq[p];
+            if (events) ev += events[p];
+            if (steps) st += steps[p];
+            const float sf = (float)s;
+            sum[p] = sf;
+            if (comp) comp[p] = (float)(s - (double)sf);
+            if (sumsq) sumsq[p] = (float)q;
+            if (events) events[p] = ev;
+            if (steps) steps[p] = st;
+        }
     }
 }
 
@@ -868,7 +919,7 @@ ms_status sphere_trace_render_workspace_size(const ms_camera* cam, const ms_rend
                                       : default_chunk((int64_t)cam->width * cam->height, desc->spp);
     const int64_t n_chunks = (desc->spp + chunk - 1) / chunk;
     const int64_t n_units = (int64_t)cam->width * cam->height * n_chunks;
-    *bytes = 256 + align_up((size_t)n_units * 4, 256) * 5;
+    *bytes = 256 + align_up((size_t)n_units * sizeof(UnitRecord), 256);
     return MS_OK;
 }
 
@@ -966,19 +1017,14 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.seed = desc->seed;
     A.sample_offset = desc->sample_offset;
     A.max_events = desc->max_events ? desc->max_events : (1u << 20);
-    A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 32;
+    A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 20;
     A.nee_samples = desc->nee_samples ? desc->nee_samples : 1;
     A.restart_min = desc->restart_min ? desc->restart_min : 16;
     A.flags = desc->flags;
     char* ws = reinterpret_cast<char*>(workspace_dev);
     A.ticket = reinterpret_cast<unsigned long long*>(ws);
     unsigned long long* flag = A.ticket + 1;
-    const size_t plane = align_up((size_t)A.n_units * 4, 256);
-    A.part_sum = reinterpret_cast<float*>(ws + 256);
-    A.part_comp = reinterpret_cast<float*>(ws + 256 + plane);
-    A.part_sq = reinterpret_cast<float*>(ws + 256 + 2 * plane);
-    A.part_events = reinterpret_cast<uint32_t*>(ws + 256 + 3 * plane);
-    A.part_steps = reinterpret_cast<uint32_t*>(ws + 256 + 4 * plane);
+    A.part = reinterpret_cast<UnitRecord*>(ws + 256);
     A.counters = reinterpret_cast<unsigned long long*>(out->counters);
 
     hipStream_t hs = (hipStream_t)stream;
@@ -1016,11 +1062,10 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     }
 #undef MS_RENDER_LAUNCH
     MS_LAUNCHED();
-    int64_t rb = (A.npix + 255) / 256;
-    if (rb > cus * 8) rb = cus * 8;
-    hipLaunchKernelGGL(render_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, hs, A.npix, A.n_chunks, A.part_sum,
-                       A.part_comp, A.part_sq, A.part_events, A.part_steps, out->sum, out->comp, out->sumsq,
-                       out->events, out->steps, flag);
+    int64_t rb = (A.npix + 3) / 4;  // four pixels (waves) per block
+    if (rb > cus * 16) rb = cus * 16;
+    hipLaunchKernelGGL(render_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, hs, A.npix, A.n_chunks, A.part,
+                       out->sum, out->comp, out->sumsq, out->events, out->steps, flag);
     MS_LAUNCHED();
     clear_error();
     return MS_OK;
