@@ -27,6 +27,7 @@ OPS_PER_PATH = 220.0         # camera ray, primary intervals, path bookkeeping
 OPS_PER_EVENT = 380.0        # one plain collision: Philox block, flight, NEE, roulette, HG, new ray
 OPS_PER_STEP = 2750.0        # one learned sphere step on VALU (the MFMA part is separate)
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
+OPS_PER_WALK_EVENT = 190.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
 PEAK_MFMA_BF16 = 2.5e15
 
@@ -80,16 +81,24 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, 
 
 
 def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), shapes=None,
-                   walk_kw=None):
+                   walk_kw=None, timing=None):
     """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
 
     The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
     steps (a guard against decoders that ignore the latent).  Returns
     ({precision: [three packed models]}, per-model losses, seconds).  shapes:
     three architecture dicts (default: width 16, three linear maps, latent 4);
-    walk_kw: extra training-walk options (e.g. a focus region)."""
+    walk_kw: extra training-walk options (e.g. a focus region); timing: a dict
+    that receives the walk's and the training steps' GPU times."""
     t0 = time.time()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     walk = M.random_walk(n_samples, seed=seed, mode=1, **(walk_kw or {}))
+    e1.record()
+    torch.cuda.synchronize()
+    if timing is not None:
+        c = walk["counters"].cpu().numpy()
+        timing["walk"] = dict(photons=n_samples, events=int(c[0]), seconds=e0.elapsed_time(e1) / 1e3)
     packs, losses = {p: [] for p in precisions}, []
     for model in range(3):
         p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
@@ -110,6 +119,8 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
         ws = torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda")
         loss = torch.zeros(3, dtype=torch.float64, device="cuda")
         first = None
+        t_model = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_model[0].record()
         for step in range(1, steps + 1):
             lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
             beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
@@ -117,7 +128,10 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
                               seed + 20 + model, step, 0, ws, loss, kl_weight=beta)
             if step == 1:
                 first = loss.cpu().numpy().copy()
+        t_model[1].record()
         last = loss.cpu().numpy().copy()
+        if timing is not None:
+            timing.setdefault("train_step_us", []).append(t_model[0].elapsed_time(t_model[1]) * 1e3 / steps)
         for p in precisions:
             pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
             M.cvae_pack(shape, master, stats, p, pk)
@@ -290,7 +304,9 @@ def main():
         del src, dst
 
     log("training CVAEs on GPU random-walk data")
-    packs, losses, t_train = train_and_pack(M, torch, args.train_samples, args.train_steps, precisions=(1, 2))
+    tim = {}
+    packs, losses, t_train = train_and_pack(M, torch, args.train_samples, args.train_steps, precisions=(1, 2),
+                                            timing=tim)
     packed = packs[1]
 
     # plain reference (debiased by its own noise) and plain timing per density
@@ -475,7 +491,12 @@ def main():
         "plain_paths_per_s": pt_rate,
         "speedup_matched_rmse": tot_pt / tot_st,
         "per_sigma": details,
-        "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps},
+        "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps,
+                  "step_us_per_model": tim.get("train_step_us"),
+                  "samples_per_s_per_model": [4096 / (us * 1e-6) for us in tim.get("train_step_us", [])]},
+        "walk": dict(tim["walk"], events_per_s=tim["walk"]["events"] / tim["walk"]["seconds"],
+                     roofline_frac=tim["walk"]["events"] * OPS_PER_WALK_EVENT / tim["walk"]["seconds"] / PEAK_VALU_LANEOPS,
+                     workload="training walks (sigma_t r log-uniform [0.1, 200], g U[-0.9, 0.95], albedo U[0.9, 1])"),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "c5": c5,

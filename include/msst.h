@@ -298,6 +298,7 @@ typedef struct {
     int32_t blocks_per_cu;   /* launch shape; 0 = default */
     int32_t cvae_batch_min;  /* waiting lanes that trigger a decoder pass; 0 = default */
     int32_t restart_min;     /* lanes waiting for a new path that trigger a restart pass, 1..64; 0 = default */
+    int32_t max_wait;        /* loop iterations after which waiting lanes force a pass anyway; 0 = default */
     int32_t nee_samples;     /* representative events per learned step, 1..16 (0 = 1) */
     int32_t flags;           /* MS_RENDER_NEE_BEFORE_ABSORPTION */
 } ms_render_desc;

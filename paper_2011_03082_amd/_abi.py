@@ -70,7 +70,7 @@ class RenderDesc(C.Structure):
     _fields_ = [("method", C.c_int32), ("sampler", C.c_int32), ("packed", C.c_void_p * 3),
                 ("tau_min", C.c_float), ("st_max", C.c_float), ("spp", C.c_int32), ("chunk", C.c_int32),
                 ("seed", C.c_uint64), ("sample_offset", C.c_uint64), ("max_events", C.c_uint32),
-                ("blocks_per_cu", C.c_int32), ("cvae_batch_min", C.c_int32), ("restart_min", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("cvae_batch_min", C.c_int32), ("restart_min", C.c_int32), ("max_wait", C.c_int32),
                 ("nee_samples", C.c_int32),
                 ("flags", C.c_int32)]
 

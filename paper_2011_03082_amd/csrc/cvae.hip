@@ -264,15 +264,14 @@ __device__ __forceinline__ f32x4 bias_d(const float* layer) {
 // units at or beyond `width` do not exist: their activations are forced to 0,
 // so their (zero-initialised) weights and biases receive zero gradients.
 template <int FIRST, int NL>
-__device__ __forceinline__ f32x4 net_forward(const float* master, WaveLds& L, f32x4* pre, int width) {
+__device__ __forceinline__ f32x4 net_forward(const bf16x4* wf, const f32x4* bs, WaveLds& L, f32x4* pre, int width) {
     constexpr int first = FIRST, nl = NL;
     const int k0 = frag_k0();
     f32x4 acc;
 #pragma unroll
     for (int j = 0; j < nl; ++j) {
-        const float* layer = master + (first + j) * kLayerFloats;
         const bf16x4 x = to_bf16x4(tile_load_d(L.act[first + j]));
-        acc = mfma_bf16(w_frag(layer), x, bias_d(layer));
+        acc = mfma_bf16(wf[first + j], x, bs[first + j]);
         pre[first + j] = acc;
         if (j < nl - 1) {
             f32x4 a;
@@ -289,14 +288,13 @@ __device__ __forceinline__ f32x4 net_forward(const float* master, WaveLds& L, f3
 // Accumulates dW (D layout: row = output unit, column = input unit) and db,
 // and returns d loss / d (input of the first layer) in D layout.
 template <int FIRST, int NL>
-__device__ __forceinline__ f32x4 net_backward(const float* master, WaveLds& L, const f32x4* pre, f32x4 dpre,
+__device__ __forceinline__ f32x4 net_backward(const bf16x4* wt, WaveLds& L, const f32x4* pre, f32x4 dpre,
                                               f32x4* dw, f32x4* db) {
     constexpr int first = FIRST, nl = NL;
     f32x4 dx = f32x4{0, 0, 0, 0};
 #pragma unroll
     for (int j = nl - 1; j >= 0; --j) {
         const int layer = first + j;
-        const float* wl = master + layer * kLayerFloats;
         db[layer] += dpre;
         // dW += dPre X^T: both operands read transposed from LDS
         tile_store_d(L.work[0], f32x4{bf16_round(dpre[0]), bf16_round(dpre[1]), bf16_round(dpre[2]),
@@ -307,7 +305,7 @@ __device__ __forceinline__ f32x4 net_backward(const float* master, WaveLds& L, c
         dw[layer] = mfma_bf16(a, b, dw[layer]);
         wave_sync();
         // dX = W^T dPre
-        dx = mfma_bf16(wt_frag(wl), to_bf16x4(dpre), f32x4{0, 0, 0, 0});
+        dx = mfma_bf16(wt[layer], to_bf16x4(dpre), f32x4{0, 0, 0, 0});
         if (j > 0) {
             const f32x4 p = pre[layer - 1];
 #pragma unroll
@@ -328,6 +326,17 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
     const int lane = lane_id();
     const float inv_b = 1.0f / (float)a.batch;
 
+    // all layers' weight fragments (both orientations) and biases of this
+    // lane, loaded once: the tile loop is a chain of dependent steps
+    bf16x4 wf[2 * NL], wt[2 * NL];
+    f32x4 bs[2 * NL];
+#pragma unroll
+    for (int i = 0; i < 2 * NL; ++i) {
+        const float* layer = a.master + i * kLayerFloats;
+        wf[i] = w_frag(layer);
+        wt[i] = wt_frag(layer);
+        bs[i] = bias_d(layer);
+    }
     f32x4 dw[2 * NL], db[2 * NL], pre[2 * NL];
 #pragma unroll
     for (int i = 0; i < 2 * NL; ++i) {
@@ -363,7 +372,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
         }
         wave_sync();
         // encoder
-        const f32x4 oe = net_forward<0, NL>(a.master, L, pre, s.width);
+        const f32x4 oe = net_forward<0, NL>(wf, bs, L, pre, s.width);
         tile_store_d(L.work[0], oe);
         wave_sync();
         if (lane < 16) {
@@ -382,7 +391,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
         }
         wave_sync();
         // decoder
-        const f32x4 od = net_forward<NL, NL>(a.master, L, pre, s.width);
+        const f32x4 od = net_forward<NL, NL>(wf, bs, L, pre, s.width);
         tile_store_d(L.work[0], od);
         for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
         wave_sync();
@@ -406,7 +415,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             nll_acc += (double)nll;
         }
         wave_sync();
-        const f32x4 dzc = net_backward<NL, NL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
+        const f32x4 dzc = net_backward<NL, NL>(wt, L, pre, tile_load_d(L.work[1]), dw, db);
         tile_store_d(L.work[0], dzc);
         for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
         wave_sync();
@@ -421,7 +430,7 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             }
         }
         wave_sync();
-        net_backward<0, NL>(a.master, L, pre, tile_load_d(L.work[1]), dw, db);
+        net_backward<0, NL>(wt, L, pre, tile_load_d(L.work[1]), dw, db);
         wave_sync();
     }
 
@@ -493,11 +502,29 @@ struct AdamArgs {
     float lr, beta1, beta2, one_m_beta1, one_m_beta2, eps, wd, bc1, bc2;
 };
 
-__global__ void cvae_adam_kernel(const AdamArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// Gradient = sum of the per-block partials, then the AdamW update.  The sum
+// over blocks is latency-bound (one dependent load per block), so each block
+// of this kernel takes 32 parameters x 8 groups of partial blocks: group q adds
+// blocks q, q + 8, ... with its loads in flight together, and the 8 group sums
+// are added in fixed order.  The loss partials are reduced by wave 0 of block 0
+// with a fixed butterfly.
+constexpr int kAdamParams = 32, kAdamGroups = 8;
+
+__global__ __launch_bounds__(256) void cvae_adam_kernel(const AdamArgs a) {
+    __shared__ float red[kAdamGroups][kAdamParams];
+    const int pl = threadIdx.x % kAdamParams, grp = threadIdx.x / kAdamParams;
+    const int p = blockIdx.x * kAdamParams + pl;
+    float part = 0.0f;
     if (p < a.n_params) {
+#pragma unroll 8
+        for (int b = grp; b < a.n_blocks; b += kAdamGroups) part += a.partial[(int64_t)b * a.n_params + p];
+    }
+    red[grp][pl] = part;
+    __syncthreads();
+    if (grp == 0 && p < a.n_params) {
         float g = 0.0f;
-        for (int b = 0; b < a.n_blocks; ++b) g += a.partial[(int64_t)b * a.n_params + p];
+#pragma unroll
+        for (int q = 0; q < kAdamGroups; ++q) g += red[q][pl];
         if (a.grad_out) a.grad_out[p] = g;
         if (a.do_update) {
             const float m = a.beta1 * a.m[p] + a.one_m_beta1 * g;
@@ -509,15 +536,22 @@ __global__ void cvae_adam_kernel(const AdamArgs a) {
             a.master[p] = th - a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * th);
         }
     }
-    if (p == 0 && a.loss_out) {
+    if (blockIdx.x == 0 && threadIdx.x < 64 && a.loss_out) {
         double k = 0.0, n = 0.0;
-        for (int b = 0; b < a.n_blocks; ++b) {
+        for (int b = threadIdx.x; b < a.n_blocks; b += 64) {
             k += a.loss_partial[b * 2 + 0];
             n += a.loss_partial[b * 2 + 1];
         }
-        a.loss_out[0] = (k + n) / a.batch;
-        a.loss_out[1] = k / a.batch;
-        a.loss_out[2] = n / a.batch;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            k += __shfl_xor(k, off);
+            n += __shfl_xor(n, off);
+        }
+        if (threadIdx.x == 0) {
+            a.loss_out[0] = (k + n) / a.batch;
+            a.loss_out[1] = k / a.batch;
+            a.loss_out[2] = n / a.batch;
+        }
     }
 }
 
@@ -887,7 +921,7 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
         aa.bc1 = (float)(1.0 - pow(adam->beta1, (double)adam->step));
         aa.bc2 = (float)(1.0 - pow(adam->beta2, (double)adam->step));
     }
-    hipLaunchKernelGGL(cvae_adam_kernel, dim3((n_params + 255) / 256), dim3(256), 0, hs, aa);
+    hipLaunchKernelGGL(cvae_adam_kernel, dim3((n_params + kAdamParams - 1) / kAdamParams), dim3(256), 0, hs, aa);
     MS_LAUNCHED();
     clear_error();
     return MS_OK;

@@ -59,6 +59,7 @@ struct RenderArgs {
     uint32_t max_events;
     int batch_min;
     int restart_min;
+    int max_wait;
     int nee_samples;
     int flags;
     UnitRecord* part;  // [n_units], unit = pixel * n_chunks + chunk
@@ -473,6 +474,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     uint32_t c0 = 0, iters = 0, p_ev = 0, p_st = 0;
     bool p_trunc = false;
     uint32_t cnt_paths = 0, cnt_events = 0, cnt_steps = 0, cnt_trunc = 0;
+    // iterations for which lanes have been waiting for a restart / a learned
+    // step (wave-uniform): a pass also runs once the oldest wait reaches
+    // max_wait, so rare steps do not idle lanes for long
+    int end_age = 0, wait_age = 0;
 
     for (;;) {
         // ---- restart phase, batched: lanes whose path ended bank it, lanes
@@ -482,7 +487,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
         // handful of lanes on most iterations.
         const uint64_t rmask = ballot(state == S_END || state == S_IDLE);
         const uint64_t amask = ballot(state == S_FLY || state == S_WAIT);
-        if (rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0)) {
+        end_age = rmask != 0 ? end_age + 1 : 0;
+        if (rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0 || end_age > A.max_wait)) {
+            end_age = 0;
             bool start = false;
             if (state == S_END) {
                 neumaier_add(acc_sum, acc_comp, Lp);
@@ -645,7 +652,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
             const uint64_t wmask = ballot(state == S_WAIT);
             const uint64_t lmask = ballot(state == S_FLY || state == S_WAIT);
             const int n_wait = __popcll(wmask);
-            if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask)) {
+            wait_age = n_wait > 0 ? wait_age + 1 : 0;
+            if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask || wait_age > A.max_wait)) {
+                wait_age = 0;
                 const bool mine = state == S_WAIT;
                 float y[6];
                 float N = 1.0f, psi = 0.0f;
@@ -950,6 +959,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     MS_REQUIRE(desc->tau_min >= 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min >= 0, st_max > 0");
     MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
     MS_REQUIRE(desc->restart_min >= 0 && desc->restart_min <= 64, "sphere_trace_render: restart_min must be in [0, 64]");
+    MS_REQUIRE(desc->max_wait >= 0, "sphere_trace_render: max_wait must be >= 0");
     MS_REQUIRE((desc->flags & ~MS_RENDER_NEE_BEFORE_ABSORPTION) == 0, "sphere_trace_render: unknown flags");
     MS_REQUIRE(out->sum && out->sumsq, "sphere_trace_render: sum and sumsq images are required");
     MS_REQUIRE(scene->sdf_fp16 == nullptr || (scene->res > 0 && scene->res <= 4096 && scene->hi[0] > scene->lo[0] &&
@@ -1020,6 +1030,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 20;
     A.nee_samples = desc->nee_samples ? desc->nee_samples : 1;
     A.restart_min = desc->restart_min ? desc->restart_min : 16;
+    A.max_wait = desc->max_wait ? desc->max_wait : 10;
     A.flags = desc->flags;
     char* ws = reinterpret_cast<char*>(workspace_dev);
     A.ticket = reinterpret_cast<unsigned long long*>(ws);
