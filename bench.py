@@ -20,14 +20,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU work of the algorithm per unit, in 32-bit lane-operation slots
-# (quarter-rate instructions -- transcendentals, 32-bit integer multiplies --
-# count 4 slots).  Derivation in DESIGN.md ("Roofline").
-OPS_PER_PATH = 220.0         # camera ray, primary intervals, path bookkeeping
-OPS_PER_EVENT = 380.0        # one plain collision: Philox block, flight, NEE, roulette, HG, new ray
-OPS_PER_STEP = 2750.0        # one learned sphere step on VALU (the MFMA part is separate)
+# VALU work per unit in 32-bit lane-operation slots, counted on the kernels
+# themselves: SQ_THREAD_CYCLES_VALU (active lanes x VALU cycles) of rocprofv3
+# runs, fitted per path / plain event / learned step over the four densities
+# (the counter summary and the fit are in profiles/).  Idle (masked) lanes are
+# not counted, so achieved / peak is the fraction of the chip's lane slots
+# that do the algorithm's work.
+OPS_PER_PATH = 400.0         # camera ray, primary intervals, banking the result
+OPS_PER_EVENT = 470.0        # one plain collision: Philox block, flight, NEE shadow ray, roulette, HG, new ray
+OPS_PER_STEP = 5300.0        # one learned step, two representative events (three decoders, 22+ normals, NEE x2)
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
-OPS_PER_WALK_EVENT = 190.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
+OPS_PER_WALK_EVENT = 205.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
 PEAK_MFMA_BF16 = 2.5e15
 
