@@ -5,7 +5,11 @@
 // One photon per lane at a time.  Scattering-chain lengths are heavy tailed
 // (1 to ~10^5 events), so lanes take new photons from a per-wave ticket pool
 // as soon as theirs leaves the sphere: waves stay full until the global
-// ticket counter runs past n_photons, and every wave then exits.
+// ticket counter runs past n_photons, and every wave then exits.  With a few
+// photons per lane the end of the run is the last long chains on nearly empty
+// waves, so training walks are handed out longest expected chain first (a
+// counting sort of the photon ids by a bucket of sigma_t r and g); each
+// photon's result depends only on its id, so the order changes no output.
 #include "device.hpp"
 #include "host.hpp"
 
@@ -32,7 +36,81 @@ struct WalkArgs {
     float* event_dir;
     unsigned long long* counters;
     unsigned long long* ticket;
+    const uint32_t* order;  // ticket -> photon index (TRAINING), or null
 };
+
+// Order buckets: more expected events first.
+constexpr int kOrderBuckets = 128;
+constexpr int kOrderChunk = 4096;  // photons per block of the sort kernels
+
+// Parameters of training photon id (the walk kernel draws the same block).
+__device__ __forceinline__ void training_params(const WalkArgs& a, uint64_t id, float& st, float& g, float& phi) {
+    const uint4 pw = philox(0u, (uint32_t)id, (uint32_t)(id >> 32), MS_TAG_WALK_PARAM, (uint32_t)a.seed,
+                            (uint32_t)(a.seed >> 32));
+    const bool focus = u24(pw.w) <= a.focus_thr;
+    st = (focus ? a.fst_lo : a.st_lo) * __builtin_amdgcn_exp2f(u01(pw.x) * (focus ? a.fst_log2_ratio : a.st_log2_ratio));
+    g = __builtin_fmaf(focus ? a.fg_span : a.g_span, u01(pw.y), focus ? a.fg_lo : a.g_lo);
+    phi = __builtin_fmaf(a.a_span, u01(pw.z), a.a_lo);
+}
+
+// Bucket of the expected chain length, about 1 + tau + tau^2 (1 - g) / 3
+// events for optical radius tau (a diffusion estimate; only its order matters),
+// reversed so that bucket 0 holds the longest chains.
+__device__ __forceinline__ int order_bucket(float st, float g) {
+    const float cost = 1.0f + st + 0.35f * st * st * (1.0f - g);
+    const int b = (int)(8.0f * __builtin_amdgcn_logf(cost));
+    return kOrderBuckets - 1 - (b < 0 ? 0 : b > kOrderBuckets - 1 ? kOrderBuckets - 1 : b);
+}
+
+__global__ __launch_bounds__(256) void walk_order_count(const WalkArgs a, uint32_t* counts) {
+    __shared__ uint32_t h[kOrderBuckets];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * kOrderChunk;
+    for (uint64_t i = lo + threadIdx.x; i < a.n && i < lo + kOrderChunk; i += blockDim.x) {
+        float st, g, phi;
+        training_params(a, a.photon_offset + i, st, g, phi);
+        atomicAdd(&h[order_bucket(st, g)], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x)
+        if (h[b]) atomicAdd(&counts[b], h[b]);
+}
+
+// Exclusive prefix of the bucket counts (one wave, bucket order).
+__global__ void walk_order_scan(const uint32_t* counts, uint32_t* cursor) {
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+        cursor[b] = acc;
+        acc += counts[b];
+    }
+}
+
+__global__ __launch_bounds__(256) void walk_order_scatter(const WalkArgs a, uint32_t* cursor, uint32_t* order) {
+    __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+    __shared__ uint8_t key[kOrderChunk];
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) h[b] = 0u;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * kOrderChunk;
+    for (uint64_t i = lo + threadIdx.x; i < a.n && i < lo + kOrderChunk; i += blockDim.x) {
+        float st, g, phi;
+        training_params(a, a.photon_offset + i, st, g, phi);
+        const int b = order_bucket(st, g);
+        key[i - lo] = (uint8_t)b;
+        atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) {
+        base[b] = h[b] ? atomicAdd(&cursor[b], h[b]) : 0u;
+        h[b] = 0u;
+    }
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < a.n && i < lo + kOrderChunk; i += blockDim.x) {
+        const int b = key[i - lo];
+        order[base[b] + atomicAdd(&h[b], 1u)] = (uint32_t)i;
+    }
+}
 
 __device__ __forceinline__ void put3(float* base, uint64_t n, uint64_t i, V3 v) {
     if (!base) return;
@@ -105,18 +183,12 @@ __global__ __launch_bounds__(256) void walk_kernel(const WalkArgs a) {
             const uint64_t t = pool.take(need, a.ticket, 64);
             if (need) {
                 if (t < a.n) {
-                    i = t;
+                    i = a.order ? a.order[t] : t;
                     active = true;
                     const uint64_t id = a.photon_offset + i;
                     rng = make_rng(a.seed, MS_TAG_WALK_EVENT, id);
                     if (MODE == MS_WALK_TRAINING) {
-                        const uint4 pw =
-                            philox(0u, (uint32_t)id, (uint32_t)(id >> 32), MS_TAG_WALK_PARAM, rng.k0, rng.k1);
-                        const bool focus = u24(pw.w) <= a.focus_thr;
-                        st = (focus ? a.fst_lo : a.st_lo) *
-                             __builtin_amdgcn_exp2f(u01(pw.x) * (focus ? a.fst_log2_ratio : a.st_log2_ratio));
-                        g = __builtin_fmaf(focus ? a.fg_span : a.g_span, u01(pw.y), focus ? a.fg_lo : a.g_lo);
-                        phi = __builtin_fmaf(a.a_span, u01(pw.z), a.a_lo);
+                        training_params(a, id, st, g, phi);
                         inv_st = 1.0f / st;
                         inv_phi = 1.0f / phi;
                     }
@@ -207,7 +279,11 @@ extern "C" {
 
 ms_status ms_random_walk_workspace_size(const ms_walk_desc* desc, size_t* bytes) {
     MS_REQUIRE(desc != nullptr && bytes != nullptr, "ms_random_walk_workspace_size: NULL argument");
+    // ticket counter; for training walks of fewer than 2^32 photons also the
+    // order buckets and the photon order (4 bytes per photon)
     *bytes = 256;
+    if (desc->mode == MS_WALK_TRAINING && desc->n_photons < (1ull << 32))
+        *bytes = 2048 + msst::align_up((size_t)desc->n_photons * 4, 256);
     return MS_OK;
 }
 
@@ -242,8 +318,11 @@ ms_status ms_random_walk(const ms_walk_desc* desc, const ms_walk_out* out, void*
                        "ms_random_walk: focus_g_range must satisfy -1 < lo <= hi < 1");
         }
     }
-    MS_REQUIRE(workspace_dev != nullptr && workspace_bytes >= 256,
-               "ms_random_walk: workspace of at least 256 bytes required");
+    size_t ws_need = 0;
+    ms_random_walk_workspace_size(desc, &ws_need);
+    MS_REQUIRE(workspace_dev != nullptr, "ms_random_walk: workspace is NULL");
+    if (workspace_bytes < ws_need)
+        return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "ms_random_walk: workspace needs %zu bytes", ws_need);
     MS_REQUIRE(((uintptr_t)workspace_dev & 7u) == 0, "ms_random_walk: workspace must be 8-byte aligned");
 
     int cus = 0;
@@ -290,9 +369,22 @@ ms_status ms_random_walk(const ms_walk_desc* desc, const ms_walk_out* out, void*
     a.ticket = reinterpret_cast<unsigned long long*>(workspace_dev);
 
     hipStream_t s = (hipStream_t)stream;
+    if (ws_need > 256) {
+        // longest expected chains first: counts, prefix, scatter of the ids
+        uint32_t* counts = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(workspace_dev) + 1024);
+        uint32_t* cursor = counts + kOrderBuckets;
+        uint32_t* order = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(workspace_dev) + 2048);
+        const unsigned ob = (unsigned)((d.n_photons + kOrderChunk - 1) / kOrderChunk);
+        hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long*>(counts),
+                           kOrderBuckets / 2);
+        hipLaunchKernelGGL(walk_order_count, dim3(ob), dim3(256), 0, s, a, counts);
+        hipLaunchKernelGGL(walk_order_scan, dim3(1), dim3(64), 0, s, counts, cursor);
+        hipLaunchKernelGGL(walk_order_scatter, dim3(ob), dim3(256), 0, s, a, cursor, order);
+        a.order = order;
+    }
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, a.ticket, 1);
     MS_LAUNCHED();
-    const int bpc = d.blocks_per_cu ? d.blocks_per_cu : 8;
+    const int bpc = d.blocks_per_cu ? d.blocks_per_cu : 2;
     uint64_t blocks = (uint64_t)cus * bpc;
     const uint64_t need = (d.n_photons + 255) / 256;
     if (blocks > need) blocks = need;

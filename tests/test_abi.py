@@ -78,3 +78,15 @@ def test_philox_fill_rejects_invalid(M):
     assert L.ms_philox_fill(0, 0, 0, 0, 0, 1, C.c_void_p(0x1000), None) == M._abi.MS_ERR_INVALID_ARGUMENT
     assert L.ms_philox_fill(0, 0, 0, 4, 0, 1, None, None) == M._abi.MS_ERR_INVALID_ARGUMENT
     assert L.ms_philox_fill(0, 0, 0, 4, 0, 1, C.c_void_p(0x1004), None) == M._abi.MS_ERR_INVALID_ARGUMENT
+
+
+def test_training_walk_workspace_holds_the_photon_order(M):
+    """Training walks take a workspace for the longest-first photon order (4
+    bytes per photon); a smaller one is refused before any launch."""
+    d = M.walk_desc(1000, mode=1)
+    n = C.c_size_t()
+    assert M.lib().ms_random_walk_workspace_size(C.byref(d), C.byref(n)) == 0 and n.value >= 4000
+    o = M._abi.WalkOut()
+    ws = C.c_void_p(0x1000)  # never dereferenced: the size check fails first
+    assert M.lib().ms_random_walk(C.byref(d), C.byref(o), ws, 256, None) == M._abi.MS_ERR_WORKSPACE_TOO_SMALL
+    assert "workspace" in M.lib().ms_last_error().decode()
