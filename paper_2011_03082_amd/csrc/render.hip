@@ -314,18 +314,74 @@ struct GeoMany {
         return sd < 0.0f ? -0.999f * sd : 0.0f;
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
+    // Shadow ray: one pass over the primitives collects the hit intervals
+    // clipped to [0, dist] (8 slots), a sorting network orders them by entry
+    // and a sweep adds the length of their union; more than 8 hits falls back
+    // to piece-by-piece queries.
     __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
         V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
         const float dist2 = dot(wl, wl);
         const float inv_dist = fast_rsq(dist2);
         const float dist = dist2 * inv_dist;
         wl = inv_dist * wl;
-        float acc = 0.0f, t = 0.0f;
-        for (int k = 0; k < n && t < dist; ++k) {
-            float ps, pe;
-            if (!piece(x, wl, t, ps, pe) || ps >= dist) break;
-            acc += __builtin_fminf(pe, dist) - ps;
-            t = pe;
+        float ca[kHitSlots], cb[kHitSlots];
+#pragma unroll
+        for (int j = 0; j < kHitSlots; ++j) {
+            ca[j] = INFINITY;
+            cb[j] = INFINITY;
+        }
+        int m = 0;
+        for (int i = 0; i < n; ++i) {
+            float a, b;
+            if (prim_interval(prim + 8 * i, x, wl, a, b) && b > 0.0f && a < dist) {
+                a = __builtin_fmaxf(a, 0.0f);
+                b = __builtin_fminf(b, dist);
+#pragma unroll
+                for (int j = 0; j < kHitSlots; ++j)
+                    if (j == m) {
+                        ca[j] = a;
+                        cb[j] = b;
+                    }
+                ++m;
+            }
+        }
+        float acc = 0.0f;
+        if (m <= kHitSlots) {
+            // odd-even transposition sort of the (entry, exit) pairs by entry
+#pragma unroll
+            for (int pass = 0; pass < kHitSlots; ++pass)
+#pragma unroll
+                for (int j = pass & 1; j + 1 < kHitSlots; j += 2) {
+                    const bool sw = ca[j + 1] < ca[j];
+                    const float ta = sw ? ca[j + 1] : ca[j], tb = sw ? cb[j + 1] : cb[j];
+                    const float ua = sw ? ca[j] : ca[j + 1], ub = sw ? cb[j] : cb[j + 1];
+                    ca[j] = ta;
+                    cb[j] = tb;
+                    ca[j + 1] = ua;
+                    cb[j + 1] = ub;
+                }
+            float s0 = ca[0], e0 = cb[0];
+#pragma unroll
+            for (int j = 1; j < kHitSlots; ++j) {
+                if (j < m) {
+                    if (ca[j] <= e0) {
+                        e0 = __builtin_fmaxf(e0, cb[j]);
+                    } else {
+                        acc += e0 - s0;
+                        s0 = ca[j];
+                        e0 = cb[j];
+                    }
+                }
+            }
+            if (m > 0) acc += e0 - s0;
+        } else {
+            float t = 0.0f;
+            for (int k = 0; k < n && t < dist; ++k) {
+                float ps, pe;
+                if (!piece(x, wl, t, ps, pe) || ps >= dist) break;
+                acc += __builtin_fminf(pe, dist) - ps;
+                t = pe;
+            }
         }
         return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) * (inv_dist * inv_dist);
     }
