@@ -382,6 +382,12 @@ def main():
         tot_st += t_sigma[s]
         tot_pt += t_pt_match
     pt_rate = sum(pt[s]["paths"] for s in sigmas) / sum(pt[s]["time"] for s in sigmas)
+    # share of camera paths that hit the object: an opaque, black medium (albedo
+    # below 2^-24: the roulette ends every path at its first collision)
+    # (every hitting path has exactly one collision and is absorbed there)
+    hit = rend.render(dict(sigma_t=1e6, g=0.0, albedo=1e-9), method=1, spp=16, seed=8000)
+    hc = hit["counters"].cpu().numpy()
+    hit_fraction = float(hc[1] / hc[0])
 
     # the paper's final architectures (Table 1) on the same data and images
     table1 = None
@@ -492,6 +498,9 @@ def main():
                                + (", direct light before absorption" if args.nee_flags & 1 else ""),
                    "paths_per_step": paths_per_step, "parallelism": "single GPU"},
         "plain_paths_per_s": pt_rate,
+        "object_hit_fraction": hit_fraction,
+        "object_hitting_paths_per_s": value * hit_fraction,
+        "plain_object_hitting_paths_per_s": pt_rate * hit_fraction,
         "speedup_matched_rmse": tot_pt / tot_st,
         "per_sigma": details,
         "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps,

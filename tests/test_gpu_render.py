@@ -232,6 +232,58 @@ def test_full_size_c4_sampled_pixels(msst, oracle):
     assert bad.mean() < 0.01
 
 
+def test_full_size_c4_learned_sampled_pixels(msst, oracle):
+    """512 x 512 with the benchmark's sphere-tracing options (tau_min 6, two
+    representative events lit before absorption, default launch shape), BF16
+    decoders; 200 sampled pixels path by path against the oracle."""
+    announce("render C4 512^2 ST sampled parity")
+    prims, cam, light, med = c4_inputs(80.0, 512)
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src, 1)
+    opts = dict(spp=1, seed=17, tau_min=6.0, nee_samples=2, flags=1)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, **opts)
+    rng = np.random.default_rng(1)
+    stepped = np.flatnonzero(g["steps"] > 0)
+    pix = np.sort(rng.choice(stepped, 200, replace=False)).astype(np.int32)
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      precision=oracle.PREC_BF16, models=models, pixels=pix, **opts)
+    sub = {k: g[k][pix] for k in ("sum", "comp", "events", "steps")}
+    frac, _ = compare_paths(sub, o, rel=2e-3)
+    print(f"diverged {frac:.2e} of {pix.size} paths with learned steps")
+    assert frac < 0.05
+
+
+@pytest.mark.parametrize("method,precision", [(PLAIN, 1), (ST, 1), (ST, 2)])
+def test_full_size_c5_sampled_pixels(msst, oracle, method, precision):
+    """The 64-sphere scene at 1024 x 1024 over the 256^3 FP16 grid, in the
+    benchmark's launch shape; 150 sampled pixels against the oracle, which
+    builds its own grid."""
+    announce(f"render C5 1024^2 sampled parity method={method} precision={precision}")
+    prims, cam, light, med = c5_inputs(1024)
+    grid_g = msst.build_sdf_grid(prims, 256)
+    grid_o = oracle.Scene(prims).build_grid(256)
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src, precision) if method == ST else (None, None, None)
+    opts = dict(spp=1, seed=23)
+    if method == ST:
+        opts.update(tau_min=6.0, nee_samples=2, flags=1)
+    r = msst.Renderer(prims, cam, light, grid=grid_g)
+    out = r.render(med, method=method, sampler=CVAE, packed=packed, **opts)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    rng = np.random.default_rng(2)
+    lit = np.flatnonzero(g["events"] + g["steps"] > 0)
+    pix = np.sort(rng.choice(lit, 150, replace=False)).astype(np.int32)
+    kw = dict(method=oracle.METHOD_PLAIN_NEE) if method == PLAIN else dict(
+        method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE, models=models,
+        precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8)
+    o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med, pixels=pix, **kw, **opts)
+    sub = {k: g[k][pix] for k in ("sum", "comp", "events", "steps")}
+    frac, _ = compare_paths(sub, o, rel=2e-3)
+    print(f"diverged {frac:.2e}; steps {o['steps'].sum()}, events {o['events'].sum()}")
+    assert frac < 0.05
+
+
 def test_image_stats_fp64(msst):
     announce("image stats")
     rng = np.random.default_rng(3)
