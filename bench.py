@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
+    ap.add_argument("--table1-sweep", action="store_true",
+                    help="also train and score every Table 1 architecture that fits one tile (untimed)")
     ap.add_argument("--no-absorption", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--absorption-sigma", type=float, default=80.0)
@@ -104,45 +106,122 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
         timing["walk"] = dict(photons=n_samples, events=int(c[0]), seconds=e0.elapsed_time(e1) / 1e3)
     packs, losses = {p: [] for p in precisions}, []
     for model in range(3):
-        p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
-        # PathGen learns N >= 2 records and EventGen k >= 2 records: the
-        # single-event cases are sampled exactly by the renderer
-        rows = None if model == 0 else M.select_rows(walk, 2, 2 if model == 2 else 0)
-        n_rows = n_samples if rows is None else rows.numel()
-        cond = torch.empty((n_rows, p_in), dtype=torch.float32, device="cuda")
-        target = torch.empty((n_rows, p_out), dtype=torch.float32, device="cuda")
-        M.cvae_features(model, n_rows, walk, seed + 1, 0, None, cond, target, rows=rows)
-        stats = M.make_stats(cond, target)
-        M.cvae_features(model, n_rows, walk, seed + 1, 0, stats, cond, target, rows=rows)
         shape = model if shapes is None else shapes[model]
-        n = M.cvae_param_count(shape)
-        master = torch.empty(n, dtype=torch.float32, device="cuda")
-        M.cvae_init(shape, seed + 10 + model, master)
-        m, v = torch.zeros_like(master), torch.zeros_like(master)
-        ws = torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda")
-        loss = torch.zeros(3, dtype=torch.float64, device="cuda")
-        first = None
-        t_model = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t_model[0].record()
-        for step in range(1, steps + 1):
-            lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
-            beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
-            M.cvae_train_step(shape, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
-                              seed + 20 + model, step, 0, ws, loss, kl_weight=beta)
-            if step == 1:
-                first = loss.cpu().numpy().copy()
-        t_model[1].record()
-        last = loss.cpu().numpy().copy()
-        if timing is not None:
-            timing.setdefault("train_step_us", []).append(t_model[0].elapsed_time(t_model[1]) * 1e3 / steps)
+        pk, loss = train_one(M, torch, walk, model, shape, steps, batch, seed, kl_warmup, precisions, timing)
         for p in precisions:
-            pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-            M.cvae_pack(shape, master, stats, p, pk)
-            packs[p].append(pk)
-        losses.append(dict(rows=int(n_rows), first=first.tolist(), last=last.tolist()))
-        log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
+            packs[p].append(pk[p])
+        losses.append(loss)
     torch.cuda.synchronize()
     return packs, losses, time.time() - t0
+
+
+def train_one(M, torch, walk, model, shape, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), timing=None):
+    """Trains one CVAE on the walk records and packs it; returns ({precision:
+    packed}, loss record)."""
+    n_samples = walk["n_scatter"].numel()
+    p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
+    # PathGen learns N >= 2 records and EventGen k >= 2 records: the
+    # single-event cases are sampled exactly by the renderer
+    rows = None if model == 0 else M.select_rows(walk, 2, 2 if model == 2 else 0)
+    n_rows = n_samples if rows is None else rows.numel()
+    cond = torch.empty((n_rows, p_in), dtype=torch.float32, device="cuda")
+    target = torch.empty((n_rows, p_out), dtype=torch.float32, device="cuda")
+    M.cvae_features(model, n_rows, walk, seed + 1, 0, None, cond, target, rows=rows)
+    stats = M.make_stats(cond, target)
+    M.cvae_features(model, n_rows, walk, seed + 1, 0, stats, cond, target, rows=rows)
+    n = M.cvae_param_count(shape)
+    master = torch.empty(n, dtype=torch.float32, device="cuda")
+    M.cvae_init(shape, seed + 10 + model, master)
+    m, v = torch.zeros_like(master), torch.zeros_like(master)
+    ws = torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    first = None
+    t_model = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_model[0].record()
+    for step in range(1, steps + 1):
+        lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
+        beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
+        M.cvae_train_step(shape, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
+                          seed + 20 + model, step, 0, ws, loss, kl_weight=beta)
+        if step == 1:
+            first = loss.cpu().numpy().copy()
+    t_model[1].record()
+    last = loss.cpu().numpy().copy()
+    if timing is not None:
+        timing.setdefault("train_step_us", []).append(t_model[0].elapsed_time(t_model[1]) * 1e3 / steps)
+    packed = {}
+    for p in precisions:
+        pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+        M.cvae_pack(shape, master, stats, p, pk)
+        packed[p] = pk
+    log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
+    return packed, dict(rows=int(n_rows), first=first.tolist(), last=last.tolist())
+
+
+def table1_sweep(M, torch, W, n_samples, steps, n_eval=10000, seed=0):
+    """The architecture sweep of Table 1: every examined (D, W, L) of each
+    model that fits one 16-wide tile is trained on the same walks, and its
+    samples are compared with the walk on the Sec. 5.3 evaluation grid
+    (sigma_t in {1, 4, 20, 100}, g in {-0.7, 0, 0.4, 0.9}, albedo 1) by the
+    mean two-sample KS distance of log N (LengthGen), cos theta given the true
+    N >= 2 (PathGen) and |X| given the true exit and N for k >= 2
+    (EventGen)."""
+    import numpy as np
+    from scipy import stats as sps
+    walk = M.random_walk(n_samples, seed=seed, mode=1)
+    grid = [(s, g) for s in (1.0, 4.0, 20.0, 100.0) for g in (-0.7, 0.0, 0.4, 0.9)]
+    truth = []
+    for i, (s, g) in enumerate(grid):
+        w = M.random_walk(n_eval, seed=900 + i, mode=1, st_range=(s, s), g_range=(g, g), albedo_range=(1.0, 1.0))
+        truth.append({k: w[k].cpu().numpy().astype(np.float64) for k in ("n_scatter", "event_index", "exit_param",
+                                                                          "event_pos")})
+
+    def sample(pk, model, cond, sd):
+        out = torch.empty((cond.shape[0], [1, 3, 6][model]), dtype=torch.float32, device="cuda")
+        M.cvae_sample(pk, torch.as_tensor(cond, dtype=torch.float32).cuda(), cond.shape[0], sd, 0, out)
+        return out.cpu().numpy().astype(np.float64)
+
+    def score(pk, model):
+        ks = []
+        for i, ((s, g), t) in enumerate(zip(grid, truth)):
+            n = t["n_scatter"]
+            if model == 0:
+                y = sample(pk, 0, np.stack([np.full(n.size, np.log(s)), np.full(n.size, g)], 1), 50 + i)[:, 0]
+                nn = np.maximum(1.0, np.floor(np.exp(np.minimum(y, 20.0)) + 0.5))
+                ks.append(sps.ks_2samp(np.log(n), np.log(nn)).statistic)
+                continue
+            sel = (n >= 2) if model == 1 else (n >= 2) & (t["event_index"] >= 2)
+            if sel.sum() < 200:
+                continue
+            ep = t["exit_param"][:, sel]
+            base = [np.full(sel.sum(), np.log(s)), np.full(sel.sum(), g)]
+            if model == 1:
+                y = sample(pk, 1, np.stack(base + [np.log(n[sel])], 1), 50 + i)
+                ks.append(sps.ks_2samp(ep[0], np.clip(y[:, 0], -1, 1)).statistic)
+            else:
+                cond = np.stack(base + [np.ones(sel.sum()), ep[0], ep[1], ep[2], np.log(n[sel])], 1)
+                y = sample(pk, 2, cond, 50 + i)
+                xl = np.minimum(np.linalg.norm(y[:, :3], axis=1), 1.0)
+                ks.append(sps.ks_2samp(np.linalg.norm(t["event_pos"][:, sel], axis=0), xl).statistic)
+        return float(np.mean(ks))
+
+    rows = []
+    for model in range(3):
+        gspec = W.TABLE1_GRID[model]
+        for D in gspec["D"]:
+            for Wd in gspec["W"]:
+                for L in gspec["L"]:
+                    shape = W.table1_shape(model, D, Wd, L)
+                    row = dict(model=model, D=D, W=Wd, L=L, final=W.TABLE1_FINAL[model] == dict(D=D, W=Wd, L=L))
+                    if not W.table1_fits(shape):
+                        row["built"] = False
+                        rows.append(row)
+                        continue
+                    pk, loss = train_one(M, torch, walk, model, shape, steps, seed=seed)
+                    row.update(built=True, ks=score(pk[1], model), loss=loss["last"][0])
+                    log(f"Table 1 sweep model {model} D={D} W={Wd} L={L}: mean KS {row['ks']:.3f}")
+                    rows.append(row)
+    return rows
 
 
 RENDER_SOURCES = ("paper_2011_03082_amd/csrc/render.hip", "paper_2011_03082_amd/csrc/device.hpp",
@@ -453,6 +532,11 @@ def main():
             log(f"absorption {a:.1e}: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {e_pt:.2e} / {e_st:.2e}, "
                 f"speed-up {row['speedup_matched_rmse']:.2f}")
 
+    sweep = None
+    if args.table1_sweep:
+        log("Table 1 architecture sweep")
+        sweep = table1_sweep(M, torch, W, args.train_samples, args.train_steps)
+
     diag = None
     if args.diagnostics:
         diag = {}
@@ -513,6 +597,7 @@ def main():
         "cpu_baseline": cpu,
         "c5": c5,
         "table1": table1,
+        "table1_sweep": sweep,
         "absorption_sweep": absorption,
         "focus_training": focus,
         "diagnostics": diag,

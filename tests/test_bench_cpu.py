@@ -1,0 +1,42 @@
+"""Host-side pieces of bench.py that run without a GPU: argument defaults,
+the refusal of several GPUs, the measured-traffic reader and the image
+moments helper."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_defaults_match_the_documented_configuration(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.gpus, a.width, a.spp, a.ref_spp) == (1, 512, 256, 4096)
+    assert a.tau_min == 6.0 and a.nee_samples == 2 and a.nee_flags == 1
+    assert a.train_samples == 1 << 22 and a.train_steps == 20000
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_traffic_reader_follows_the_kernel_sources():
+    d = bench.render_source_digest()
+    assert len(d) == 16 and d == bench.render_source_digest()
+    t = bench.measured_traffic()
+    assert t is None or t > 0
+
+
+def test_image_moments():
+    img = {"sum": torch.tensor([4.0, 2.0]), "comp": torch.tensor([0.0, 1e-7]),
+           "sumsq": torch.tensor([8.0, 2.0])}
+    mean, var = bench.image_moments(img, 4)
+    np.testing.assert_allclose(mean.numpy(), [1.0, (2.0 + 1e-7) / 4], rtol=1e-7)
+    assert var.min() >= 0
