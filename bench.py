@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--table1-sweep", action="store_true",
                     help="also train and score every Table 1 architecture that fits one tile (untimed)")
     ap.add_argument("--no-absorption", action="store_true")
+    ap.add_argument("--no-rgb", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--absorption-sigma", type=float, default=80.0)
     ap.add_argument("--absorption-points", type=int, default=6)
@@ -504,6 +505,32 @@ def main():
             log(f"focus sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e}, speed-up "
                 f"{focus[str(s)]['speedup_matched_rmse']:.2f}")
 
+    # RGB medium: one (sigma_t, albedo) per colour channel, each channel its
+    # own trace (Philox key seed + c); speed-up at matched RMSE per channel
+    rgb = None
+    if not args.no_rgb:
+        media = [dict(sigma_t=s_, g=0.8, albedo=a_) for s_, a_ in ((20.0, 0.999), (40.0, 0.995), (80.0, 0.99))]
+        ref_rgb = rend.render_rgb(media, method=1, spp=args.ref_spp // 2, seed=9000, **kw)
+        rgb = {"media": media}
+        img_pt, t_pt = timed(lambda: rend.render_rgb(media, method=1, spp=spp, seed=9100, **kw))
+        img_st, t_st = timed(lambda: rend.render_rgb(media, method=2, sampler=0, packed=packed, spp=spp, seed=9200,
+                                                     tau_min=args.tau_min, nee_samples=args.nee_samples,
+                                                     flags=args.nee_flags, **kw))
+        e2_st = e2_pt = v_pt = 0.0
+        for c in range(3):
+            pick = lambda im: {k: v[c] for k, v in im.items() if k != "counters"}
+            rm, rv = image_moments(pick(ref_rgb), args.ref_spp // 2)
+            noise2 = float(rv.mean()) / (args.ref_spp // 2)
+            pm, pv = image_moments(pick(img_pt), spp)
+            sm, _ = image_moments(pick(img_st), spp)
+            e2_st += max(float(((sm - rm) ** 2).mean()) - noise2, 1e-30)
+            e2_pt += max(float(((pm - rm) ** 2).mean()) - noise2, 1e-30)
+            v_pt += float(pv.mean())
+        rgb.update(pt_ms=t_pt * 1e3, st_ms=t_st * 1e3, rmse_pt=float(np.sqrt(e2_pt / 3)), rmse_st=float(np.sqrt(e2_st / 3)),
+                   speedup_matched_rmse=(v_pt / e2_st) / spp * t_pt / t_st)
+        log(f"RGB: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {rgb['rmse_pt']:.2e} / {rgb['rmse_st']:.2e}, "
+            f"speed-up {rgb['speedup_matched_rmse']:.2f}")
+
     # absorption sweep (the paper's absorption experiment): one density, the
     # absorption 1 - albedo doubled from 2e-4; rendering time and error of
     # both tracers at the same spp, matched-RMSE speed-up
@@ -599,6 +626,7 @@ def main():
         "table1": table1,
         "table1_sweep": sweep,
         "absorption_sweep": absorption,
+        "rgb": rgb,
         "focus_training": focus,
         "diagnostics": diag,
         "wall_s_timed": wall,
