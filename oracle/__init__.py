@@ -55,7 +55,8 @@ class _WalkOut(C.Structure):
 
 class _Scene(C.Structure):
     _fields_ = [("prims", C.c_void_p), ("n_prims", C.c_int32), ("sdf_fp16", C.c_void_p),
-                ("res", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+                ("res", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("tris", C.c_void_p),
+                ("n_tris", C.c_int32)]
 
 
 class _Camera(C.Structure):
@@ -295,12 +296,18 @@ def cvae_features(model, walk, seed, id_offset=0):
 
 # ---------------------------------------------------------------- scenes and rendering
 class Scene:
-    def __init__(self, prims, sdf_fp16=None, lo=(-1, -1, -1), hi=(1, 1, 1)):
-        self.prims = np.ascontiguousarray(prims, dtype=np.float32).reshape(-1, 8)
+    """Primitives [n, 8] or, with tris ([n, 9] float32 vertex triples of a
+    closed mesh), the mesh interior; optional FP16 distance grid."""
+
+    def __init__(self, prims, sdf_fp16=None, lo=(-1, -1, -1), hi=(1, 1, 1), tris=None):
+        self.prims = np.ascontiguousarray(prims if prims is not None else np.zeros((0, 8)),
+                                          dtype=np.float32).reshape(-1, 8)
         self.grid = None if sdf_fp16 is None else np.ascontiguousarray(sdf_fp16, dtype=np.uint16)
+        self.tris = None if tris is None else np.ascontiguousarray(tris, dtype=np.float32).reshape(-1, 9)
         res = 0 if self.grid is None else int(round(self.grid.size ** (1 / 3)))
         self.c = _Scene(_p(self.prims), self.prims.shape[0], _p(self.grid), res,
-                        (C.c_float * 3)(*lo), (C.c_float * 3)(*hi))
+                        (C.c_float * 3)(*lo), (C.c_float * 3)(*hi), _p(self.tris),
+                        0 if self.tris is None else self.tris.shape[0])
 
     def sdf(self, p):
         p = np.ascontiguousarray(p, dtype=np.float64)

@@ -143,6 +143,11 @@ typedef struct {
     const uint16_t* sdf_fp16; /* optional conservative grid, res^3, x fastest */
     int32_t res;
     float lo[3], hi[3];
+    /* Optional closed triangle mesh (n_tris x 9 floats: three vertices, any
+     * winding); when n_tris > 0 the body is the mesh interior and prims are
+     * ignored. */
+    const float* tris;
+    int32_t n_tris;
 } or_scene;
 
 typedef struct {

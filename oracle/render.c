@@ -52,7 +52,110 @@ static double or_prim_sdf(const float* pr, const double p[3]) {
     return sqrt(or_dot(out, out)) + inside;
 }
 
+/* ---------------- triangle meshes ---------------- */
+
+/* Line parameter t of the crossing of o + t d with triangle (a, b, c), any t
+ * (Moller and Trumbore, "Fast, Minimum Storage Ray/Triangle Intersection",
+ * JGT 1997, without back-face culling); 0 if the line misses it. */
+static int or_tri_cross(const float* tr, const double o[3], const double d[3], double* t) {
+    double a[3] = {tr[0], tr[1], tr[2]}, e1[3], e2[3], s[3], pv[3], qv[3];
+    for (int i = 0; i < 3; ++i) {
+        e1[i] = (double)tr[3 + i] - a[i];
+        e2[i] = (double)tr[6 + i] - a[i];
+        s[i] = o[i] - a[i];
+    }
+    pv[0] = d[1] * e2[2] - d[2] * e2[1];
+    pv[1] = d[2] * e2[0] - d[0] * e2[2];
+    pv[2] = d[0] * e2[1] - d[1] * e2[0];
+    double det = or_dot(e1, pv);
+    if (det == 0.0) return 0;
+    double inv = 1.0 / det;
+    double u = or_dot(s, pv) * inv;
+    if (u < 0.0 || u > 1.0) return 0;
+    qv[0] = s[1] * e1[2] - s[2] * e1[1];
+    qv[1] = s[2] * e1[0] - s[0] * e1[2];
+    qv[2] = s[0] * e1[1] - s[1] * e1[0];
+    double v = or_dot(d, qv) * inv;
+    if (v < 0.0 || u + v > 1.0) return 0;
+    *t = or_dot(e2, qv) * inv;
+    return 1;
+}
+
+/* All crossings of the whole line with the mesh, sorted; returns their
+ * number (at most cap). */
+static int or_mesh_crossings(const or_scene* sc, const double o[3], const double d[3], double* tc, int cap) {
+    int n = 0;
+    for (int i = 0; i < sc->n_tris; ++i) {
+        double t;
+        if (!or_tri_cross(sc->tris + 9 * i, o, d, &t)) continue;
+        if (n == cap) return cap + 1;
+        int k = n++;
+        while (k > 0 && tc[k - 1] > t) {
+            tc[k] = tc[k - 1];
+            --k;
+        }
+        tc[k] = t;
+    }
+    return n;
+}
+
+/* Distance from p to triangle tr (closest point by region tests, after
+ * Ericson, "Real-Time Collision Detection", Sec. 5.1.5). */
+static double or_tri_distance(const float* tr, const double p[3]) {
+    double a[3], b[3], c[3], ab[3], ac[3], ap[3], bp[3], cp[3], q[3];
+    for (int i = 0; i < 3; ++i) {
+        a[i] = tr[i];
+        b[i] = tr[3 + i];
+        c[i] = tr[6 + i];
+        ab[i] = b[i] - a[i];
+        ac[i] = c[i] - a[i];
+        ap[i] = p[i] - a[i];
+        bp[i] = p[i] - b[i];
+        cp[i] = p[i] - c[i];
+    }
+    double d1 = or_dot(ab, ap), d2 = or_dot(ac, ap);
+    double d3 = or_dot(ab, bp), d4 = or_dot(ac, bp);
+    double d5 = or_dot(ab, cp), d6 = or_dot(ac, cp);
+    double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        for (int i = 0; i < 3; ++i) q[i] = a[i];
+    } else if (d3 >= 0.0 && d4 <= d3) {
+        for (int i = 0; i < 3; ++i) q[i] = b[i];
+    } else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        double v = d1 / (d1 - d3);
+        for (int i = 0; i < 3; ++i) q[i] = a[i] + v * ab[i];
+    } else if (d6 >= 0.0 && d5 <= d6) {
+        for (int i = 0; i < 3; ++i) q[i] = c[i];
+    } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        double w = d2 / (d2 - d6);
+        for (int i = 0; i < 3; ++i) q[i] = a[i] + w * ac[i];
+    } else if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+        double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        for (int i = 0; i < 3; ++i) q[i] = b[i] + w * (c[i] - b[i]);
+    } else {
+        double den = 1.0 / (va + vb + vc), v = vb * den, w = vc * den;
+        for (int i = 0; i < 3; ++i) q[i] = a[i] + ab[i] * v + ac[i] * w;
+    }
+    double e[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+    return sqrt(or_dot(e, e));
+}
+
+/* A fixed direction for inside tests, away from the axes and diagonals. */
+static const double OR_PARITY_DIR[3] = {0.2672612419124244, 0.5345224838248488, 0.8017837257372732};
+
+static double or_mesh_sdf(const or_scene* sc, const double p[3]) {
+    double dmin = INFINITY;
+    int odd = 0;
+    for (int i = 0; i < sc->n_tris; ++i) {
+        dmin = fmin(dmin, or_tri_distance(sc->tris + 9 * i, p));
+        double t;
+        if (or_tri_cross(sc->tris + 9 * i, p, OR_PARITY_DIR, &t) && t > 0.0) odd ^= 1;
+    }
+    return odd ? -dmin : dmin;
+}
+
 double or_scene_sdf(const or_scene* sc, const double p[3]) {
+    if (sc->n_tris > 0) return or_mesh_sdf(sc, p);
     double s = INFINITY;
     for (int i = 0; i < sc->n_prims; ++i) s = fmin(s, or_prim_sdf(sc->prims + 8 * i, p));
     return s;
@@ -97,6 +200,20 @@ static int or_prim_interval(const float* pr, const double o[3], const double d[3
 /* Sorted, merged intervals of the ray inside the union of all primitives. */
 int or_ray_intervals(const or_scene* sc, const double o[3], const double d[3], double* t0,
                      double* t1, int cap) {
+    if (sc->n_tris > 0) {
+        /* a closed mesh: consecutive crossings of the whole line pair up as
+         * (entry, exit); an odd count (a crossing lost on an edge) drops the
+         * last one */
+        double tc[2 * OR_MAX_IV];
+        int n = or_mesh_crossings(sc, o, d, tc, 2 * OR_MAX_IV);
+        if (n > 2 * OR_MAX_IV) n = 2 * OR_MAX_IV;
+        int m = 0;
+        for (int i = 0; i + 1 < n && m < cap; i += 2, ++m) {
+            t0[m] = tc[i];
+            t1[m] = tc[i + 1];
+        }
+        return m;
+    }
     double a[OR_MAX_IV * 8], b[OR_MAX_IV * 8];
     int n = 0;
     for (int i = 0; i < sc->n_prims && n < OR_MAX_IV * 8; ++i) {

@@ -80,6 +80,62 @@ def scene_c5(seed=0, n=64):
     return np.array([prim_sphere(c[i], r[i]) for i in range(n)], np.float32)
 
 
+# ---------------------------------------------------------------- triangle meshes
+def icosphere(subdiv):
+    """Unit icosphere: vertices [v, 3] float64 and faces [f, 3] (outward
+    counter-clockwise), each face split into four `subdiv` times."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    verts = [np.array(x, np.float64) / np.linalg.norm(x) for x in v]
+    for _ in range(subdiv):
+        mid, nf = {}, []
+
+        def midpoint(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                mid[key] = len(verts) - 1
+            return mid[key]
+        for a, b, c in f:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = nf
+    return np.array(verts), np.array(f, np.int64)
+
+
+def blob_radius(u, seed=0):
+    """Radial function r(u) of the star-shaped test body for unit directions
+    u [n, 3]: a lumpy core of radius ~0.55 and one thin spike (an 'ear')
+    along a seeded direction."""
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=3)
+    a /= np.linalg.norm(a)
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    lump = 0.06 * np.sin(4 * u[:, 0] + ph[0]) * np.sin(3 * u[:, 1] + ph[1]) * np.sin(2 * u[:, 2] + ph[2])
+    spike = 0.55 * np.maximum(0.0, (u @ a - 0.9) / 0.1) ** 1.5
+    return 0.55 + lump + spike
+
+
+def mesh_blob(seed=0, subdiv=4):
+    """Closed triangle mesh [f, 9] (float32 vertex triples, outward winding)
+    of the star-shaped body blob_radius: an icosphere with each vertex moved
+    to radius r(u) -- a voluminous body with a thin part, standing in for the
+    paper's scanned meshes."""
+    v, f = icosphere(subdiv)
+    v = v * blob_radius(v, seed)[:, None]
+    return v[f].reshape(-1, 9).astype(np.float32)
+
+
+def camera_mesh(width=512, height=512):
+    return dict(eye=(0.0, 0.3, 3.0), look_at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=40.0,
+                width=width, height=height)
+
+
 def camera_c4(width=512, height=512):
     return dict(eye=(0.5, 0.6, 4.5), look_at=(0.5, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=40.0,
                 width=width, height=height)
