@@ -266,11 +266,32 @@ enum { MS_SAMPLER_CVAE = 0, MS_SAMPLER_EXACT_WALK = 1 };
 
 typedef struct {
     const float* prims;       /* device [n_prims][8] */
-    int32_t n_prims;          /* 1..256 (up to 4 are held in registers) */
-    const uint16_t* sdf_fp16; /* optional device grid [res^3], x fastest */
+    int32_t n_prims;          /* 1..256 (up to 4 are held in registers); 0 with a mesh */
+    const uint16_t* sdf_fp16; /* optional device grid [res^3], x fastest (required with a mesh) */
     int32_t res;
     float lo[3], hi[3];
+    /* Optional closed triangle mesh (the polygon-mesh boundary the paper
+     * renders): when n_tris > 0 the body is the mesh interior and prims are
+     * ignored.  tris: device [n_tris][9] vertex triples in the order
+     * ms_build_mesh_bvh returns, bvh: its device node array.  A line's
+     * crossings pair up as (entry, exit); up to 8 crossings per line are
+     * kept (the nearest along it). */
+    const float* tris;
+    int32_t n_tris;
+    const void* bvh;
+    int32_t n_nodes;
 } ms_scene;
+
+/* Bounding-volume hierarchy of a closed triangle mesh, built on the host:
+ * median splits on the longest centroid axis, leaves of up to 4 triangles,
+ * 32-byte nodes in depth-first order with skip links (stackless traversal).
+ * tris_host: [n_tris][9] floats; writes the nodes (at most 2 n_tris, size
+ * from ms_mesh_bvh_size) and the triangles reordered to the leaves' order
+ * (tris_sorted_host, [n_tris][9]); the caller copies both to the device.
+ * Host memory only; nothing is launched. */
+ms_status ms_mesh_bvh_size(int32_t n_tris, size_t* node_bytes);
+ms_status ms_build_mesh_bvh(const float* tris_host, int32_t n_tris, void* nodes_host, size_t node_bytes,
+                            float* tris_sorted_host, int32_t* n_nodes);
 
 typedef struct {
     float eye[3], look_at[3], up[3];
@@ -333,7 +354,11 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
  * rounded toward zero, h = (hi - lo) / res, over scene->lo .. scene->hi
  * (scene->sdf_fp16 and scene->res are ignored).  Passing the grid back in
  * ms_scene makes the renderer take sphere radii from the nearest voxel
- * minus half a voxel diagonal.  1..256 primitives, res <= 4096. */
+ * minus half a voxel diagonal.  1..256 primitives, res <= 4096.  For a mesh
+ * scene (n_tris > 0, tris on the device) the distance is the FP64 distance
+ * to the nearest triangle, negative where a ray from the voxel centre along
+ * (1, 2, 3) / sqrt(14) crosses the mesh an odd number of times (every
+ * triangle is tested: a pre-process, not a per-frame cost). */
 ms_status ms_build_sdf_grid(const ms_scene* scene, int32_t res, uint16_t* grid_dev, void* stream);
 
 /* FP64 image statistics (deterministic): out_dev[0] mean radiance,

@@ -50,7 +50,8 @@ class Adam(C.Structure):
 
 class Scene(C.Structure):
     _fields_ = [("prims", C.c_void_p), ("n_prims", C.c_int32), ("sdf_fp16", C.c_void_p), ("res", C.c_int32),
-                ("lo", C.c_float * 3), ("hi", C.c_float * 3)]
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("tris", C.c_void_p), ("n_tris", C.c_int32),
+                ("bvh", C.c_void_p), ("n_nodes", C.c_int32)]
 
 
 class Camera(C.Structure):
@@ -105,6 +106,8 @@ SIGNATURES = {
     "sphere_trace_render": ([_P(Scene), _P(Camera), _P(Light), _P(Medium), _P(RenderDesc), _P(ImageOut), _vp,
                              _sz, _vp], C.c_int32),
     "ms_build_sdf_grid": ([_P(Scene), _i32, _vp, _vp], C.c_int32),
+    "ms_mesh_bvh_size": ([_i32, _P(_sz)], C.c_int32),
+    "ms_build_mesh_bvh": ([_vp, _i32, _vp, _sz, _vp, _P(_i32)], C.c_int32),
     "ms_image_stats_workspace_size": ([_i64, _P(_sz)], C.c_int32),
     "ms_image_stats": ([_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _sz, _vp], C.c_int32),
 }

@@ -194,10 +194,31 @@ def cvae_sample(packed, cond, n, seed, id_offset, out, stream=None):
 
 
 # ---------------------------------------------------------------- rendering
-def make_scene(prims, grid=None, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), res=0):
-    """prims: device float32 tensor [n, 8]; grid: optional device int16 tensor [res^3]."""
-    return _abi.Scene(_ptr(prims), prims.shape[0], _ptr(grid), res if grid is not None else 0,
-                      (C.c_float * 3)(*lo), (C.c_float * 3)(*hi))
+def make_scene(prims, grid=None, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), res=0, mesh=None):
+    """prims: device float32 tensor [n, 8] (or None with a mesh); grid:
+    optional device int16 tensor [res^3]; mesh: (tris [n, 9], nodes, n_nodes)
+    from build_mesh (device tensors)."""
+    tris, nodes, n_nodes = mesh if mesh is not None else (None, None, 0)
+    return _abi.Scene(_ptr(prims), 0 if prims is None else prims.shape[0], _ptr(grid),
+                      res if grid is not None else 0, (C.c_float * 3)(*lo), (C.c_float * 3)(*hi), _ptr(tris),
+                      0 if tris is None else tris.shape[0], _ptr(nodes), n_nodes)
+
+
+def build_mesh(tris, device="cuda"):
+    """BVH of a closed triangle mesh ([n, 9] float32 vertex triples) built on
+    the host by ms_build_mesh_bvh; returns (reordered triangles, nodes,
+    n_nodes) on the device."""
+    import numpy as np
+    t = np.ascontiguousarray(tris, dtype=np.float32).reshape(-1, 9)
+    n = t.shape[0]
+    nb = C.c_size_t()
+    check(lib().ms_mesh_bvh_size(n, C.byref(nb)))
+    nodes = np.zeros(nb.value, np.uint8)
+    tsorted = np.zeros_like(t)
+    nn = C.c_int32()
+    check(lib().ms_build_mesh_bvh(t.ctypes.data, n, nodes.ctypes.data, nb.value, tsorted.ctypes.data, C.byref(nn)))
+    return (torch.as_tensor(tsorted).to(device).contiguous(),
+            torch.as_tensor(nodes[: nn.value * 32]).to(device).contiguous(), nn.value)
 
 
 def make_camera(cam):
@@ -228,10 +249,16 @@ def ms_build_sdf_grid(scene, res, grid, stream=None):
     check(lib().ms_build_sdf_grid(C.byref(scene), res, _ptr(grid), _stream(stream)))
 
 
-def build_sdf_grid(prims, res, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), device="cuda"):
-    """FP16 conservative distance grid (int16 device tensor of binary16 bits)."""
-    prims = torch.as_tensor(prims, dtype=torch.float32).reshape(-1, 8).to(device).contiguous()
+def build_sdf_grid(prims, res, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), device="cuda", tris=None):
+    """FP16 conservative distance grid (int16 device tensor of binary16 bits)
+    of primitives, or of a closed triangle mesh (tris [n, 9])."""
     grid = torch.empty(res ** 3, dtype=torch.int16, device=device)
+    if tris is not None:
+        t = torch.as_tensor(tris, dtype=torch.float32).reshape(-1, 9).to(device).contiguous()
+        ms_build_sdf_grid(make_scene(None, None, lo, hi, mesh=(t, None, 0)), res, grid)
+        torch.cuda.synchronize()
+        return grid
+    prims = torch.as_tensor(prims, dtype=torch.float32).reshape(-1, 8).to(device).contiguous()
     ms_build_sdf_grid(make_scene(prims, None, lo, hi), res, grid)
     return grid
 
@@ -271,11 +298,14 @@ def ms_image_stats(sum_, comp, sumsq, ref, n_pixels, spp, out, workspace, stream
 class Renderer:
     """Holds a scene on the device and renders images through sphere_trace_render."""
 
-    def __init__(self, prims, camera, light, grid=None, grid_lo=(-1, -1, -1), grid_hi=(1, 1, 1), device="cuda"):
-        self.prims = torch.as_tensor(prims, dtype=torch.float32).reshape(-1, 8).to(device).contiguous()
+    def __init__(self, prims, camera, light, grid=None, grid_lo=(-1, -1, -1), grid_hi=(1, 1, 1), device="cuda",
+                 tris=None):
+        self.prims = None if prims is None else torch.as_tensor(prims, dtype=torch.float32).reshape(-1, 8).to(
+            device).contiguous()
         self.grid = None if grid is None else torch.as_tensor(grid).to(device).contiguous()
         res = 0 if grid is None else round(self.grid.numel() ** (1 / 3))
-        self.scene = make_scene(self.prims, self.grid, grid_lo, grid_hi, res)
+        self.mesh = None if tris is None else build_mesh(tris, device)
+        self.scene = make_scene(self.prims, self.grid, grid_lo, grid_hi, res, mesh=self.mesh)
         self.camera = camera
         self.cam = make_camera(camera)
         self.light = make_light(light)

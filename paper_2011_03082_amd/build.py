@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmsst.so")
-SOURCES = ["common.hip", "walk.hip", "cvae.hip", "render.hip", "stats.hip"]
+SOURCES = ["common.hip", "walk.hip", "cvae.hip", "render.hip", "stats.hip", "mesh.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,108 @@
+// mesh.hip -- host construction of the triangle BVH (median split on the
+// longest axis of the centroid bounds, leaves of up to four triangles,
+// preorder layout with skip links for stackless traversal).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "host.hpp"
+#include "mesh.hpp"
+
+namespace msst {
+namespace {
+
+struct Builder {
+    const float* tris;
+    std::vector<int32_t> idx;
+    std::vector<BvhNode> nodes;
+
+    void bounds(int b, int e, float* lo, float* hi, bool centroids) const {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = INFINITY;
+            hi[a] = -INFINITY;
+        }
+        for (int i = b; i < e; ++i) {
+            const float* t = tris + 9 * (size_t)idx[i];
+            for (int a = 0; a < 3; ++a) {
+                if (centroids) {
+                    const float c = (t[a] + t[3 + a] + t[6 + a]) / 3.0f;
+                    lo[a] = std::min(lo[a], c);
+                    hi[a] = std::max(hi[a], c);
+                } else {
+                    for (int v = 0; v < 3; ++v) {
+                        lo[a] = std::min(lo[a], t[3 * v + a]);
+                        hi[a] = std::max(hi[a], t[3 * v + a]);
+                    }
+                }
+            }
+        }
+    }
+
+    void build(int b, int e) {
+        const int self = (int)nodes.size();
+        nodes.push_back(BvhNode{});
+        BvhNode nd{};
+        bounds(b, e, nd.lo, nd.hi, false);
+        if (e - b <= kBvhLeafMax) {
+            nd.leaf = (b << 4) | (e - b);
+            nd.skip = self + 1;
+            nodes[self] = nd;
+            return;
+        }
+        float clo[3], chi[3];
+        bounds(b, e, clo, chi, true);
+        int axis = 0;
+        for (int a = 1; a < 3; ++a)
+            if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
+        const int mid = b + (e - b) / 2;
+        const float* T = tris;
+        std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [T, axis](int32_t x, int32_t y) {
+            const float cx = T[9 * (size_t)x + axis] + T[9 * (size_t)x + 3 + axis] + T[9 * (size_t)x + 6 + axis];
+            const float cy = T[9 * (size_t)y + axis] + T[9 * (size_t)y + 3 + axis] + T[9 * (size_t)y + 6 + axis];
+            return cx < cy || (cx == cy && x < y);
+        });
+        build(b, mid);
+        build(mid, e);
+        nd.leaf = -1;
+        nd.skip = (int)nodes.size();
+        nodes[self] = nd;
+    }
+};
+
+}  // namespace
+}  // namespace msst
+
+extern "C" {
+
+ms_status ms_mesh_bvh_size(int32_t n_tris, size_t* node_bytes) {
+    MS_REQUIRE(node_bytes != nullptr, "ms_mesh_bvh_size: node_bytes is NULL");
+    MS_REQUIRE(n_tris >= 1 && n_tris < (1 << 26), "ms_mesh_bvh_size: n_tris must be in [1, 2^26)");
+    *node_bytes = (size_t)(2 * n_tris) * sizeof(msst::BvhNode);
+    return MS_OK;
+}
+
+ms_status ms_build_mesh_bvh(const float* tris_host, int32_t n_tris, void* nodes_host, size_t node_bytes,
+                            float* tris_sorted_host, int32_t* n_nodes) {
+    using namespace msst;
+    MS_REQUIRE(tris_host && nodes_host && tris_sorted_host && n_nodes, "ms_build_mesh_bvh: NULL argument");
+    MS_REQUIRE(n_tris >= 1 && n_tris < (1 << 26), "ms_build_mesh_bvh: n_tris must be in [1, 2^26)");
+    for (int64_t i = 0; i < 9 * (int64_t)n_tris; ++i)
+        MS_REQUIRE(std::isfinite(tris_host[i]), "ms_build_mesh_bvh: vertex coordinates must be finite");
+    size_t need = 0;
+    ms_mesh_bvh_size(n_tris, &need);
+    if (node_bytes < need) return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "ms_build_mesh_bvh: nodes need %zu bytes", need);
+    Builder bld;
+    bld.tris = tris_host;
+    bld.idx.resize(n_tris);
+    for (int i = 0; i < n_tris; ++i) bld.idx[i] = i;
+    bld.nodes.reserve(2 * (size_t)n_tris);
+    bld.build(0, n_tris);
+    std::memcpy(nodes_host, bld.nodes.data(), bld.nodes.size() * sizeof(BvhNode));
+    for (int i = 0; i < n_tris; ++i)
+        std::memcpy(tris_sorted_host + 9 * (size_t)i, tris_host + 9 * (size_t)bld.idx[i], 9 * sizeof(float));
+    *n_nodes = (int32_t)bld.nodes.size();
+    clear_error();
+    return MS_OK;
+}
+
+}  // extern "C"

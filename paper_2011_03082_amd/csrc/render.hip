@@ -18,6 +18,7 @@
 #include <math.h>
 
 #include "host.hpp"
+#include "mesh.hpp"
 #include "packed.hpp"
 
 namespace msst {
@@ -41,6 +42,9 @@ struct alignas(16) UnitRecord {
 struct RenderArgs {
     const float* prims;  // device [n_prims][8]
     int n_prims;
+    const BvhNode* bvh;  // mesh scenes: nodes and reordered triangles
+    const float* tris;
+    int n_nodes, n_tris;
     const uint16_t* grid;
     int res;
     float grid_lo[3], grid_inv_h[3], grid_half_diag;
@@ -387,9 +391,61 @@ struct GeoMany {
     }
 };
 
+// A closed triangle mesh: the crossings of each new ray's line (BVH
+// traversal) pair up into at most four medium intervals kept in registers;
+// radii come from the distance grid; shadow rays traverse their own line.
+struct GeoMesh {
+    const BvhNode* nodes;
+    const float* tris;
+    int n_nodes;
+    RayIv<4> iv;
+    __device__ __forceinline__ void init(const RenderArgs& A, const float*) {
+        nodes = A.bvh;
+        tris = A.tris;
+        n_nodes = A.n_nodes;
+    }
+    __device__ __forceinline__ void set_ray(V3 o, V3 d) {
+        float c[kMeshCross];
+        const int m = mesh_crossings(nodes, n_nodes, tris, o, d, c);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool pair = 2 * k + 1 < m;
+            iv.a[k] = pair ? c[2 * k] : INFINITY;
+            iv.b[k] = pair ? c[2 * k + 1] : -INFINITY;
+        }
+    }
+    __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
+    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const {
+        Prims<1> none;
+        none.n = 0;
+        return conservative_radius(A, none, p);
+    }
+    __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
+    __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
+        V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
+        const float dist2 = dot(wl, wl);
+        const float inv_dist = fast_rsq(dist2);
+        const float dist = dist2 * inv_dist;
+        wl = inv_dist * wl;
+        float c[kMeshCross];
+        const int m = mesh_crossings(nodes, n_nodes, tris, x, wl, c);
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMeshCross / 2; ++k)
+            if (2 * k + 1 < m)
+                acc += __builtin_fmaxf(0.0f, __builtin_fminf(c[2 * k + 1], dist) - __builtin_fmaxf(c[2 * k], 0.0f));
+        return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) * (inv_dist * inv_dist);
+    }
+};
+constexpr int kGeoMesh = 8;  // render_kernel template tag of mesh scenes
+
 template <int NP>
 struct GeoSel {
     typedef Geo<NP> type;
+};
+template <>
+struct GeoSel<kGeoMesh> {
+    typedef GeoMesh type;
 };
 template <>
 struct GeoSel<0> {
@@ -960,6 +1016,26 @@ __global__ void sdf_grid_kernel(const float* prims, int n_prims, int res, double
     }
 }
 
+// Mesh bodies: distance to the nearest triangle, negative where the ray from
+// the voxel centre along (1, 2, 3) / sqrt(14) crosses the mesh an odd number
+// of times.  Every triangle is visited (a pre-process).
+__global__ void sdf_grid_mesh_kernel(const float* tris, int n_tris, int res, double lox, double loy, double loz,
+                                     double hx, double hy, double hz, uint16_t* out) {
+    const double u[3] = {0.2672612419124244, 0.5345224838248488, 0.8017837257372732};
+    const int64_t total = (int64_t)res * res * res;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < total; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = v % res, j = (v / res) % res, k = v / ((int64_t)res * res);
+        const double p[3] = {lox + (i + 0.5) * hx, loy + (j + 0.5) * hy, loz + (k + 0.5) * hz};
+        double dmin = INFINITY;
+        int odd = 0;
+        for (int q = 0; q < n_tris; ++q) {
+            dmin = fmin(dmin, tri_distance64(tris + 9 * q, p));
+            odd ^= (int)tri_ray_crosses64(tris + 9 * q, p, u);
+        }
+        out[v] = fp16_bits_rtz(odd ? -dmin : dmin);
+    }
+}
+
 // Samples per work unit: small units balance the end of the persistent
 // kernel (a lane's last unit is its tail), large ones bound the partial
 // buffers.  About 2^24 units (64 per resident lane of a 256-CU device at
@@ -993,8 +1069,18 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                               void* workspace_dev, size_t workspace_bytes, void* stream) {
     using namespace msst;
     MS_REQUIRE(scene && cam && light && medium && desc && out, "sphere_trace_render: NULL descriptor");
-    MS_REQUIRE(scene->prims != nullptr && scene->n_prims >= 1 && scene->n_prims <= kMaxManyPrims,
-               "sphere_trace_render: need 1..256 primitives");
+    const bool mesh = scene->n_tris > 0;
+    if (mesh) {
+        MS_REQUIRE(scene->tris != nullptr && scene->bvh != nullptr && scene->n_nodes >= 1 &&
+                       scene->n_nodes <= 2 * scene->n_tris && scene->n_tris < (1 << 26),
+                   "sphere_trace_render: a mesh scene needs tris, bvh and 1 <= n_nodes <= 2 n_tris");
+        MS_REQUIRE(scene->sdf_fp16 != nullptr && scene->res >= 1,
+                   "sphere_trace_render: a mesh scene needs its distance grid");
+        MS_REQUIRE(((uintptr_t)scene->bvh & 15u) == 0, "sphere_trace_render: bvh must be 16-byte aligned");
+    } else {
+        MS_REQUIRE(scene->prims != nullptr && scene->n_prims >= 1 && scene->n_prims <= kMaxManyPrims,
+                   "sphere_trace_render: need 1..256 primitives");
+    }
     MS_REQUIRE(cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < ((int64_t)1 << 31),
                "sphere_trace_render: image size must be positive and below 2^31 pixels");
     MS_REQUIRE(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f, "sphere_trace_render: vfov must be in (0, 180)");
@@ -1032,7 +1118,11 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
 
     RenderArgs A{};
     A.prims = scene->prims;
-    A.n_prims = scene->n_prims;
+    A.n_prims = mesh ? 0 : scene->n_prims;
+    A.bvh = mesh ? reinterpret_cast<const BvhNode*>(scene->bvh) : nullptr;
+    A.tris = mesh ? scene->tris : nullptr;
+    A.n_nodes = mesh ? scene->n_nodes : 0;
+    A.n_tris = mesh ? scene->n_tris : 0;
     A.grid = scene->sdf_fp16;
     A.res = scene->res;
     for (int k = 0; k < 3; ++k) {
@@ -1110,7 +1200,11 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                      : (desc->sampler == MS_SAMPLER_EXACT_WALK ? kModeStExact : kModeStCvae);
     const dim3 grid((unsigned)blocks), block(64 * kRenderWaves);
 #define MS_RENDER_LAUNCH(M, N) hipLaunchKernelGGL((render_kernel<M, N>), grid, block, 0, hs, A)
-    if (A.n_prims <= 1) {
+    if (mesh) {
+        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, kGeoMesh);
+        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, kGeoMesh);
+        else MS_RENDER_LAUNCH(kModeStCvae, kGeoMesh);
+    } else if (A.n_prims <= 1) {
         if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 1);
         else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 1);
         else MS_RENDER_LAUNCH(kModeStCvae, 1);
@@ -1142,8 +1236,11 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
 
 extern "C" ms_status ms_build_sdf_grid(const ms_scene* scene, int32_t res, uint16_t* grid_dev, void* stream) {
     using namespace msst;
-    MS_REQUIRE(scene && scene->prims && grid_dev, "ms_build_sdf_grid: NULL argument");
-    MS_REQUIRE(scene->n_prims >= 1 && scene->n_prims <= kMaxManyPrims, "ms_build_sdf_grid: need 1..256 primitives");
+    MS_REQUIRE(scene && grid_dev, "ms_build_sdf_grid: NULL argument");
+    const bool mesh = scene->n_tris > 0;
+    MS_REQUIRE(mesh ? scene->tris != nullptr : scene->prims != nullptr, "ms_build_sdf_grid: NULL geometry");
+    MS_REQUIRE(mesh || (scene->n_prims >= 1 && scene->n_prims <= kMaxManyPrims),
+               "ms_build_sdf_grid: need 1..256 primitives or a mesh");
     MS_REQUIRE(res >= 1 && res <= 4096, "ms_build_sdf_grid: res must be in [1, 4096]");
     MS_REQUIRE(scene->hi[0] > scene->lo[0] && scene->hi[1] > scene->lo[1] && scene->hi[2] > scene->lo[2],
                "ms_build_sdf_grid: empty bounds");
@@ -1155,9 +1252,14 @@ extern "C" ms_status ms_build_sdf_grid(const ms_scene* scene, int32_t res, uint1
     if (blocks > (int64_t)cus * 16) blocks = (int64_t)cus * 16;
     const double h[3] = {((double)scene->hi[0] - scene->lo[0]) / res, ((double)scene->hi[1] - scene->lo[1]) / res,
                          ((double)scene->hi[2] - scene->lo[2]) / res};
-    hipLaunchKernelGGL(sdf_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, scene->prims,
-                       scene->n_prims, res, (double)scene->lo[0], (double)scene->lo[1], (double)scene->lo[2], h[0], h[1],
-                       h[2], grid_dev);
+    if (mesh)
+        hipLaunchKernelGGL(sdf_grid_mesh_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, scene->tris,
+                           scene->n_tris, res, (double)scene->lo[0], (double)scene->lo[1], (double)scene->lo[2], h[0],
+                           h[1], h[2], grid_dev);
+    else
+        hipLaunchKernelGGL(sdf_grid_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, scene->prims,
+                           scene->n_prims, res, (double)scene->lo[0], (double)scene->lo[1], (double)scene->lo[2], h[0],
+                           h[1], h[2], grid_dev);
     MS_LAUNCHED();
     clear_error();
     return MS_OK;
