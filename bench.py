@@ -63,6 +63,7 @@ def parse():
                     help="also train and score every Table 1 architecture that fits one tile (untimed)")
     ap.add_argument("--no-absorption", action="store_true")
     ap.add_argument("--no-rgb", action="store_true")
+    ap.add_argument("--no-mesh", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--absorption-sigma", type=float, default=80.0)
     ap.add_argument("--absorption-points", type=int, default=6)
@@ -531,6 +532,38 @@ def main():
         log(f"RGB: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {rgb['rmse_pt']:.2e} / {rgb['rmse_st']:.2e}, "
             f"speed-up {rgb['speedup_matched_rmse']:.2f}")
 
+    # a closed triangle mesh (a star-shaped body with a thin spike, 20 480
+    # triangles through the BVH), radii from a 128^3 grid built on the mesh
+    mesh = None
+    if not args.no_mesh:
+        tris = W.mesh_blob(0, 5)
+        lo, hi = (-1.2, -1.2, -1.2), (1.2, 1.2, 1.2)
+        t0 = time.time()
+        grid = M.build_sdf_grid(None, 128, lo, hi, tris=tris)
+        t_grid = time.time() - t0
+        mr = M.Renderer(None, W.camera_mesh(width, width), W.light_c4(), grid=grid, grid_lo=lo, grid_hi=hi, tris=tris)
+        mesh = {"workload": f"closed mesh, {tris.shape[0]} triangles, {width}x{width}, {spp} spp, g=0.8, albedo=0.995",
+                "grid_seconds": t_grid}
+        for s_ in (40.0, 80.0):
+            med = W.medium_c4(s_)
+            img = mr.render(med, method=1, spp=args.ref_spp // 2, seed=9300, **kw)
+            rm, rv = image_moments(img, args.ref_spp // 2)
+            noise2 = float(rv.mean()) / (args.ref_spp // 2)
+            img_pt, t_pt = timed(lambda: mr.render(med, method=1, spp=spp, seed=9400, **kw))
+            pm, pv = image_moments(img_pt, spp)
+            img_st, t_st = timed(lambda: mr.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=9500,
+                                                   tau_min=args.tau_min, nee_samples=args.nee_samples,
+                                                   flags=args.nee_flags, **kw))
+            sm, _ = image_moments(img_st, spp)
+            e_st = max(float(((sm - rm) ** 2).mean()) - noise2, 1e-30)
+            e_pt = max(float(((pm - rm) ** 2).mean()) - noise2, 1e-30)
+            c = img_st["counters"].cpu().numpy()
+            mesh[str(s_)] = dict(pt_ms=t_pt * 1e3, st_ms=t_st * 1e3, rmse_pt=float(np.sqrt(e_pt)),
+                                 rmse_st=float(np.sqrt(e_st)), st_steps_per_path=float(c[2] / c[0]),
+                                 speedup_matched_rmse=float(pv.mean()) / e_st / spp * t_pt / t_st)
+            log(f"mesh sigma_t={s_}: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {np.sqrt(e_pt):.2e} / "
+                f"{np.sqrt(e_st):.2e}, speed-up {mesh[str(s_)]['speedup_matched_rmse']:.2f}")
+
     # absorption sweep (the paper's absorption experiment): one density, the
     # absorption 1 - albedo doubled from 2e-4; rendering time and error of
     # both tracers at the same spp, matched-RMSE speed-up
@@ -627,6 +660,7 @@ def main():
         "table1_sweep": sweep,
         "absorption_sweep": absorption,
         "rgb": rgb,
+        "mesh": mesh,
         "focus_training": focus,
         "diagnostics": diag,
         "wall_s_timed": wall,
