@@ -273,9 +273,11 @@ typedef struct {
     /* Optional closed triangle mesh (the polygon-mesh boundary the paper
      * renders): when n_tris > 0 the body is the mesh interior and prims are
      * ignored.  tris: device [n_tris][9] vertex triples in the order
-     * ms_build_mesh_bvh returns, bvh: its device node array.  A line's
-     * crossings pair up as (entry, exit); up to 8 crossings per line are
-     * kept (the nearest along it). */
+     * ms_build_mesh_bvh returns, bvh: its device node array.  Camera rays
+     * start outside the body and every other ray inside it (at a collision
+     * or a sphere-step exit), so the crossings ahead of a ray's origin
+     * alternate entry / exit (resp. exit / entry); up to 8 are kept, the
+     * nearest first. */
     const float* tris;
     int32_t n_tris;
     const void* bvh;

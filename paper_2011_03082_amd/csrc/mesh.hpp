@@ -19,8 +19,8 @@ struct alignas(16) BvhNode {
 static_assert(sizeof(BvhNode) == 32, "BvhNode is 32 bytes");
 constexpr int kBvhLeafMax = 4;
 
-// Does the whole line o + t d (any t) meet the box?
-__device__ __forceinline__ bool line_box(const BvhNode& nd, V3 o, V3 inv) {
+// Does the segment o + t d, tlo <= t <= thi, meet the box?
+__device__ __forceinline__ bool line_box(const BvhNode& nd, V3 o, V3 inv, float tlo, float thi) {
     const float ax = (nd.lo[0] - o.x) * inv.x, bx = (nd.hi[0] - o.x) * inv.x;
     const float ay = (nd.lo[1] - o.y) * inv.y, by = (nd.hi[1] - o.y) * inv.y;
     const float az = (nd.lo[2] - o.z) * inv.z, bz = (nd.hi[2] - o.z) * inv.z;
@@ -28,7 +28,7 @@ __device__ __forceinline__ bool line_box(const BvhNode& nd, V3 o, V3 inv) {
                                      __builtin_fminf(az, bz));
     const float t1 = __builtin_fminf(__builtin_fminf(__builtin_fmaxf(ax, bx), __builtin_fmaxf(ay, by)),
                                      __builtin_fmaxf(az, bz));
-    return t0 <= t1;
+    return __builtin_fmaxf(t0, tlo) <= __builtin_fminf(t1, thi);
 }
 
 // Line parameter of the crossing with triangle tr (Moller and Trumbore,
@@ -52,22 +52,23 @@ __device__ __forceinline__ bool tri_cross(const float* tr, V3 o, V3 d, float& t)
 
 constexpr int kMeshCross = 8;  // crossings of one line kept (sorted)
 
-// All crossings of the line o + t d with the mesh, sorted, in c[0 .. m) (at
-// most kMeshCross; more are dropped from the end of the sorted order).
+// The crossings of the segment o + t d, tlo < t <= thi, with the mesh,
+// sorted, in c[0 .. m) (at most kMeshCross; more are dropped from the end of
+// the sorted order).  Boxes the segment misses are skipped whole.
 __device__ __forceinline__ int mesh_crossings(const BvhNode* nodes, int n_nodes, const float* tris, V3 o, V3 d,
-                                              float* c) {
+                                              float tlo, float thi, float* c) {
     const V3 inv = v3(fast_rcp(d.x), fast_rcp(d.y), fast_rcp(d.z));
 #pragma unroll
     for (int j = 0; j < kMeshCross; ++j) c[j] = INFINITY;
     int m = 0;
     for (int i = 0; i < n_nodes;) {
         const BvhNode nd = nodes[i];
-        const bool hit = line_box(nd, o, inv);
+        const bool hit = line_box(nd, o, inv, tlo, thi);
         if (hit && nd.leaf >= 0) {
             const int first = nd.leaf >> 4, cnt = nd.leaf & 15;
             for (int k = 0; k < cnt; ++k) {
                 float t;
-                if (tri_cross(tris + 9 * (first + k), o, d, t)) {
+                if (tri_cross(tris + 9 * (first + k), o, d, t) && t > tlo && t <= thi) {
                     // insertion into the sorted slots (the largest falls off)
 #pragma unroll
                     for (int j = kMeshCross - 1; j >= 0; --j) {

@@ -244,6 +244,7 @@ struct Geo {
             for (int k = 0; k < 8; ++k) P.p[i][k] = i < A.n_prims ? A.prims[i * 8 + k] : 0.0f;
     }
     __device__ __forceinline__ void set_ray(V3 o, V3 d) { ray_intervals(P, o, d, iv); }
+    __device__ __forceinline__ void set_camera_ray(V3 o, V3 d) { ray_intervals(P, o, d, iv); }
     __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
     __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const { return conservative_radius(A, P, p); }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
@@ -265,6 +266,7 @@ struct GeoMany {
         n = A.n_prims;
     }
     __device__ __forceinline__ void set_ray(V3, V3) {}
+    __device__ __forceinline__ void set_camera_ray(V3, V3) {}
     __device__ __forceinline__ bool piece(V3 o, V3 d, float t, float& s, float& e) const {
         float ca[kHitSlots], cb[kHitSlots];
         int m = 0;
@@ -391,9 +393,11 @@ struct GeoMany {
     }
 };
 
-// A closed triangle mesh: the crossings of each new ray's line (BVH
-// traversal) pair up into at most four medium intervals kept in registers;
-// radii come from the distance grid; shadow rays traverse their own line.
+// A closed triangle mesh: the crossings ahead of each new ray's origin (BVH
+// traversal of the half-line) alternate exit / entry from a scattering
+// point inside the body and entry / exit from the camera; up to four medium
+// intervals are kept in registers.  Radii come from the distance grid;
+// shadow rays traverse their own segment to the light.
 struct GeoMesh {
     const BvhNode* nodes;
     const float* tris;
@@ -404,14 +408,18 @@ struct GeoMesh {
         tris = A.tris;
         n_nodes = A.n_nodes;
     }
-    __device__ __forceinline__ void set_ray(V3 o, V3 d) {
+    __device__ __forceinline__ void set_ray(V3 o, V3 d) { set_ray_from(o, d, true); }
+    __device__ __forceinline__ void set_camera_ray(V3 o, V3 d) { set_ray_from(o, d, false); }
+    __device__ __forceinline__ void set_ray_from(V3 o, V3 d, bool inside) {
         float c[kMeshCross];
-        const int m = mesh_crossings(nodes, n_nodes, tris, o, d, c);
+        const int m = mesh_crossings(nodes, n_nodes, tris, o, d, 0.0f, INFINITY, c);
+        // inside: (-inf, c0), (c1, c2), (c3, c4), ...; outside: (c0, c1), (c2, c3), ...
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool pair = 2 * k + 1 < m;
-            iv.a[k] = pair ? c[2 * k] : INFINITY;
-            iv.b[k] = pair ? c[2 * k + 1] : -INFINITY;
+            const float a_in = k == 0 ? -INFINITY : c[2 * k - 1];
+            const bool ok = inside ? 2 * k < m : 2 * k + 1 < m;
+            iv.a[k] = ok ? (inside ? a_in : c[2 * k]) : INFINITY;
+            iv.b[k] = ok ? (inside ? c[2 * k] : c[2 * k + 1]) : -INFINITY;
         }
     }
     __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
@@ -428,12 +436,16 @@ struct GeoMesh {
         const float dist = dist2 * inv_dist;
         wl = inv_dist * wl;
         float c[kMeshCross];
-        const int m = mesh_crossings(nodes, n_nodes, tris, x, wl, c);
-        float acc = 0.0f;
+        const int m = mesh_crossings(nodes, n_nodes, tris, x, wl, 0.0f, dist, c);
+        // x is inside: inside until c[0], outside until c[1], ...
+        float acc = 0.0f, prev = 0.0f;
 #pragma unroll
-        for (int k = 0; k < kMeshCross / 2; ++k)
-            if (2 * k + 1 < m)
-                acc += __builtin_fmaxf(0.0f, __builtin_fminf(c[2 * k + 1], dist) - __builtin_fmaxf(c[2 * k], 0.0f));
+        for (int k = 0; k < kMeshCross; ++k)
+            if (k < m) {
+                if ((k & 1) == 0) acc += c[k] - prev;
+                prev = c[k];
+            }
+        if ((m & 1) == 0) acc += dist - prev;
         return A.intensity * hg_eval(A.g, dot(d, wl)) * fast_exp(-A.sigma_t * acc) * (inv_dist * inv_dist);
     }
 };
@@ -656,7 +668,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0],
                                  A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
                                  A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
-                G.set_ray(o, d);
+                G.set_camera_ray(o, d);
                 t = 0.0f;
                 Lp = 0.0f;
                 c0 = 0;
