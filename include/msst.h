@@ -285,7 +285,8 @@ typedef struct {
 } ms_scene;
 
 /* Bounding-volume hierarchy of a closed triangle mesh, built on the host:
- * median splits on the longest centroid axis, leaves of up to 4 triangles,
+ * binned surface-area-heuristic splits (median splits where the bins cannot
+ * separate the triangles), leaves of up to 4 triangles,
  * 32-byte nodes in depth-first order with skip links (stackless traversal).
  * tris_host: [n_tris][9] floats; writes the nodes (at most 2 n_tris, size
  * from ms_mesh_bvh_size) and the triangles reordered to the leaves' order
