@@ -181,27 +181,21 @@ __device__ __forceinline__ float fp16_value(uint16_t h) {
     return (float)__builtin_bit_cast(_Float16, h);
 }
 
-// Radius of a sphere around p inside the body (see the C header): analytic
-// union distance shrunk by 0.1 %, or nearest grid voxel minus half a voxel
-// diagonal.
-template <int NP>
-__device__ __forceinline__ float conservative_radius(const RenderArgs& A, const Prims<NP>& P, V3 p) {
-    if (A.grid) {
-        const float fx = (p.x - A.grid_lo[0]) * A.grid_inv_h[0];
-        const float fy = (p.y - A.grid_lo[1]) * A.grid_inv_h[1];
-        const float fz = (p.z - A.grid_lo[2]) * A.grid_inv_h[2];
-        const float fr = (float)A.res;
-        if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f && fx < fr && fy < fr && fz < fr)) return 0.0f;
-        const int64_t ix = (int64_t)fx, iy = (int64_t)fy, iz = (int64_t)fz;
-        const float s = fp16_value(A.grid[(iz * A.res + iy) * A.res + ix]);
-        return __builtin_fmaxf(0.0f, -s - A.grid_half_diag);
-    }
-    float s = INFINITY;
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-        if (i < P.n) s = __builtin_fminf(s, prim_sdf(P.p[i], p));
-    return s < 0.0f ? -0.999f * s : 0.0f;
+// Radius of a sphere around p inside the body (see the C header): the
+// nearest grid voxel's distance minus half a voxel diagonal ...
+__device__ __forceinline__ float grid_radius(const RenderArgs& A, V3 p) {
+    const float fx = (p.x - A.grid_lo[0]) * A.grid_inv_h[0];
+    const float fy = (p.y - A.grid_lo[1]) * A.grid_inv_h[1];
+    const float fz = (p.z - A.grid_lo[2]) * A.grid_inv_h[2];
+    const float fr = (float)A.res;
+    if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f && fx < fr && fy < fr && fz < fr)) return 0.0f;
+    const int64_t ix = (int64_t)fx, iy = (int64_t)fy, iz = (int64_t)fz;
+    const float s = fp16_value(A.grid[(iz * A.res + iy) * A.res + ix]);
+    return __builtin_fmaxf(0.0f, -s - A.grid_half_diag);
 }
+
+// ... or, without a grid, the analytic union distance shrunk by 0.1 %.
+__device__ __forceinline__ float union_radius(float s) { return s < 0.0f ? -0.999f * s : 0.0f; }
 
 // Point-light next-event estimate at x for a path travelling along d:
 // I rho_g(d . w_{x->L}) exp(-sigma_t d_t) / |x_L - x|^2 (Sec. 4.3).
@@ -232,7 +226,7 @@ __device__ __forceinline__ float nee(const RenderArgs& A, const Prims<NP>& P, V3
 
 // Few primitives (NP <= 4) in registers; the intervals of the current ray
 // are computed once per ray and kept in registers.
-template <int NP>
+template <int NP, bool GRID>
 struct Geo {
     Prims<NP> P;
     RayIv<NP> iv;
@@ -246,7 +240,14 @@ struct Geo {
     __device__ __forceinline__ void set_ray(V3 o, V3 d) { ray_intervals(P, o, d, iv); }
     __device__ __forceinline__ void set_camera_ray(V3 o, V3 d) { ray_intervals(P, o, d, iv); }
     __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
-    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const { return conservative_radius(A, P, p); }
+    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const {
+        if (GRID) return grid_radius(A, p);
+        float s = INFINITY;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            if (i < P.n) s = __builtin_fminf(s, prim_sdf(P.p[i], p));
+        return union_radius(s);
+    }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
     __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const { return nee(A, P, x, d); }
 };
@@ -258,6 +259,7 @@ struct Geo {
 constexpr int kMaxManyPrims = 256;
 constexpr int kHitSlots = 8;
 
+template <bool GRID>
 struct GeoMany {
     const float* prim;  // LDS [n][8]
     int n;
@@ -310,14 +312,10 @@ struct GeoMany {
         return true;
     }
     __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const {
-        if (A.grid) {
-            Prims<1> none;
-            none.n = 0;
-            return conservative_radius(A, none, p);
-        }
+        if (GRID) return grid_radius(A, p);
         float sd = INFINITY;
         for (int i = 0; i < n; ++i) sd = __builtin_fminf(sd, prim_sdf(prim + 8 * i, p));
-        return sd < 0.0f ? -0.999f * sd : 0.0f;
+        return union_radius(sd);
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
     // Shadow ray: one pass over the primitives collects the hit intervals
@@ -423,11 +421,7 @@ struct GeoMesh {
         }
     }
     __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
-    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const {
-        Prims<1> none;
-        none.n = 0;
-        return conservative_radius(A, none, p);
-    }
+    __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const { return grid_radius(A, p); }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
     __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
         V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
@@ -451,17 +445,19 @@ struct GeoMesh {
 };
 constexpr int kGeoMesh = 8;  // render_kernel template tag of mesh scenes
 
-template <int NP>
+// Geometry policy of a kernel instance; GRID fixes the radius source at
+// compile time (a mesh always has its grid).
+template <int NP, bool GRID>
 struct GeoSel {
-    typedef Geo<NP> type;
+    typedef Geo<NP, GRID> type;
 };
-template <>
-struct GeoSel<kGeoMesh> {
+template <bool GRID>
+struct GeoSel<kGeoMesh, GRID> {
     typedef GeoMesh type;
 };
-template <>
-struct GeoSel<0> {
-    typedef GeoMany type;
+template <bool GRID>
+struct GeoSel<0, GRID> {
+    typedef GeoMany<GRID> type;
 };
 
 // ---------------------------------------------------------------- kernel
@@ -570,7 +566,7 @@ __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L,
 
 // Four waves per SIMD: measured faster than the unconstrained allocation
 // (three waves) despite a few spilled registers.
-template <int MODE, int NP>
+template <int MODE, int NP, bool GRID>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
     __shared__ RenderLds lds_all[kRenderWaves];
     __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
@@ -579,7 +575,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
         for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
         __syncthreads();
     }
-    typename GeoSel<NP>::type G;
+    typename GeoSel<NP, GRID>::type G;
     G.init(A, lds_prims);
 
     TicketPool pool;
@@ -1052,6 +1048,14 @@ __global__ void sdf_grid_mesh_kernel(const float* tris, int n_tris, int res, dou
 // kernel (a lane's last unit is its tail), large ones bound the partial
 // buffers.  About 2^24 units (64 per resident lane of a 256-CU device at
 // four 256-thread blocks per CU), and at least 2 samples per unit.
+// One render_kernel instance per (mode, geometry policy, radius source).
+template <int NP, bool GRID>
+static void launch_render(int mode, dim3 grid, dim3 block, hipStream_t hs, const RenderArgs& A) {
+    if (mode == kModePlain) hipLaunchKernelGGL((render_kernel<kModePlain, NP, GRID>), grid, block, 0, hs, A);
+    else if (mode == kModeStExact) hipLaunchKernelGGL((render_kernel<kModeStExact, NP, GRID>), grid, block, 0, hs, A);
+    else hipLaunchKernelGGL((render_kernel<kModeStCvae, NP, GRID>), grid, block, 0, hs, A);
+}
+
 static int default_chunk(int64_t npix, int spp) {
     int64_t c = (npix * spp + (1 << 24) - 1) >> 24;
     if (c < 2) c = 2;
@@ -1211,29 +1215,12 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     const int mode = desc->method == MS_METHOD_PLAIN_NEE ? kModePlain
                      : (desc->sampler == MS_SAMPLER_EXACT_WALK ? kModeStExact : kModeStCvae);
     const dim3 grid((unsigned)blocks), block(64 * kRenderWaves);
-#define MS_RENDER_LAUNCH(M, N) hipLaunchKernelGGL((render_kernel<M, N>), grid, block, 0, hs, A)
-    if (mesh) {
-        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, kGeoMesh);
-        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, kGeoMesh);
-        else MS_RENDER_LAUNCH(kModeStCvae, kGeoMesh);
-    } else if (A.n_prims <= 1) {
-        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 1);
-        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 1);
-        else MS_RENDER_LAUNCH(kModeStCvae, 1);
-    } else if (A.n_prims == 2) {
-        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 2);
-        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 2);
-        else MS_RENDER_LAUNCH(kModeStCvae, 2);
-    } else if (A.n_prims <= 4) {
-        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 4);
-        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 4);
-        else MS_RENDER_LAUNCH(kModeStCvae, 4);
-    } else {
-        if (mode == kModePlain) MS_RENDER_LAUNCH(kModePlain, 0);
-        else if (mode == kModeStExact) MS_RENDER_LAUNCH(kModeStExact, 0);
-        else MS_RENDER_LAUNCH(kModeStCvae, 0);
-    }
-#undef MS_RENDER_LAUNCH
+    const bool grid_r = A.grid != nullptr;
+    if (mesh) launch_render<kGeoMesh, true>(mode, grid, block, hs, A);
+    else if (A.n_prims <= 1) grid_r ? launch_render<1, true>(mode, grid, block, hs, A) : launch_render<1, false>(mode, grid, block, hs, A);
+    else if (A.n_prims == 2) grid_r ? launch_render<2, true>(mode, grid, block, hs, A) : launch_render<2, false>(mode, grid, block, hs, A);
+    else if (A.n_prims <= 4) grid_r ? launch_render<4, true>(mode, grid, block, hs, A) : launch_render<4, false>(mode, grid, block, hs, A);
+    else grid_r ? launch_render<0, true>(mode, grid, block, hs, A) : launch_render<0, false>(mode, grid, block, hs, A);
     MS_LAUNCHED();
     int64_t rb = (A.npix + 3) / 4;  // four pixels (waves) per block
     if (rb > cus * 16) rb = cus * 16;
