@@ -469,10 +469,31 @@ __device__ __forceinline__ void neumaier_add(float& sum, float& comp, float v) {
     sum = t;
 }
 
-// Sum_{i<=N} albedo^i / albedo^N = albedo (albedo^-N - 1) / (1 - albedo).
+// e^x - 1 and 1 - e^-x for x >= 0 without cancellation: below 1/64 a
+// four-term Taylor series (relative truncation below x^4 / 120), above it
+// the exponential.
+__device__ __forceinline__ float exp_minus_one(float x) {
+    if (x < 0.015625f) return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f))));
+    return fast_exp(x) - 1.0f;
+}
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
+    if (x < 0.015625f) return x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f))));
+    return 1.0f - fast_exp(-x);
+}
+
+// Lambda^(N) = Sum_{i<=N} albedo^i = albedo (1 - albedo^N) / (1 - albedo),
+// bounded by albedo / (1 - albedo) for any N.
+__device__ __forceinline__ float lambda_total(const RenderArgs& A, float N) {
+    if (A.albedo >= 1.0f) return N;
+    return fast_div(A.albedo * one_minus_exp_neg(-N * A.ln_albedo), 1.0f - A.albedo);
+}
+
+// Lambda^(N) / albedo^N = albedo (albedo^-N - 1) / (1 - albedo), the weight
+// of a surviving step; it only matters while albedo^N >= 2^-24 (a survivor),
+// so the exponent is capped where it would overflow.
 __device__ __forceinline__ float lambda_weight(const RenderArgs& A, float N) {
     if (A.albedo >= 1.0f) return N;
-    return fast_div(A.albedo * (fast_exp(-N * A.ln_albedo) - 1.0f), 1.0f - A.albedo);
+    return fast_div(A.albedo * exp_minus_one(__builtin_fminf(80.0f, -N * A.ln_albedo)), 1.0f - A.albedo);
 }
 
 // Writes this lane's part of its decoder input row -- the standardised
@@ -811,8 +832,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 const bool before = (A.flags & MS_RENDER_NEE_BEFORE_ABSORPTION) != 0;
                 const bool lit = before ? mine : alive;
                 const bool use_path = lit && N >= 2.0f;
-                const float wgt = lambda_weight(A, N);
-                const float w_nee = (before ? wgt * phiN : wgt) / (float)A.nee_samples;
+                // Lambda and Lambda / albedo^N each in a form that stays finite
+                // for any N (their product form overflows once albedo^-N does)
+                const float lam = lambda_total(A, N);
+                const float w_nee = (before ? lam : lambda_weight(A, N)) / (float)A.nee_samples;
                 float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
                 if (lit && !use_path) ct = hg_sample(A.g, u_hg).mu;
                 const uint64_t pmask = ballot(use_path);
@@ -847,7 +870,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                 for (int k = 0; k < A.nee_samples; ++k) {
                     float uf = u_first;
                     if (k > 0 && lit) uf = u01(rng.block(c0++).x);
-                    const bool use_event = use_path && !(uf * wgt * phiN <= A.albedo);
+                    const bool use_event = use_path && !(uf * lam <= A.albedo);
                     V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
                     const uint64_t emask = ballot(use_event);
                     if (emask) {

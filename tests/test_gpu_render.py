@@ -139,6 +139,27 @@ def test_learned_steps_with_several_events_path_by_path(msst, oracle, nee_sample
     assert frac < 0.03
 
 
+@pytest.mark.parametrize("flags", [0, 1])
+def test_learned_steps_with_very_long_chains_path_by_path(msst, oracle, flags):
+    """LengthGen answering chains of ~10^5 events at albedo 0.995: albedo^-N
+    overflows binary32, yet the step weights Lambda (Sec. 4.3) and the
+    first-event probability stay finite and match the oracle path by path."""
+    announce(f"render ST CVAE parity, very long chains, flags={flags}")
+    prims, cam, light, med = c4_inputs(20.0, 40)
+    models, src = models_for_test(oracle)
+    models[0]["stats"][32] = np.log(1e5)  # mean of log N
+    packed = pack_all(msst, src, 1)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=16,
+                   nee_samples=2, flags=flags)
+    assert np.isfinite(g["sum"]).all() and np.isfinite(g["comp"]).all()
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      precision=oracle.PREC_BF16, models=models, spp=1, seed=16, nee_samples=2, flags=flags)
+    frac, _ = compare_paths(g, o, rel=2e-3)
+    print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, lit sum {o['sum'].sum():.4g}")
+    assert o["steps"].sum() > 100
+    assert frac < 0.03
+
+
 def test_tau_above_all_radii_is_plain(msst):
     announce("render ST with tau_min huge")
     prims, cam, light, med = c4_inputs(10.0, 32)
