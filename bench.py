@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--no-rgb", action="store_true")
     ap.add_argument("--no-mesh", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
+    ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--density-sigmas", type=str, default="80,160,320,640,1280")
+    ap.add_argument("--density-albedo", type=float, default=0.9999)
+    ap.add_argument("--density-width", type=int, default=256)
     ap.add_argument("--absorption-sigma", type=float, default=80.0)
     ap.add_argument("--absorption-points", type=int, default=6)
     ap.add_argument("--restart-min", type=int, default=0)
@@ -592,6 +596,40 @@ def main():
             log(f"absorption {a:.1e}: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {e_pt:.2e} / {e_st:.2e}, "
                 f"speed-up {row['speedup_matched_rmse']:.2f}")
 
+    # density sweep (the paper's density experiments, Sec. 5.4: doubling
+    # densities of a nearly non-absorbing medium): smaller image, same
+    # matched-RMSE procedure, plus the mean bias of the sphere tracer
+    density = None
+    if not args.no_density:
+        density = []
+        dw = args.density_width
+        drend = M.Renderer(W.scene_c4(), W.camera_c4(dw, dw), W.light_c4())
+        for k, s_ in enumerate(float(x) for x in args.density_sigmas.split(",")):
+            med = dict(W.medium_c4(s_), albedo=args.density_albedo)
+            img = drend.render(med, method=1, spp=args.ref_spp, seed=9000 + k, **kw)
+            r_mean, r_var = image_moments(img, args.ref_spp)
+            r_noise2 = float(r_var.mean()) / args.ref_spp
+            img_pt, t_pt = timed(lambda: drend.render(med, method=1, spp=spp, seed=9100 + k, **kw))
+            pm, pv = image_moments(img_pt, spp)
+            img_st, t_st = timed(lambda: drend.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=9200 + k,
+                                                      tau_min=args.tau_min, nee_samples=args.nee_samples,
+                                                      flags=args.nee_flags, **kw))
+            sm, _ = image_moments(img_st, spp)
+            e_st = float(np.sqrt(max(float(((sm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+            e_pt = float(np.sqrt(max(float(((pm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+            cp, cs = img_pt["counters"].cpu().numpy(), img_st["counters"].cpu().numpy()
+            row = dict(sigma_t=s_, pt_ms=t_pt * 1e3, st_ms=t_st * 1e3, rmse_pt=e_pt, rmse_st=e_st,
+                       pt_events_per_path=float(cp[1] / cp[0]), st_events_per_path=float(cs[1] / cs[0]),
+                       st_steps_per_path=float(cs[2] / cs[0]),
+                       st_mean_bias=float(sm.mean() / r_mean.mean() - 1.0),
+                       speedup_matched_rmse=float(pv.mean()) / e_st**2 / spp * t_pt / t_st)
+            density.append(row)
+            log(f"density sigma_t={s_:g} (albedo {args.density_albedo}): PT {t_pt * 1e3:.1f} ms "
+                f"({row['pt_events_per_path']:.1f} events/path), ST {t_st * 1e3:.1f} ms "
+                f"({row['st_events_per_path']:.1f} events + {row['st_steps_per_path']:.2f} steps), "
+                f"rmse {e_pt:.2e} / {e_st:.2e}, bias {row['st_mean_bias']:+.3f}, "
+                f"speed-up {row['speedup_matched_rmse']:.2f}")
+
     sweep = None
     if args.table1_sweep:
         log("Table 1 architecture sweep")
@@ -658,6 +696,9 @@ def main():
         "c5": c5,
         "table1": table1,
         "table1_sweep": sweep,
+        "density_sweep": None if density is None else {
+            "workload": f"sphere+box scene {args.density_width}x{args.density_width}, {spp} spp, g=0.8, "
+                        f"albedo={args.density_albedo}, doubling sigma_t", "rows": density},
         "absorption_sweep": absorption,
         "rgb": rgb,
         "mesh": mesh,

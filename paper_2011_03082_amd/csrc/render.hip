@@ -168,13 +168,15 @@ __device__ __forceinline__ bool union_piece(const RayIv<NP>& iv, float t, float&
     return true;
 }
 
-__device__ __forceinline__ float prim_sdf(const float* pr, V3 p) {
+// Signed distance of one primitive where it is negative (p inside); outside
+// only its sign is kept (a box returns its largest axis excess, a lower
+// bound of the distance).  The union radius only reads the most negative
+// value, so it equals the one from the exact distances.
+__device__ __forceinline__ float prim_depth(const float* pr, V3 p) {
     const V3 q = v3(p.x - pr[1], p.y - pr[2], p.z - pr[3]);
     if (pr[0] == 0.0f) return fast_sqrt(dot(q, q)) - pr[4];
     const float ex = __builtin_fabsf(q.x) - pr[4], ey = __builtin_fabsf(q.y) - pr[5], ez = __builtin_fabsf(q.z) - pr[6];
-    const float ox = __builtin_fmaxf(ex, 0.0f), oy = __builtin_fmaxf(ey, 0.0f), oz = __builtin_fmaxf(ez, 0.0f);
-    const float inside = __builtin_fminf(__builtin_fmaxf(ex, __builtin_fmaxf(ey, ez)), 0.0f);
-    return fast_sqrt(ox * ox + oy * oy + oz * oz) + inside;
+    return __builtin_fmaxf(ex, __builtin_fmaxf(ey, ez));
 }
 
 __device__ __forceinline__ float fp16_value(uint16_t h) {
@@ -245,7 +247,7 @@ struct Geo {
         float s = INFINITY;
 #pragma unroll
         for (int i = 0; i < NP; ++i)
-            if (i < P.n) s = __builtin_fminf(s, prim_sdf(P.p[i], p));
+            if (i < P.n) s = __builtin_fminf(s, prim_depth(P.p[i], p));
         return union_radius(s);
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
@@ -314,7 +316,7 @@ struct GeoMany {
     __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const {
         if (GRID) return grid_radius(A, p);
         float sd = INFINITY;
-        for (int i = 0; i < n; ++i) sd = __builtin_fminf(sd, prim_sdf(prim + 8 * i, p));
+        for (int i = 0; i < n; ++i) sd = __builtin_fminf(sd, prim_depth(prim + 8 * i, p));
         return union_radius(sd);
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
