@@ -160,6 +160,28 @@ def test_learned_steps_with_very_long_chains_path_by_path(msst, oracle, flags):
     assert frac < 0.03
 
 
+@pytest.mark.parametrize("sigma_t", [320.0, 1280.0])
+def test_dense_nearly_white_medium_learned_path_by_path(msst, oracle, sigma_t):
+    """The density sweep's media (albedo 0.9999, sigma_t up to 1280): radii
+    capped at st_max / sigma_t, long plain chains near the surface; same
+    per-path values as the oracle."""
+    announce(f"render ST CVAE parity, dense medium sigma_t={sigma_t}")
+    prims, cam, light, med = c4_inputs(sigma_t, 40)
+    med["albedo"] = float(np.float32(0.9999))
+    models, src = models_for_test(oracle)
+    packed = pack_all(msst, src, 1)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=17,
+                   tau_min=6.0, nee_samples=2, flags=1)
+    assert np.isfinite(g["sum"]).all()
+    o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
+                      precision=oracle.PREC_BF16, models=models, spp=1, seed=17, tau_min=6.0, nee_samples=2,
+                      flags=1)
+    frac, _ = compare_paths(g, o, rel=2e-3)
+    print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
+    assert o["steps"].sum() > 100
+    assert frac < 0.03
+
+
 def test_tau_above_all_radii_is_plain(msst):
     announce("render ST with tau_min huge")
     prims, cam, light, med = c4_inputs(10.0, 32)
