@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-mesh", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-walk-full", action="store_true")
+    ap.add_argument("--walk-full-photons", type=int, default=1 << 24)
     ap.add_argument("--density-sigmas", type=str, default="80,160,320,640,1280")
     ap.add_argument("--density-albedo", type=float, default=0.9999)
     ap.add_argument("--density-width", type=int, default=256)
@@ -596,6 +598,28 @@ def main():
             log(f"absorption {a:.1e}: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {e_pt:.2e} / {e_st:.2e}, "
                 f"speed-up {row['speedup_matched_rmse']:.2f}")
 
+    # training-data walk at its full size (2^24 photons, parameters drawn per
+    # photon as in training), both representative-event weightings; outputs
+    # and workspace allocated before the timed launch, counters reset inside
+    walk_full = None
+    if not args.no_walk_full:
+        walk_full = {}
+        n_w = args.walk_full_photons
+        for name, ew in (("albedo_power", 0), ("uniform", 1)):
+            desc = M.walk_desc(n_w, seed=0, mode=1, event_weighting=ew)
+            wout = M.alloc_walk_outputs(n_w, 1)
+            wws = torch.empty(M.ms_random_walk_workspace_size(desc), dtype=torch.uint8, device="cuda")
+            M.ms_random_walk(desc, wout, wws)  # warm-up
+            wout["counters"].zero_()
+            _, t_w = timed(lambda: M.ms_random_walk(desc, wout, wws))
+            cw = wout["counters"].cpu().numpy()
+            walk_full[name] = dict(photons=n_w, events=int(cw[0]), seconds=t_w, events_per_s=cw[0] / t_w,
+                                   max_chain=int(cw[3]),
+                                   roofline_frac=cw[0] * OPS_PER_WALK_EVENT / t_w / PEAK_VALU_LANEOPS)
+            log(f"walk {n_w} photons ({name}): {t_w * 1e3:.1f} ms, {cw[0]:.3e} events, {cw[0] / t_w:.3e} events/s, "
+                f"longest chain {int(cw[3])}")
+            del wout, wws
+
     # density sweep (the paper's density experiments, Sec. 5.4: doubling
     # densities of a nearly non-absorbing medium): smaller image, same
     # matched-RMSE procedure, plus the mean bias of the sphere tracer
@@ -696,6 +720,9 @@ def main():
         "c5": c5,
         "table1": table1,
         "table1_sweep": sweep,
+        "walk_full": None if walk_full is None else dict(
+            walk_full, workload=f"training walks, {args.walk_full_photons} photons, sigma_t r log-uniform [0.1, 200], "
+                                "g U[-0.9, 0.95], albedo U[0.9, 1]"),
         "density_sweep": None if density is None else {
             "workload": f"sphere+box scene {args.density_width}x{args.density_width}, {spp} spp, g=0.8, "
                         f"albedo={args.density_albedo}, doubling sigma_t", "rows": density},
