@@ -33,6 +33,10 @@ MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + Even
 OPS_PER_WALK_EVENT = 205.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
 PEAK_MFMA_BF16 = 2.5e15
+PEAK_HBM_BYTES = 8.0e12
+# active-lane VALU slots per decoded sample of cvae_sample for the standard
+# shapes (latent 4, width 16, three layers), (model, precision 1 BF16 / 2 FP8)
+SAMPLE_VALU_SLOTS = {(0, 1): 709.0, (0, 2): 761.0, (1, 1): 739.0, (1, 2): 791.0, (2, 1): 874.0, (2, 2): 926.0}
 
 
 def log(msg):
@@ -67,6 +71,8 @@ def parse():
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--no-density", action="store_true")
     ap.add_argument("--no-walk-full", action="store_true")
+    ap.add_argument("--no-sample", action="store_true")
+    ap.add_argument("--sample-rows", type=int, default=1 << 24)
     ap.add_argument("--walk-full-photons", type=int, default=1 << 24)
     ap.add_argument("--density-sigmas", type=str, default="80,160,320,640,1280")
     ap.add_argument("--density-albedo", type=float, default=0.9999)
@@ -598,6 +604,35 @@ def main():
             log(f"absorption {a:.1e}: PT {t_pt * 1e3:.1f} ms, ST {t_st * 1e3:.1f} ms, rmse {e_pt:.2e} / {e_st:.2e}, "
                 f"speed-up {row['speedup_matched_rmse']:.2f}")
 
+    # standalone decoder sampling (cvae_sample) of each trained model, BF16
+    # and FP8: conditions resident in HBM, timed launch after a warm-up.
+    # VALU work per sample is the kernel's own active-lane count
+    # (SQ_THREAD_CYCLES_VALU per row, committed sampling profile); HBM bytes
+    # are the conditions read and the samples written
+    sample = None
+    if not args.no_sample:
+        sample = {}
+        n_s = args.sample_rows
+        for m in range(3):
+            sh = M.STANDARD_SHAPES[m]
+            cond = torch.randn((n_s, sh["p_in"]), dtype=torch.float32, device="cuda",
+                               generator=torch.Generator(device="cuda").manual_seed(m))
+            out_s = torch.empty((n_s, sh["p_out"]), dtype=torch.float32, device="cuda")
+            for prec, pname in ((1, "bf16"), (2, "fp8")):
+                pk = packs[prec][m]
+                M.cvae_sample(pk, cond, n_s, 11, 0, out_s)
+                _, t_s = timed(lambda: M.cvae_sample(pk, cond, n_s, 12, 0, out_s))
+                rate = n_s / t_s
+                slots = SAMPLE_VALU_SLOTS[(m, prec)]
+                nbytes = 4 * (sh["p_in"] + sh["p_out"])
+                row = dict(rows=n_s, seconds=t_s, samples_per_s=rate, valu_slots_per_sample=slots,
+                           valu_frac=rate * slots / PEAK_VALU_LANEOPS, hbm_bytes_per_sample=nbytes,
+                           hbm_frac=rate * nbytes / PEAK_HBM_BYTES)
+                sample[f"model{m}_{pname}"] = row
+                log(f"cvae_sample model {m} {pname.upper()}: {n_s} rows in {t_s * 1e3:.2f} ms, {rate:.3e} samples/s, "
+                    f"VALU {row['valu_frac']:.2f} of peak, HBM {row['hbm_frac']:.2f}")
+            del cond, out_s
+
     # training-data walk at its full size (2^24 photons, parameters drawn per
     # photon as in training), both representative-event weightings; outputs
     # and workspace allocated before the timed launch, counters reset inside
@@ -720,6 +755,7 @@ def main():
         "c5": c5,
         "table1": table1,
         "table1_sweep": sweep,
+        "cvae_sample": sample,
         "walk_full": None if walk_full is None else dict(
             walk_full, workload=f"training walks, {args.walk_full_photons} photons, sigma_t r log-uniform [0.1, 200], "
                                 "g U[-0.9, 0.95], albedo U[0.9, 1]"),
