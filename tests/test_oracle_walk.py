@@ -243,3 +243,84 @@ def test_focus_weighted_training_parameters(oracle):
     st1, g1, _ = full["params"]
     assert stats.kstest(np.log(st1 / 10.0) / np.log(2.0), "uniform").pvalue > 1e-4
     assert stats.kstest((g1 - 0.7) / 0.2, "uniform").pvalue > 1e-4
+
+
+
+def _lambert_entry(rng, x, n_in, oracle):
+    """Direction cosine-weighted about the inward normal n_in."""
+    b1, b2 = oracle.onb(n_in)
+    u1, u2 = rng.random(), rng.random()
+    a = 2.0 * np.pi * u2
+    return np.sqrt(u1) * n_in + np.sqrt(1.0 - u1) * (np.cos(a) * b1 + np.sin(a) * b2)
+
+
+def _mean_path(oracle, scene, entry, sigma_t, g, n, seed):
+    """Mean path length inside and mean collision count of walks entering
+    through `entry(rng) -> (x, d)`; the exits come from the oracle's exact
+    ray intervals of the scene (entry points lie on its binary32 surface),
+    the scattering from its HG inversion and direction update."""
+    rng = np.random.default_rng(seed)
+    lengths, colls = np.empty(n), np.empty(n)
+    for i in range(n):
+        x, d = entry(rng)
+        total, k = 0.0, 0
+        for _ in range(100000):
+            t_exit = None
+            for t0, t1 in scene.intervals(x, d):
+                if t0 <= 1e-7 < t1:
+                    t_exit = t1
+            assert t_exit is not None
+            fl = -np.log(1.0 - rng.random()) / sigma_t
+            if fl >= t_exit:
+                total += t_exit
+                break
+            total += fl
+            x = x + fl * d
+            k += 1
+            d = oracle.scatter_dir(d, oracle.hg_sample(g, rng.random()), 2.0 * np.pi * rng.random())
+        lengths[i], colls[i] = total, k
+    return lengths, colls
+
+
+@pytest.mark.parametrize("body,sigma_t,g", [("sphere", 0.5, 0.0), ("sphere", 3.0, 0.8), ("box", 3.0, -0.5),
+                                            ("box", 1.0, 0.6)])
+def test_mean_path_length_is_four_volume_over_surface(oracle, body, sigma_t, g):
+    """Invariance of the mean path length (Blanco and Fournier, Europhys.
+    Lett. 61, 2003): light entering a non-absorbing convex body uniformly
+    over its surface, cosine-weighted about the inward normal, travels 4V/S
+    inside on average whatever sigma_t and g are (4R/3 for a sphere of radius
+    R, 4 abc / (ab + bc + ca) for a box of half-extents a, b, c), and makes
+    sigma_t times that many collisions.  The exits are the oracle's exact ray
+    intervals, so a wrong root or slab there, or a flight rate other than
+    sigma_t, moves the mean."""
+    if body == "sphere":
+        rad, c = float(np.float32(0.7)), np.array([0.1, -0.2, 0.3], np.float32).astype(np.float64)
+        scene = oracle.Scene(np.array([[0, *c, rad, 0, 0, 0]], np.float32))
+        expect = 4.0 * rad / 3.0
+
+        def entry(rng):
+            z = 2.0 * rng.random() - 1.0
+            ph = 2.0 * np.pi * rng.random()
+            nrm = np.array([np.sqrt(1 - z * z) * np.cos(ph), np.sqrt(1 - z * z) * np.sin(ph), z])
+            return c + rad * nrm, _lambert_entry(rng, c + rad * nrm, -nrm, oracle)
+    else:
+        h = np.array([0.8, 0.4, 0.3], np.float32).astype(np.float64)
+        scene = oracle.Scene(np.array([[1, 0.2, -0.1, 0.3, *h, 0]], np.float32))
+        c = np.array([0.2, -0.1, 0.3], np.float32).astype(np.float64)
+        area = np.array([h[1] * h[2], h[0] * h[2], h[0] * h[1]])
+        expect = 4.0 * h.prod() / (h[0] * h[1] + h[1] * h[2] + h[2] * h[0])
+
+        def entry(rng):
+            ax = rng.choice(3, p=area / area.sum())
+            side = 1.0 if rng.random() < 0.5 else -1.0
+            x = c + h * (2.0 * rng.random(3) - 1.0)
+            x[ax] = c[ax] + side * h[ax]
+            n_in = np.zeros(3)
+            n_in[ax] = -side
+            return x, _lambert_entry(rng, x, n_in, oracle)
+    n = 8000
+    lengths, colls = _mean_path(oracle, scene, entry, sigma_t, g, n, seed=11)
+    se_l = lengths.std() / np.sqrt(n)
+    se_k = colls.std() / np.sqrt(n)
+    assert abs(lengths.mean() - expect) < 4.5 * se_l, (lengths.mean(), expect, se_l)
+    assert abs(colls.mean() - sigma_t * expect) < 4.5 * se_k, (colls.mean(), sigma_t * expect, se_k)
