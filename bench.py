@@ -118,10 +118,30 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
     if timing is not None:
         c = walk["counters"].cpu().numpy()
         timing["walk"] = dict(photons=n_samples, events=int(c[0]), seconds=e0.elapsed_time(e1) / 1e3)
+    # the three models train at once, one stream each: a step is latency
+    # bound (about one wave per CU), so their launches overlap on the GPU
+    setups = [prepare_model(M, torch, walk, model, model if shapes is None else shapes[model], batch, seed)
+              for model in range(3)]
+    streams = [torch.cuda.Stream() for _ in setups]
+    cur = torch.cuda.current_stream()
+    for st in streams:
+        st.wait_stream(cur)
+    t_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_ev[0].record()
+    for step in range(1, steps + 1):
+        for su, st in zip(setups, streams):
+            train_step_model(M, su, step, steps, kl_warmup, stream=st)
+    for st in streams:
+        cur.wait_stream(st)
+    t_ev[1].record()
+    torch.cuda.synchronize()
+    if timing is not None:
+        us = t_ev[0].elapsed_time(t_ev[1]) * 1e3 / steps
+        timing["train_step_us_three_models"] = us
+        timing["train_samples_per_s_per_model"] = batch / (us * 1e-6)
     packs, losses = {p: [] for p in precisions}, []
-    for model in range(3):
-        shape = model if shapes is None else shapes[model]
-        pk, loss = train_one(M, torch, walk, model, shape, steps, batch, seed, kl_warmup, precisions, timing)
+    for su in setups:
+        pk, loss = finish_model(M, torch, su, precisions)
         for p in precisions:
             packs[p].append(pk[p])
         losses.append(loss)
@@ -129,9 +149,9 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
     return packs, losses, time.time() - t0
 
 
-def train_one(M, torch, walk, model, shape, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), timing=None):
-    """Trains one CVAE on the walk records and packs it; returns ({precision:
-    packed}, loss record)."""
+def prepare_model(M, torch, walk, model, shape, batch=4096, seed=0):
+    """Features, FP64 standardisation, initial weights and AdamW state of one
+    CVAE on the walk records."""
     n_samples = walk["n_scatter"].numel()
     p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
     # PathGen learns N >= 2 records and EventGen k >= 2 records: the
@@ -146,30 +166,45 @@ def train_one(M, torch, walk, model, shape, steps, batch=4096, seed=0, kl_warmup
     n = M.cvae_param_count(shape)
     master = torch.empty(n, dtype=torch.float32, device="cuda")
     M.cvae_init(shape, seed + 10 + model, master)
-    m, v = torch.zeros_like(master), torch.zeros_like(master)
-    ws = torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda")
-    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
-    first = None
-    t_model = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_model[0].record()
-    for step in range(1, steps + 1):
-        lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
-        beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
-        M.cvae_train_step(shape, master, m, v, M.adam_params(step, lr=lr), cond, target, n_rows, batch, 1,
-                          seed + 20 + model, step, 0, ws, loss, kl_weight=beta)
-        if step == 1:
-            first = loss.cpu().numpy().copy()
-    t_model[1].record()
-    last = loss.cpu().numpy().copy()
-    if timing is not None:
-        timing.setdefault("train_step_us", []).append(t_model[0].elapsed_time(t_model[1]) * 1e3 / steps)
+    return dict(model=model, shape=shape, n_rows=n_rows, cond=cond, target=target, stats=stats, master=master,
+                m=torch.zeros_like(master), v=torch.zeros_like(master), batch=batch, seed=seed,
+                ws=torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda"),
+                loss=torch.zeros(3, dtype=torch.float64, device="cuda"), first=None)
+
+
+def train_step_model(M, su, step, steps, kl_warmup=0.6, stream=None):
+    """One AdamW step (step = 1 .. steps) with the learning-rate schedule and
+    the KL warm-up; keeps the first step's loss."""
+    lr = 2e-3 if step < 0.5 * steps else (6e-4 if step < 0.8 * steps else 2e-4)
+    beta = min(1.0, step / (kl_warmup * steps)) if kl_warmup > 0 else 1.0
+    M.cvae_train_step(su["shape"], su["master"], su["m"], su["v"], M.adam_params(step, lr=lr), su["cond"],
+                      su["target"], su["n_rows"], su["batch"], 1, su["seed"] + 20 + su["model"], step, 0, su["ws"],
+                      su["loss"], stream=stream, kl_weight=beta)
+    if step == 1:
+        import torch
+        with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+            su["first"] = su["loss"].clone()
+
+
+def finish_model(M, torch, su, precisions=(1,)):
+    """Packs the trained model; returns ({precision: packed}, loss record)."""
+    first, last = su["first"].cpu().numpy(), su["loss"].cpu().numpy().copy()
     packed = {}
     for p in precisions:
         pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-        M.cvae_pack(shape, master, stats, p, pk)
+        M.cvae_pack(su["shape"], su["master"], su["stats"], p, pk)
         packed[p] = pk
-    log(f"model {model}: {n_rows} rows, loss (total, KL, NLL) {first} -> {last}")
-    return packed, dict(rows=int(n_rows), first=first.tolist(), last=last.tolist())
+    log(f"model {su['model']}: {su['n_rows']} rows, loss (total, KL, NLL) {first} -> {last}")
+    return packed, dict(rows=int(su["n_rows"]), first=first.tolist(), last=last.tolist())
+
+
+def train_one(M, torch, walk, model, shape, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,)):
+    """Trains one CVAE on the walk records and packs it; returns ({precision:
+    packed}, loss record)."""
+    su = prepare_model(M, torch, walk, model, shape, batch, seed)
+    for step in range(1, steps + 1):
+        train_step_model(M, su, step, steps, kl_warmup)
+    return finish_model(M, torch, su, precisions)
 
 
 def table1_sweep(M, torch, W, n_samples, steps, n_eval=10000, seed=0):
@@ -745,8 +780,8 @@ def main():
         "speedup_matched_rmse": tot_pt / tot_st,
         "per_sigma": details,
         "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps,
-                  "step_us_per_model": tim.get("train_step_us"),
-                  "samples_per_s_per_model": [4096 / (us * 1e-6) for us in tim.get("train_step_us", [])]},
+                  "step_us_three_models_concurrent": tim.get("train_step_us_three_models"),
+                  "samples_per_s_per_model": tim.get("train_samples_per_s_per_model")},
         "walk": dict(tim["walk"], events_per_s=tim["walk"]["events"] / tim["walk"]["seconds"],
                      roofline_frac=tim["walk"]["events"] * OPS_PER_WALK_EVENT / tim["walk"]["seconds"] / PEAK_VALU_LANEOPS,
                      workload="training walks (sigma_t r log-uniform [0.1, 200], g U[-0.9, 0.95], albedo U[0.9, 1])"),
