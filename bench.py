@@ -30,7 +30,7 @@ OPS_PER_PATH = 400.0         # camera ray, primary intervals, banking the result
 OPS_PER_EVENT = 470.0        # one plain collision: Philox block, flight, NEE shadow ray, roulette, HG, new ray
 OPS_PER_STEP = 5300.0        # one learned step, two representative events (three decoders, 22+ normals, NEE x2)
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
-OPS_PER_WALK_EVENT = 205.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
+OPS_PER_WALK_EVENT = 186.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
 PEAK_MFMA_BF16 = 2.5e15
 PEAK_HBM_BYTES = 8.0e12
