@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-mesh", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--no-confirm", action="store_true", help="skip the plain tracer's run at the matched spp")
     ap.add_argument("--no-walk-full", action="store_true")
     ap.add_argument("--no-sample", action="store_true")
     ap.add_argument("--sample-rows", type=int, default=1 << 24)
@@ -327,7 +328,7 @@ def c5_section(M, W, torch, packs, args, timed):
     grid = M.build_sdf_grid(prims, res)
     cam, light, med = W.camera_c5(width, width), W.light_c5(), W.medium_c5()
     rend = M.Renderer(prims, cam, light, grid=grid)
-    img, t_ref = timed(lambda: rend.render(med, method=1, spp=args.c5_ref_spp, seed=77))
+    img, t_ref = timed(lambda: rend.render(med, method=1, spp=args.c5_ref_spp, seed=77), warm=False)
     ref, ref_var = image_moments(img, args.c5_ref_spp)
     ref_noise2 = float(ref_var.mean()) / args.c5_ref_spp
     out = {"workload": f"64 spheres (seed 0) over a {res}^3 FP16 distance grid, {width}x{width}, {spp} spp, "
@@ -413,7 +414,11 @@ def main():
     kw = dict(blocks_per_cu=args.blocks_per_cu, cvae_batch_min=args.batch_min, chunk=args.chunk,
               restart_min=args.restart_min)
 
-    def timed(fn):
+    def timed(fn, warm=True):
+        # one untimed call first (buffers, caches), then the timed one: every
+        # tracer is timed warm
+        if warm:
+            fn()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         out = fn()
@@ -497,7 +502,18 @@ def main():
         s_star = pt[s]["var"] / r_st**2
         t_pt_match = s_star * npix / (pt[s]["paths"] / pt[s]["time"])
         mean_st = float(image_moments(img, spp)[0].mean())
+        # confirmation: the plain tracer actually run at ceil(S*) spp (its own
+        # seed), its RMSE and time beside the sphere tracer's
+        s_conf = max(1, int(np.ceil(s_star)))
+        confirm = None
+        if not args.no_confirm:
+            med_s = W.medium_c4(s)
+            img_c, t_c = timed(lambda: rend.render(med_s, method=1, spp=s_conf, seed=2501, **kw))
+            mc, _ = image_moments(img_c, s_conf)
+            r_conf = float(np.sqrt(max(float(((mc.float() - ref[s]) ** 2).mean()) - ref_noise2[s], 1e-30)))
+            confirm = dict(spp=s_conf, rmse=r_conf, ms=t_c * 1e3, speedup=t_c / t_sigma[s])
         details[str(s)] = dict(
+            pt_confirm=confirm,
             rmse_st=r_st, rmse_pt_same_spp=r_pt, ref_noise_rms=float(np.sqrt(ref_noise2[s])),
             mean_st=mean_st, mean_ref=float(ref[s].double().mean()),
             st_paths_per_s=float(c[0] / t_sigma[s]), st_steps_per_path=float(c[2] / c[0]),
@@ -506,7 +522,9 @@ def main():
             speedup_matched_rmse=t_pt_match / t_sigma[s])
         log(f"ST sigma_t={s}: {t_sigma[s] * 1e3:.1f} ms, rmse {r_st:.3e} (PT@{spp} {r_pt:.3e}), "
             f"mean {mean_st:.4e} vs ref {details[str(s)]['mean_ref']:.4e}, matched PT spp {s_star:.1f}, "
-            f"speed-up {t_pt_match / t_sigma[s]:.2f}")
+            f"speed-up {t_pt_match / t_sigma[s]:.2f}"
+            + ("" if confirm is None else f"; plain run at {s_conf} spp: rmse {confirm['rmse']:.3e}, "
+               f"{confirm['ms']:.1f} ms ({confirm['speedup']:.2f})"))
         tot_st += t_sigma[s]
         tot_pt += t_pt_match
     pt_rate = sum(pt[s]["paths"] for s in sigmas) / sum(pt[s]["time"] for s in sigmas)
@@ -526,7 +544,6 @@ def main():
         table1 = {"shapes": W.TABLE1_SHAPES, "train_seconds": t1,
                   "loss_last": [l["last"] for l in losses1]}
         for s in sigmas:
-            st_render(s, 6000, packed=pk1[1])
             img, t = timed(lambda: st_render(s, 6001, packed=pk1[1]))
             r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
             s_star = pt[s]["var"] / r_st**2
@@ -655,7 +672,6 @@ def main():
             out_s = torch.empty((n_s, sh["p_out"]), dtype=torch.float32, device="cuda")
             for prec, pname in ((1, "bf16"), (2, "fp8")):
                 pk = packs[prec][m]
-                M.cvae_sample(pk, cond, n_s, 11, 0, out_s)
                 _, t_s = timed(lambda: M.cvae_sample(pk, cond, n_s, 12, 0, out_s))
                 rate = n_s / t_s
                 slots = SAMPLE_VALU_SLOTS[(m, prec)]
@@ -681,7 +697,7 @@ def main():
             wws = torch.empty(M.ms_random_walk_workspace_size(desc), dtype=torch.uint8, device="cuda")
             M.ms_random_walk(desc, wout, wws)  # warm-up
             wout["counters"].zero_()
-            _, t_w = timed(lambda: M.ms_random_walk(desc, wout, wws))
+            _, t_w = timed(lambda: M.ms_random_walk(desc, wout, wws), warm=False)
             cw = wout["counters"].cpu().numpy()
             walk_full[name] = dict(photons=n_w, events=int(cw[0]), seconds=t_w, events_per_s=cw[0] / t_w,
                                    max_chain=int(cw[3]),
