@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--ref-spp", type=int, default=4096)
     ap.add_argument("--width", type=int, default=512)
     ap.add_argument("--spp", type=int, default=256)
-    ap.add_argument("--tau-min", type=float, default=6.0)
+    ap.add_argument("--tau-min", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
