@@ -250,6 +250,20 @@ struct Geo {
             if (i < P.n) s = __builtin_fminf(s, prim_depth(P.p[i], p));
         return union_radius(s);
     }
+    // An upper bound of radius() over the whole scene: union_radius of the
+    // deepest point of the deepest primitive (a sphere's centre at depth r, a
+    // box's at its smallest half size), in the same rounding; unbounded with
+    // a grid.
+    __device__ __forceinline__ float max_radius() const {
+        if (GRID) return INFINITY;
+        float m = 0.0f;
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+            if (i < P.n)
+                m = __builtin_fmaxf(m, P.p[i][0] == 0.0f ? P.p[i][4]
+                                                         : __builtin_fminf(P.p[i][4], __builtin_fminf(P.p[i][5], P.p[i][6])));
+        return union_radius(-m);
+    }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
     __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const { return nee(A, P, x, d); }
 };
@@ -320,6 +334,7 @@ struct GeoMany {
         return union_radius(sd);
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
+    __device__ __forceinline__ float max_radius() const { return INFINITY; }
     // Shadow ray: one pass over the primitives collects the hit intervals
     // clipped to [0, dist] (8 slots), a sorting network orders them by entry
     // and a sweep adds the length of their union; more than 8 hits falls back
@@ -424,6 +439,7 @@ struct GeoMesh {
     }
     __device__ __forceinline__ bool piece(V3, V3, float t, float& s, float& e) const { return union_piece(iv, t, s, e); }
     __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const { return grid_radius(A, p); }
+    __device__ __forceinline__ float max_radius() const { return INFINITY; }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
     __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
         V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
@@ -600,6 +616,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }
     typename GeoSel<NP, GRID>::type G;
     G.init(A, lds_prims);
+    // no sphere in the scene reaches tau_min: every collision is a plain one,
+    // and the radius query is skipped (same paths, same draws)
+    const bool can_step = MODE != kModePlain &&
+                          A.sigma_t * __builtin_fminf(G.max_radius(), A.st_max * A.inv_sigma_t) >= A.tau_min;
 
     TicketPool pool;
     pool.reset();
@@ -723,7 +743,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         truncated = true;
                     } else {
                         bool plain = true;
-                        if (MODE != kModePlain) {
+                        if (MODE != kModePlain && can_step) {
                             const float r = __builtin_fminf(G.radius(A, p), A.st_max * A.inv_sigma_t);
                             if (A.sigma_t * r >= A.tau_min) {
                                 plain = false;
