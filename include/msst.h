@@ -316,13 +316,13 @@ typedef struct {
     const void* packed[3];   /* LengthGen, PathGen, EventGen (ST with CVAE) */
     float tau_min, st_max;
     int32_t spp;
-    int32_t chunk;           /* samples per work unit; 0 = default */
+    int32_t chunk;           /* samples per work unit; 0 = max(2, ceil(pixels spp / 2^24)) */
     uint64_t seed, sample_offset;
     uint32_t max_events;     /* per path; 0 = 2^20 */
-    int32_t blocks_per_cu;   /* launch shape; 0 = default */
-    int32_t cvae_batch_min;  /* waiting lanes that trigger a decoder pass; 0 = default */
-    int32_t restart_min;     /* lanes waiting for a new path that trigger a restart pass, 1..64; 0 = default */
-    int32_t max_wait;        /* loop iterations after which waiting lanes force a pass anyway; 0 = default */
+    int32_t blocks_per_cu;   /* 256-thread blocks per CU, 1..64; 0 = 4 */
+    int32_t cvae_batch_min;  /* waiting lanes that trigger a decoder pass, 1..64; 0 = 20 */
+    int32_t restart_min;     /* lanes waiting for a new path that trigger a restart pass, 1..64; 0 = 16 */
+    int32_t max_wait;        /* loop iterations after which waiting lanes force a pass anyway; 0 = 10 */
     int32_t nee_samples;     /* representative events per learned step, 1..16 (0 = 1) */
     int32_t flags;           /* MS_RENDER_NEE_BEFORE_ABSORPTION */
 } ms_render_desc;
