@@ -230,6 +230,7 @@ __device__ __forceinline__ float nee(const RenderArgs& A, const Prims<NP>& P, V3
 // are computed once per ray and kept in registers.
 template <int NP, bool GRID>
 struct Geo {
+    static constexpr bool kWaveLight = false;  // shadow rays tested per lane (few primitives)
     Prims<NP> P;
     RayIv<NP> iv;
     __device__ __forceinline__ void init(const RenderArgs& A, const float*) {
@@ -277,6 +278,8 @@ constexpr int kHitSlots = 8;
 
 template <bool GRID>
 struct GeoMany {
+    // shadow rays of a wave share a primitive mask (light_mask below)
+    static constexpr bool kWaveLight = true;
     const float* prim;  // LDS [n][8]
     int n;
     __device__ __forceinline__ void init(const RenderArgs& A, const float* lds_prims) {
@@ -335,11 +338,58 @@ struct GeoMany {
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
     __device__ __forceinline__ float max_radius() const { return INFINITY; }
-    // Shadow ray: one pass over the primitives collects the hit intervals
-    // clipped to [0, dist] (8 slots), a sorting network orders them by entry
-    // and a sweep adds the length of their union; more than 8 hits falls back
-    // to piece-by-piece queries.
-    __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
+    // Primitives the shadow segments of this wave can meet.  Called by every
+    // lane of the wave (converged); lanes with `active` will trace a segment
+    // from x to the light.  All segments lie in the union of balls around the
+    // axis from the centre C of the origins' bounding box to the light with
+    // radius rho (the box's half diagonal), so a primitive whose bounding
+    // sphere stays farther than rho from that axis segment meets none of them
+    // and is left out of the wave's mask (bit i of word i / 64); the mask
+    // only drops primitives that cannot contribute, so the result is the
+    // one of testing them all.
+    __device__ __forceinline__ void light_mask(const RenderArgs& A, bool active, V3 x, uint64_t* mask) const {
+        float lo0 = active ? x.x : INFINITY, lo1 = active ? x.y : INFINITY, lo2 = active ? x.z : INFINITY;
+        float hi0 = active ? x.x : -INFINITY, hi1 = active ? x.y : -INFINITY, hi2 = active ? x.z : -INFINITY;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            lo0 = __builtin_fminf(lo0, __shfl_xor(lo0, off));
+            lo1 = __builtin_fminf(lo1, __shfl_xor(lo1, off));
+            lo2 = __builtin_fminf(lo2, __shfl_xor(lo2, off));
+            hi0 = __builtin_fmaxf(hi0, __shfl_xor(hi0, off));
+            hi1 = __builtin_fmaxf(hi1, __shfl_xor(hi1, off));
+            hi2 = __builtin_fmaxf(hi2, __shfl_xor(hi2, off));
+        }
+        const V3 c = v3(0.5f * (lo0 + hi0), 0.5f * (lo1 + hi1), 0.5f * (lo2 + hi2));
+        const V3 half = v3(0.5f * (hi0 - lo0), 0.5f * (hi1 - lo1), 0.5f * (hi2 - lo2));
+        const float rho = __builtin_sqrtf(dot(half, half));
+        const V3 u = v3(A.light[0] - c.x, A.light[1] - c.y, A.light[2] - c.z);
+        const float uu = dot(u, u);
+        const float inv_uu = uu > 0.0f ? 1.0f / uu : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kMaxManyPrims / 64; ++k) {
+            const int i = 64 * k + lane_id();
+            bool keep = false;
+            if (i < n) {
+                const float* pr = prim + 8 * i;
+                const V3 q = v3(pr[1] - c.x, pr[2] - c.y, pr[3] - c.z);
+                const float tt = __builtin_fminf(1.0f, __builtin_fmaxf(0.0f, dot(q, u) * inv_uu));
+                const V3 off = q - tt * u;
+                const float br = pr[0] == 0.0f ? pr[4] : __builtin_sqrtf(pr[4] * pr[4] + pr[5] * pr[5] + pr[6] * pr[6]);
+                // widened by a relative 1e-4 against rounding
+                const float reach = (rho + br) * 1.0001f + 1e-4f * (__builtin_fabsf(tt) + 1.0f) * __builtin_sqrtf(uu);
+                keep = dot(off, off) <= reach * reach;
+            }
+            mask[k] = ballot(keep && active_any(lo0));
+        }
+    }
+    __device__ __forceinline__ static bool active_any(float lo0) { return lo0 != INFINITY; }
+
+    // Shadow ray: the primitives (all of them, or those of a wave mask)
+    // contribute their hit intervals clipped to [0, dist] (8 slots), a
+    // sorting network orders them by entry and a sweep adds the length of
+    // their union; more than 8 hits falls back to piece-by-piece queries.
+    __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const { return light_masked(A, x, d, nullptr); }
+    __device__ __forceinline__ float light_masked(const RenderArgs& A, V3 x, V3 d, const uint64_t* mask) const {
         V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
         const float dist2 = dot(wl, wl);
         const float inv_dist = fast_rsq(dist2);
@@ -352,7 +402,7 @@ struct GeoMany {
             cb[j] = INFINITY;
         }
         int m = 0;
-        for (int i = 0; i < n; ++i) {
+        auto visit = [&](int i) {
             float a, b;
             if (prim_interval(prim + 8 * i, x, wl, a, b) && b > 0.0f && a < dist) {
                 a = __builtin_fmaxf(a, 0.0f);
@@ -365,6 +415,12 @@ struct GeoMany {
                     }
                 ++m;
             }
+        };
+        if (mask == nullptr) {
+            for (int i = 0; i < n; ++i) visit(i);
+        } else {
+            for (int k = 0; k < kMaxManyPrims / 64; ++k)
+                for (uint64_t bits = mask[k]; bits != 0; bits &= bits - 1) visit(64 * k + __builtin_ctzll(bits));
         }
         float acc = 0.0f;
         if (m <= kHitSlots) {
@@ -414,6 +470,7 @@ struct GeoMany {
 // intervals are kept in registers.  Radii come from the distance grid;
 // shadow rays traverse their own segment to the light.
 struct GeoMesh {
+    static constexpr bool kWaveLight = false;  // shadow rays traverse the BVH per lane
     const BvhNode* nodes;
     const float* tris;
     int n_nodes;
@@ -615,6 +672,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
         __syncthreads();
     }
     typename GeoSel<NP, GRID>::type G;
+    constexpr bool kWaveLight = GeoSel<NP, GRID>::type::kWaveLight;
     G.init(A, lds_prims);
     // no sphere in the scene reaches tau_min: every collision is a plain one,
     // and the radius query is skipped (same paths, same draws)
@@ -721,6 +779,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 
         // ---- VALU phase
         bool path_end = false, truncated = false;
+        // many primitives: a plain event's shadow ray is traced after the
+        // branch, where the whole wave builds its primitive mask
+        bool nee_now = false;
+        V3 nee_x = v3(0, 0, 0), nee_d = v3(0, 0, 1);
         if (state == S_FLY) {
             // one Philox block per flight; the boundary query (the medium
             // piece of the ray containing or following t) is skipped when the
@@ -794,7 +856,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         }
                         if (plain) {
                             ++p_ev;
-                            Lp += A.albedo * G.light(A, p, d);
+                            if constexpr (kWaveLight) {
+                                nee_now = true;
+                                nee_x = p;
+                                nee_d = d;
+                            } else {
+                                Lp += A.albedo * G.light(A, p, d);
+                            }
                             if (u24(w.w) > A.surv_thr) {
                                 path_end = true;
                             } else {
@@ -808,6 +876,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                     }
                 }
             }
+        }
+
+        if constexpr (kWaveLight) {
+            uint64_t mk[kMaxManyPrims / 64];
+            G.light_mask(A, nee_now, nee_x, mk);
+            if (nee_now) Lp += A.albedo * G.light_masked(A, nee_x, nee_d, mk);
         }
 
         // ---- MFMA phase: learned sphere steps for the waiting lanes
@@ -913,13 +987,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                             W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
                         }
                     }
+                    V3 Xw = v3(0, 0, 0), Ww = v3(0, 0, 1);
                     if (lit) {
                         // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
                         const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
                         const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
-                        const V3 Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
-                        const V3 Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
-                        Lp += w_nee * G.light(A, Xw, Ww);
+                        Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
+                        Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
+                        if constexpr (!kWaveLight) Lp += w_nee * G.light(A, Xw, Ww);
+                    }
+                    if constexpr (kWaveLight) {
+                        uint64_t mk[kMaxManyPrims / 64];
+                        G.light_mask(A, lit, Xw, mk);
+                        if (lit) Lp += w_nee * G.light_masked(A, Xw, Ww, mk);
                     }
                 }
                 if (alive) {
