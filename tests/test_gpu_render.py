@@ -412,6 +412,32 @@ def test_c5_learned_path_by_path(msst, oracle, precision):
     assert frac < 0.05
 
 
+@pytest.mark.parametrize("n,res", [(5, 0), (65, 0), (200, 64), (256, 0)])
+@pytest.mark.parametrize("method,sampler", [(PLAIN, CVAE), (ST, EXACT)])
+def test_many_primitives_path_by_path(msst, oracle, n, res, method, sampler):
+    """Scenes held in LDS with a shadow-ray mask per wave: the fewest such
+    primitives (5), a ragged count just past one 64-bit mask word (65),
+    several words with a distance grid (200), and the maximum (256)."""
+    announce(f"render {n} spheres grid={res} method={method} sampler={sampler}")
+    prims = W.scene_c5(seed=n, n=n)
+    cam, light, med = f32_camera(W.camera_c5(48, 48)), f32_light(W.light_c5()), f32_medium(W.medium_c5())
+    grid_g = msst.build_sdf_grid(prims, res) if res else None
+    scene_o = oracle.Scene(prims, sdf_fp16=oracle.Scene(prims).build_grid(res)) if res else oracle.Scene(prims)
+    r = msst.Renderer(prims, cam, light, grid=grid_g)
+    out = r.render(med, method=method, sampler=sampler, spp=1, seed=23, tau_min=4.0)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    o = oracle.render(scene_o, cam, light, med,
+                      method=oracle.METHOD_PLAIN_NEE if method == PLAIN else oracle.METHOD_ST,
+                      sampler=oracle.SAMPLER_EXACT_WALK, spp=1, seed=23, tau_min=4.0)
+    frac, _ = compare_paths(g, o)
+    print(f"diverged {frac:.2e}; lit {(o['sum'] > 0).mean():.2f}, events {o['events'].sum()}, steps {o['steps'].sum()}")
+    assert (o["sum"] > 0).mean() > 0.05
+    assert frac < 1e-2
+    if method == ST:
+        assert o["steps"].sum() > 20
+
+
 def test_rgb_media_channel_by_channel(msst, oracle):
     """RGB media: each channel traced with its own sigma_t and albedo and the
     Philox key seed + c, path by path against the oracle with the same keys."""
