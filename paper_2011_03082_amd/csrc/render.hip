@@ -660,24 +660,13 @@ __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L,
     wave_sync();
 }
 
-// Four waves per SIMD: measured faster than the unconstrained allocation
-// (three waves) despite a few spilled registers.
+// The persistent render loop of one kernel instance (MODE fixes the
+// method); the whole body of render_kernel below.
 template <int MODE, int NP, bool GRID>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
-    __shared__ RenderLds lds_all[kRenderWaves];
-    __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
-    RenderLds& L = lds_all[threadIdx.x >> 6];
-    if (NP == 0) {
-        for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
-        __syncthreads();
-    }
+__device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, const float* lds_prims) {
     typename GeoSel<NP, GRID>::type G;
     constexpr bool kWaveLight = GeoSel<NP, GRID>::type::kWaveLight;
     G.init(A, lds_prims);
-    // no sphere in the scene reaches tau_min: every collision is a plain one,
-    // and the radius query is skipped (same paths, same draws)
-    const bool can_step = MODE != kModePlain &&
-                          A.sigma_t * __builtin_fminf(G.max_radius(), A.st_max * A.inv_sigma_t) >= A.tau_min;
 
     TicketPool pool;
     pool.reset();
@@ -805,7 +794,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
                         truncated = true;
                     } else {
                         bool plain = true;
-                        if (MODE != kModePlain && can_step) {
+                        if (MODE != kModePlain) {
                             const float r = __builtin_fminf(G.radius(A, p), A.st_max * A.inv_sigma_t);
                             if (A.sigma_t * r >= A.tau_min) {
                                 plain = false;
@@ -1032,6 +1021,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
             atomicAdd(A.counters + 3, (unsigned long long)a3);
         }
     }
+}
+
+// Four waves per SIMD: measured faster than the unconstrained allocation
+// (three waves) despite a few spilled registers.
+template <int MODE, int NP, bool GRID>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
+    __shared__ RenderLds lds_all[kRenderWaves];
+    __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
+    RenderLds& L = lds_all[threadIdx.x >> 6];
+    if (NP == 0) {
+        for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
+        __syncthreads();
+    }
+    if (MODE != kModePlain) {
+        // No point of the scene reaches tau_min (the deepest point of the
+        // deepest primitive, or the step cap, is too shallow): every collision
+        // is a plain one, so the plain loop runs -- the same paths and draws,
+        // without the learned step's checks and register pressure.
+        typename GeoSel<NP, GRID>::type G;
+        G.init(A, lds_prims);
+        if (!(A.sigma_t * __builtin_fminf(G.max_radius(), A.st_max * A.inv_sigma_t) >= A.tau_min)) {
+            render_loop<kModePlain, NP, GRID>(A, L, lds_prims);
+            return;
+        }
+    }
+    render_loop<MODE, NP, GRID>(A, L, lds_prims);
 }
 
 // Per-pixel fixed-order reduction of the unit partials, added to the image

@@ -182,11 +182,17 @@ def test_dense_nearly_white_medium_learned_path_by_path(msst, oracle, sigma_t):
     assert frac < 0.03
 
 
-def test_tau_above_all_radii_is_plain(msst):
-    announce("render ST with tau_min huge")
+@pytest.mark.parametrize("sampler,tau_min", [(EXACT, 1e30), (CVAE, 1e30), (EXACT, 10.0), (CVAE, 10.0)])
+def test_tau_above_all_radii_is_plain(msst, oracle, sampler, tau_min):
+    """No point of the scene reaches tau_min -- a huge threshold, or sigma_t
+    times the deepest point's radius (0.999 at the unit sphere's centre)
+    just below 10 -- so sphere tracing is plain tracing."""
+    announce(f"render ST with tau_min {tau_min} above every radius, sampler={sampler}")
     prims, cam, light, med = c4_inputs(10.0, 32)
-    a = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=3, seed=6)
-    b = gpu_render(msst, prims, cam, light, med, method=ST, sampler=EXACT, tau_min=1e30, spp=3, seed=6)
+    packed = pack_all(msst, models_for_test(oracle)[1]) if sampler == CVAE else (None, None, None)
+    a = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=3, seed=6, nee_samples=2, flags=1)
+    b = gpu_render(msst, prims, cam, light, med, method=ST, sampler=sampler, packed=packed, tau_min=tau_min, spp=3,
+                   seed=6, nee_samples=2, flags=1)
     # separate kernel instantiations may contract floating point differently
     np.testing.assert_allclose(a["sum"], b["sum"], rtol=1e-5, atol=1e-9)
     np.testing.assert_array_equal(a["events"], b["events"])
