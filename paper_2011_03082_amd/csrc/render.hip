@@ -23,9 +23,7 @@
 
 namespace msst {
 
-constexpr int kMaxPrims = 4;
 constexpr int kRenderWaves = 4;
-constexpr float kTwoPiRev = 1.0f;  // angles are passed in revolutions
 
 // Lane states: out of samples (IDLE), tracing (FLY), waiting for a learned
 // step (WAIT), path finished and not yet banked (END), no work left (DONE).
@@ -688,350 +686,358 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
     // step (wave-uniform): a pass also runs once the oldest wait reaches
     // max_wait, so rare steps do not idle lanes for long
     int end_age = 0, wait_age = 0;
-    bool restart_due = true;
 
-    for (;;) {
-        // ---- restart phase, batched: lanes whose path ended bank it, lanes
-        // out of samples take a work unit, then every lane with a sample to
-        // trace starts its camera ray.  It runs once restart_min lanes wait
-        // or nothing else is in flight, so that its code is not issued for a
-        // handful of lanes on most iterations.
-        if (restart_due) {
-            end_age = 0;
-            bool start = false;
-            if (state == S_END) {
-                neumaier_add(acc_sum, acc_comp, Lp);
-                acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
-                acc_ev += p_ev;
-                acc_st += p_st;
-                ++cnt_paths;
-                cnt_events += p_ev;
-                cnt_steps += p_st;
-                cnt_trunc += p_trunc;
-                ++s;
-                if (s >= s_end) {
-                    UnitRecord rec;
-                    rec.sum = acc_sum + acc_comp;
-                    rec.sumsq = acc_sq;
-                    rec.events = acc_ev;
-                    rec.steps = acc_st;
-                    A.part[unit] = rec;
-                    state = S_IDLE;
-                } else {
-                    start = true;
-                }
-            }
-            const bool need = state == S_IDLE;
-            const uint64_t tk = pool.take(need, A.ticket, 64);
-            if (need) {
-                if (tk < (uint64_t)A.n_units) {
-                    unit = (int64_t)tk;
-                    // pixel-major: a wave's block of tickets covers few pixels
-                    const int pixel = (int)(unit / A.n_chunks);
-                    const int ch = (int)(unit - (int64_t)pixel * A.n_chunks);
-                    py = pixel / A.width;
-                    px = pixel - py * A.width;
-                    s = ch * A.chunk;
-                    s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
-                    acc_sum = acc_comp = acc_sq = 0.0f;
-                    acc_ev = acc_st = 0;
-                    start = true;
-                } else {
-                    state = S_DONE;
-                }
-            }
-            if (start) {
-                const uint64_t sample = A.sample_offset + (uint64_t)s;
-                const uint64_t id = (uint64_t)(uint32_t)(py * A.width + px) | (sample << 32);
-                const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
-                const uint4 jw = rp.block(0);
-                rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
-                const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
-                const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
-                o = v3(A.eye[0], A.eye[1], A.eye[2]);
-                d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0],
-                                 A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
-                                 A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
-                G.set_camera_ray(o, d);
-                t = 0.0f;
-                Lp = 0.0f;
-                c0 = 0;
-                iters = 0;
-                p_ev = 0;
-                p_st = 0;
-                state = S_FLY;
+    // ---- restart phase, batched: lanes whose path ended bank it, lanes out
+    // of samples take a work unit, then every lane with a sample to trace
+    // starts its camera ray.  It runs once restart_min lanes wait, or nothing
+    // else is in flight, or the oldest wait reaches max_wait, so that its
+    // code is not issued for a handful of lanes on most iterations.
+    auto restart_now = [&]() __attribute__((always_inline)) -> bool {
+        const uint64_t rmask = ballot(state == S_END || state == S_IDLE);
+        const uint64_t amask = ballot(state == S_FLY || state == S_WAIT);
+        end_age = rmask != 0 ? end_age + 1 : 0;
+        return rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0 || end_age > A.max_wait);
+    };
+    auto restart = [&]() __attribute__((always_inline)) {
+        end_age = 0;
+        bool start = false;
+        if (state == S_END) {
+            neumaier_add(acc_sum, acc_comp, Lp);
+            acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
+            acc_ev += p_ev;
+            acc_st += p_st;
+            ++cnt_paths;
+            cnt_events += p_ev;
+            cnt_steps += p_st;
+            cnt_trunc += p_trunc;
+            ++s;
+            if (s >= s_end) {
+                UnitRecord rec;
+                rec.sum = acc_sum + acc_comp;
+                rec.sumsq = acc_sq;
+                rec.events = acc_ev;
+                rec.steps = acc_st;
+                A.part[unit] = rec;
+                state = S_IDLE;
+            } else {
+                start = true;
             }
         }
-        if (ballot(state != S_DONE) == 0) break;
+        const bool need = state == S_IDLE;
+        const uint64_t tk = pool.take(need, A.ticket, 64);
+        if (need) {
+            if (tk < (uint64_t)A.n_units) {
+                unit = (int64_t)tk;
+                // pixel-major: a wave's block of tickets covers few pixels
+                const int pixel = (int)(unit / A.n_chunks);
+                const int ch = (int)(unit - (int64_t)pixel * A.n_chunks);
+                py = pixel / A.width;
+                px = pixel - py * A.width;
+                s = ch * A.chunk;
+                s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
+                acc_sum = acc_comp = acc_sq = 0.0f;
+                acc_ev = acc_st = 0;
+                start = true;
+            } else {
+                state = S_DONE;
+            }
+        }
+        if (start) {
+            const uint64_t sample = A.sample_offset + (uint64_t)s;
+            const uint64_t id = (uint64_t)(uint32_t)(py * A.width + px) | (sample << 32);
+            const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
+            const uint4 jw = rp.block(0);
+            rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
+            const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
+            const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
+            o = v3(A.eye[0], A.eye[1], A.eye[2]);
+            d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0],
+                             A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
+                             A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
+            G.set_camera_ray(o, d);
+            t = 0.0f;
+            Lp = 0.0f;
+            c0 = 0;
+            iters = 0;
+            p_ev = 0;
+            p_st = 0;
+            state = S_FLY;
+        }
+    };
 
-        // ---- plain collisions until a learned-step pass or a restart is due,
-        // in a loop of their own so that neither phase's working set weighs on
-        // it (the order of the phases changes no path: each draws from its own
-        // stream, and decoder rows are independent)
-        bool pass_due = false;
-        uint64_t wmask = 0;
-        for (;;) {
-            // ---- VALU phase
-            bool path_end = false, truncated = false;
-            // many primitives: a plain event's shadow ray is traced after the
-            // branch, where the whole wave builds its primitive mask
-            bool nee_now = false;
-            V3 nee_x = v3(0, 0, 0), nee_d = v3(0, 0, 1);
-            if (state == S_FLY) {
-                // one Philox block per flight; the boundary query (the medium
-                // piece of the ray containing or following t) is skipped when the
-                // flight is shorter than the conservative radius at its start
-                const uint4 w = rng.block(c0++);
-                const float l = -flight_ln(u01(w.x)) * A.inv_sigma_t;
-                float ps = t, pe = INFINITY;
-                bool inside = l < G.flight_bound(A, fma3(t, d, o));
-                if (!inside && !G.piece(o, d, t, ps, pe)) {
-                    path_end = true;
+    // ---- VALU phase: one flight, and at a collision a plain event or the
+    // start of a learned step, for every lane in flight
+    auto collide = [&](bool& path_end, bool& truncated) __attribute__((always_inline)) {
+        // many primitives: a plain event's shadow ray is traced after the
+        // branch, where the whole wave builds its primitive mask
+        bool nee_now = false;
+        V3 nee_x = v3(0, 0, 0), nee_d = v3(0, 0, 1);
+        if (state == S_FLY) {
+            // one Philox block per flight; the boundary query (the medium
+            // piece of the ray containing or following t) is skipped when the
+            // flight is shorter than the conservative radius at its start
+            const uint4 w = rng.block(c0++);
+            const float l = -flight_ln(u01(w.x)) * A.inv_sigma_t;
+            float ps = t, pe = INFINITY;
+            bool inside = l < G.flight_bound(A, fma3(t, d, o));
+            if (!inside && !G.piece(o, d, t, ps, pe)) {
+                path_end = true;
+            } else {
+                t = __builtin_fmaxf(t, ps);
+                if (t + l >= pe) {
+                    t = pe;
                 } else {
-                    t = __builtin_fmaxf(t, ps);
-                    if (t + l >= pe) {
-                        t = pe;
+                    t += l;
+                    const V3 p = fma3(t, d, o);
+                    if (++iters > A.max_events) {
+                        path_end = true;
+                        truncated = true;
                     } else {
-                        t += l;
-                        const V3 p = fma3(t, d, o);
-                        if (++iters > A.max_events) {
-                            path_end = true;
-                            truncated = true;
-                        } else {
-                            bool plain = true;
-                            if (MODE != kModePlain) {
-                                const float r = __builtin_fminf(G.radius(A, p), A.st_max * A.inv_sigma_t);
-                                if (A.sigma_t * r >= A.tau_min) {
-                                    plain = false;
-                                    if (MODE == kModeStExact) {
-                                        // the actual walk inside the sphere (reference sampler)
-                                        V3 x = p, dir = d, Xk = p, Wk = d;
-                                        float resv = 0.0f;
-                                        const float r2 = r * r;
-                                        const float inv_phi = 1.0f / A.albedo;
-                                        uint32_t nev = 0;
-                                        for (;;) {
-                                            if (++nev > A.max_events) break;  // bounded even for degenerate input
-                                            const uint4 ww = rng.block(c0++);
-                                            resv = nev == 1 ? 1.0f : __builtin_fmaf(resv, inv_phi, 1.0f);
-                                            if (u01(ww.w) * resv <= 1.0f) {
-                                                Xk = x;
-                                                Wk = dir;
-                                            }
-                                            const HgSample h = hg_sample(A.g, u01(ww.y));
-                                            dir = scatter(dir, h.mu, h.sin_t, u01(ww.z));
-                                            const float ll = -flight_ln(u01(ww.x)) * A.inv_sigma_t;
-                                            const V3 rel = x - p;
-                                            const V3 qn = fma3(ll, dir, rel);
-                                            if (!(dot(qn, qn) < r2)) {
-                                                x = fma3(sphere_exit(rel, dir, r2), dir, x);
-                                                break;
-                                            }
-                                            x = fma3(ll, dir, x);
+                        bool plain = true;
+                        if (MODE != kModePlain) {
+                            const float r = __builtin_fminf(G.radius(A, p), A.st_max * A.inv_sigma_t);
+                            if (A.sigma_t * r >= A.tau_min) {
+                                plain = false;
+                                if (MODE == kModeStExact) {
+                                    // the actual walk inside the sphere (reference sampler)
+                                    V3 x = p, dir = d, Xk = p, Wk = d;
+                                    float resv = 0.0f;
+                                    const float r2 = r * r;
+                                    const float inv_phi = 1.0f / A.albedo;
+                                    uint32_t nev = 0;
+                                    for (;;) {
+                                        if (++nev > A.max_events) break;  // bounded even for degenerate input
+                                        const uint4 ww = rng.block(c0++);
+                                        resv = nev == 1 ? 1.0f : __builtin_fmaf(resv, inv_phi, 1.0f);
+                                        if (u01(ww.w) * resv <= 1.0f) {
+                                            Xk = x;
+                                            Wk = dir;
                                         }
-                                        ++p_st;
-                                        const uint4 wa = rng.block(c0++);
-                                        const float N = (float)nev;
-                                        if (!(u01(wa.x) <= fast_exp(N * A.ln_albedo))) {
-                                            path_end = true;
-                                        } else {
-                                            Lp += lambda_weight(A, N) * G.light(A, Xk, Wk);
-                                            o = x;
-                                            d = dir;
-                                            G.set_ray(o, d);
-                                            t = 0.0f;
+                                        const HgSample h = hg_sample(A.g, u01(ww.y));
+                                        dir = scatter(dir, h.mu, h.sin_t, u01(ww.z));
+                                        const float ll = -flight_ln(u01(ww.x)) * A.inv_sigma_t;
+                                        const V3 rel = x - p;
+                                        const V3 qn = fma3(ll, dir, rel);
+                                        if (!(dot(qn, qn) < r2)) {
+                                            x = fma3(sphere_exit(rel, dir, r2), dir, x);
+                                            break;
                                         }
-                                    } else {
-                                        o = p;
-                                        r_step = r;
-                                        state = S_WAIT;
+                                        x = fma3(ll, dir, x);
                                     }
+                                    ++p_st;
+                                    const uint4 wa = rng.block(c0++);
+                                    const float N = (float)nev;
+                                    if (!(u01(wa.x) <= fast_exp(N * A.ln_albedo))) {
+                                        path_end = true;
+                                    } else {
+                                        Lp += lambda_weight(A, N) * G.light(A, Xk, Wk);
+                                        o = x;
+                                        d = dir;
+                                        G.set_ray(o, d);
+                                        t = 0.0f;
+                                    }
+                                } else {
+                                    o = p;
+                                    r_step = r;
+                                    state = S_WAIT;
                                 }
                             }
-                            if (plain) {
-                                ++p_ev;
-                                if constexpr (kWaveLight) {
-                                    nee_now = true;
-                                    nee_x = p;
-                                    nee_d = d;
-                                } else {
-                                    Lp += A.albedo * G.light(A, p, d);
-                                }
-                                if (u24(w.w) > A.surv_thr) {
-                                    path_end = true;
-                                } else {
-                                    const HgSample h = hg_sample(A.g, u01(w.y));
-                                    d = scatter(d, h.mu, h.sin_t, u01(w.z));
-                                    o = p;
-                                    G.set_ray(o, d);
-                                    t = 0.0f;
-                                }
+                        }
+                        if (plain) {
+                            ++p_ev;
+                            if constexpr (kWaveLight) {
+                                nee_now = true;
+                                nee_x = p;
+                                nee_d = d;
+                            } else {
+                                Lp += A.albedo * G.light(A, p, d);
+                            }
+                            if (u24(w.w) > A.surv_thr) {
+                                path_end = true;
+                            } else {
+                                const HgSample h = hg_sample(A.g, u01(w.y));
+                                d = scatter(d, h.mu, h.sin_t, u01(w.z));
+                                o = p;
+                                G.set_ray(o, d);
+                                t = 0.0f;
                             }
                         }
                     }
                 }
             }
+        }
 
+        if constexpr (kWaveLight) {
+            uint64_t mk[kMaxManyPrims / 64];
+            G.light_mask(A, nee_now, nee_x, mk);
+            if (nee_now) Lp += A.albedo * G.light_masked(A, nee_x, nee_d, mk);
+        }
+    };
+
+    // ---- MFMA phase: learned sphere steps for the waiting lanes (wmask)
+    auto learned_pass = [&](uint64_t wmask, bool& path_end) __attribute__((always_inline)) {
+        wait_age = 0;
+        const int n_wait = __popcll(wmask);
+        const bool mine = state == S_WAIT;
+        float y[6];
+        float N = 1.0f, psi = 0.0f;
+        const float lst = fast_ln(A.sigma_t * r_step);
+        // LengthGen (sigma_t r, g) -> N
+        const int slot0 = rank_in(wmask);
+        if (mine) {
+            const float c2[2] = {lst, A.g};
+            stage_row<1, 2>(A.pm[0], L, slot0, rng, c0, c2);
+        }
+        stage_normals<1>(A, A.pm[0], L, n_wait);
+        decode_rows<1>(A.pm[0], L, mine, slot0, n_wait, y);
+        bool alive = false;
+        float u_hg = 0.5f, u_first = 1.0f, phiN = 1.0f;
+        if (mine) {
+            ++p_st;
+            N = __builtin_fmaxf(1.0f, floorf(fast_exp(__builtin_fminf(y[0], 20.0f)) + 0.5f));
+            const uint4 wa = rng.block(c0++);
+            psi = u01(wa.y);
+            u_hg = u01(wa.z);
+            u_first = u01(wa.w);
+            // absorption along the bypassed chain (Sec. 3.2)
+            phiN = fast_exp(N * A.ln_albedo);
+            alive = u01(wa.x) <= phiN;
+            if (!alive) path_end = true;
+        }
+        // N = 1: a single HG scatter at the centre, sampled exactly;
+        // N >= 2: PathGen, then each representative event is the centre
+        // with probability albedo / Lambda^(N), else EventGen.  With
+        // NEE before absorption the direct light of the step is
+        // estimated for every step (weight Lambda) and the absorption
+        // only ends the path; otherwise only surviving steps add it
+        // (weight Lambda / albedo^N, the order of Sec. 3.2).
+        const bool before = (A.flags & MS_RENDER_NEE_BEFORE_ABSORPTION) != 0;
+        const bool lit = before ? mine : alive;
+        const bool use_path = lit && N >= 2.0f;
+        // Lambda and Lambda / albedo^N each in a form that stays finite
+        // for any N (their product form overflows once albedo^-N does)
+        const float lam = lambda_total(A, N);
+        const float w_nee = (before ? lam : lambda_weight(A, N)) / (float)A.nee_samples;
+        float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
+        if (lit && !use_path) ct = hg_sample(A.g, u_hg).mu;
+        const uint64_t pmask = ballot(use_path);
+        const float lnN = fast_ln(N);
+        if (pmask) {
+            const int slot = rank_in(pmask);
+            // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
+            if (use_path) {
+                const float c3[3] = {lst, A.g, lnN};
+                stage_row<3, 3>(A.pm[1], L, slot, rng, c0, c3);
+            }
+            stage_normals<3>(A, A.pm[1], L, __popcll(pmask));
+            decode_rows<3>(A.pm[1], L, use_path, slot, __popcll(pmask), y);
+            if (use_path) {
+                ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
+                al = y[1];
+                be = y[2];
+                ga = fast_sqrt(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
+                const float inl = fast_rsq(al * al + be * be + ga * ga);
+                al *= inl;
+                be *= inl;
+                ga *= inl;
+            }
+        }
+        V3 e1 = v3(1, 0, 0), e2 = v3(0, 1, 0);
+        float cp = 1.0f, sp = 0.0f;
+        if (lit) {
+            onb(d, e1, e2);
+            cp = cos_rev(psi);
+            sp = sin_rev(psi);
+        }
+        for (int k = 0; k < A.nee_samples; ++k) {
+            float uf = u_first;
+            if (k > 0 && lit) uf = u01(rng.block(c0++).x);
+            const bool use_event = use_path && !(uf * lam <= A.albedo);
+            V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
+            const uint64_t emask = ballot(use_event);
+            if (emask) {
+                const int slot = rank_in(emask);
+                // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
+                if (use_event) {
+                    const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
+                    stage_row<6, 7>(A.pm[2], L, slot, rng, c0, c7);
+                }
+                stage_normals<6>(A, A.pm[2], L, __popcll(emask));
+                decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
+                if (use_event) {
+                    X = v3(y[0], y[1], y[2]);
+                    W = v3(y[3], y[4], y[5]);
+                    const float xl2 = dot(X, X);
+                    if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
+                    const float wl2 = dot(W, W);
+                    W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
+                }
+            }
+            V3 Xw = v3(0, 0, 0), Ww = v3(0, 0, 1);
+            if (lit) {
+                // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
+                const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
+                const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
+                Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
+                Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
+                if constexpr (!kWaveLight) Lp += w_nee * G.light(A, Xw, Ww);
+            }
             if constexpr (kWaveLight) {
                 uint64_t mk[kMaxManyPrims / 64];
-                G.light_mask(A, nee_now, nee_x, mk);
-                if (nee_now) Lp += A.albedo * G.light_masked(A, nee_x, nee_d, mk);
+                G.light_mask(A, lit, Xw, mk);
+                if (lit) Lp += w_nee * G.light_masked(A, Xw, Ww, mk);
             }
+        }
+        if (alive) {
+            // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
+            const float st = fast_sqrt(__builtin_fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+            const V3 xt = v3(st * cp, st * sp, ct);
+            const V3 w0 = v3(be * ct + ga * st, al, -be * st + ga * ct);
+            const V3 wt = v3(cp * w0.x - sp * w0.y, sp * w0.x + cp * w0.y, w0.z);
+            o = o + r_step * (xt.x * e1 + xt.y * e2 + xt.z * d);
+            d = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
+            G.set_ray(o, d);
+            t = 0.0f;
+            state = S_FLY;
+        }
+    };
+
+    if constexpr (MODE == kModeStCvae) {
+        // both checks after every collision: measured faster here than the
+        // inner loop below
+        for (;;) {
+            if (restart_now()) restart();
+            if (ballot(state != S_DONE) == 0) break;
+            bool path_end = false, truncated = false;
+            collide(path_end, truncated);
+            const uint64_t wmask = ballot(state == S_WAIT);
+            const uint64_t lmask = ballot(state == S_FLY || state == S_WAIT);
+            const int n_wait = __popcll(wmask);
+            wait_age = n_wait > 0 ? wait_age + 1 : 0;
+            if (n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask || wait_age > A.max_wait))
+                learned_pass(wmask, path_end);
             if (path_end) {
                 p_trunc = truncated;
                 state = S_END;
             }
-            if (MODE == kModeStCvae) {
-                wmask = ballot(state == S_WAIT);
-                const uint64_t lmask = ballot(state == S_FLY || state == S_WAIT);
-                const int n_wait = __popcll(wmask);
-                wait_age = n_wait > 0 ? wait_age + 1 : 0;
-                pass_due = n_wait > 0 && (n_wait >= A.batch_min || wmask == lmask || wait_age > A.max_wait);
-            }
-            // the restart phase is batched: it runs once restart_min lanes wait,
-            // or nothing else is in flight, or the oldest wait reaches max_wait
-            const uint64_t rmask = ballot(state == S_END || state == S_IDLE);
-            const uint64_t amask = ballot(state == S_FLY || state == S_WAIT);
-            end_age = rmask != 0 ? end_age + 1 : 0;
-            restart_due = rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0 || end_age > A.max_wait);
-            if (pass_due || restart_due) break;
         }
-
-        // ---- MFMA phase: learned sphere steps for the waiting lanes
-        if (MODE == kModeStCvae && pass_due) {
-            wait_age = 0;
-            bool path_end = false;
-            const int n_wait = __popcll(wmask);
-            const bool mine = state == S_WAIT;
-            float y[6];
-            float N = 1.0f, psi = 0.0f;
-            const float lst = fast_ln(A.sigma_t * r_step);
-            // LengthGen (sigma_t r, g) -> N
-            const int slot0 = rank_in(wmask);
-            if (mine) {
-                const float c2[2] = {lst, A.g};
-                stage_row<1, 2>(A.pm[0], L, slot0, rng, c0, c2);
-            }
-            stage_normals<1>(A, A.pm[0], L, n_wait);
-            decode_rows<1>(A.pm[0], L, mine, slot0, n_wait, y);
-            bool alive = false;
-            float u_hg = 0.5f, u_first = 1.0f, phiN = 1.0f;
-            if (mine) {
-                ++p_st;
-                N = __builtin_fmaxf(1.0f, floorf(fast_exp(__builtin_fminf(y[0], 20.0f)) + 0.5f));
-                const uint4 wa = rng.block(c0++);
-                psi = u01(wa.y);
-                u_hg = u01(wa.z);
-                u_first = u01(wa.w);
-                // absorption along the bypassed chain (Sec. 3.2)
-                phiN = fast_exp(N * A.ln_albedo);
-                alive = u01(wa.x) <= phiN;
-                if (!alive) path_end = true;
-            }
-            // N = 1: a single HG scatter at the centre, sampled exactly;
-            // N >= 2: PathGen, then each representative event is the centre
-            // with probability albedo / Lambda^(N), else EventGen.  With
-            // NEE before absorption the direct light of the step is
-            // estimated for every step (weight Lambda) and the absorption
-            // only ends the path; otherwise only surviving steps add it
-            // (weight Lambda / albedo^N, the order of Sec. 3.2).
-            const bool before = (A.flags & MS_RENDER_NEE_BEFORE_ABSORPTION) != 0;
-            const bool lit = before ? mine : alive;
-            const bool use_path = lit && N >= 2.0f;
-            // Lambda and Lambda / albedo^N each in a form that stays finite
-            // for any N (their product form overflows once albedo^-N does)
-            const float lam = lambda_total(A, N);
-            const float w_nee = (before ? lam : lambda_weight(A, N)) / (float)A.nee_samples;
-            float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
-            if (lit && !use_path) ct = hg_sample(A.g, u_hg).mu;
-            const uint64_t pmask = ballot(use_path);
-            const float lnN = fast_ln(N);
-            if (pmask) {
-                const int slot = rank_in(pmask);
-                // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
-                if (use_path) {
-                    const float c3[3] = {lst, A.g, lnN};
-                    stage_row<3, 3>(A.pm[1], L, slot, rng, c0, c3);
+    } else {
+        // plain collisions in a loop of their own until a restart is due, so
+        // that the restart phase's working set does not weigh on them (the
+        // order of the phases changes no path: each draws from its own stream)
+        bool restart_due = true;
+        for (;;) {
+            if (restart_due) restart();
+            if (ballot(state != S_DONE) == 0) break;
+            do {
+                bool path_end = false, truncated = false;
+                collide(path_end, truncated);
+                if (path_end) {
+                    p_trunc = truncated;
+                    state = S_END;
                 }
-                stage_normals<3>(A, A.pm[1], L, __popcll(pmask));
-                decode_rows<3>(A.pm[1], L, use_path, slot, __popcll(pmask), y);
-                if (use_path) {
-                    ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
-                    al = y[1];
-                    be = y[2];
-                    ga = fast_sqrt(__builtin_fmaxf(0.0f, 1.0f - al * al - be * be));
-                    const float inl = fast_rsq(al * al + be * be + ga * ga);
-                    al *= inl;
-                    be *= inl;
-                    ga *= inl;
-                }
-            }
-            V3 e1 = v3(1, 0, 0), e2 = v3(0, 1, 0);
-            float cp = 1.0f, sp = 0.0f;
-            if (lit) {
-                onb(d, e1, e2);
-                cp = cos_rev(psi);
-                sp = sin_rev(psi);
-            }
-            for (int k = 0; k < A.nee_samples; ++k) {
-                float uf = u_first;
-                if (k > 0 && lit) uf = u01(rng.block(c0++).x);
-                const bool use_event = use_path && !(uf * lam <= A.albedo);
-                V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
-                const uint64_t emask = ballot(use_event);
-                if (emask) {
-                    const int slot = rank_in(emask);
-                    // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
-                    if (use_event) {
-                        const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-                        stage_row<6, 7>(A.pm[2], L, slot, rng, c0, c7);
-                    }
-                    stage_normals<6>(A, A.pm[2], L, __popcll(emask));
-                    decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
-                    if (use_event) {
-                        X = v3(y[0], y[1], y[2]);
-                        W = v3(y[3], y[4], y[5]);
-                        const float xl2 = dot(X, X);
-                        if (xl2 > 1.0f) X = fast_rsq(xl2) * X;
-                        const float wl2 = dot(W, W);
-                        W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
-                    }
-                }
-                V3 Xw = v3(0, 0, 0), Ww = v3(0, 0, 1);
-                if (lit) {
-                    // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
-                    const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
-                    const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
-                    Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
-                    Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
-                    if constexpr (!kWaveLight) Lp += w_nee * G.light(A, Xw, Ww);
-                }
-                if constexpr (kWaveLight) {
-                    uint64_t mk[kMaxManyPrims / 64];
-                    G.light_mask(A, lit, Xw, mk);
-                    if (lit) Lp += w_nee * G.light_masked(A, Xw, Ww, mk);
-                }
-            }
-            if (alive) {
-                // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
-                const float st = fast_sqrt(__builtin_fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
-                const V3 xt = v3(st * cp, st * sp, ct);
-                const V3 w0 = v3(be * ct + ga * st, al, -be * st + ga * ct);
-                const V3 wt = v3(cp * w0.x - sp * w0.y, sp * w0.x + cp * w0.y, w0.z);
-                o = o + r_step * (xt.x * e1 + xt.y * e2 + xt.z * d);
-                d = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
-                G.set_ray(o, d);
-                t = 0.0f;
-                state = S_FLY;
-            }
-            if (path_end) {
-                p_trunc = false;
-                state = S_END;
-            }
-            // lanes ended by the pass count for the restart condition
-            const uint64_t rmask = ballot(state == S_END || state == S_IDLE);
-            const uint64_t amask = ballot(state == S_FLY || state == S_WAIT);
-            restart_due = rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0 || end_age > A.max_wait);
+                restart_due = restart_now();
+            } while (!restart_due);
         }
     }
     if (A.counters) {
