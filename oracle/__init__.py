@@ -24,6 +24,8 @@ PREC_FP64, PREC_BF16, PREC_FP8 = 0, 1, 2
 METHOD_PLAIN_NEE, METHOD_ST = 1, 2
 SAMPLER_CVAE, SAMPLER_EXACT_WALK = 0, 1
 NEE_BEFORE_ABSORPTION = 1  # render flag: CVAE steps add direct light before the absorption test
+STEP_PAPER = 2  # render flag: the learned step as printed (PathGen and EventGen for every case)
+MAX_NEE = 16
 LAYER_FLOATS = 16 * 16 + 16
 
 
@@ -81,6 +83,12 @@ class _RenderDesc(C.Structure):
                 ("n_threads", C.c_int32), ("nee_samples", C.c_int32), ("flags", C.c_int32)]
 
 
+class _StepResult(C.Structure):
+    _fields_ = [("x", C.c_double * 3), ("w", C.c_double * 3), ("X", (C.c_double * 3) * MAX_NEE),
+                ("W", (C.c_double * 3) * MAX_NEE), ("first", C.c_int * MAX_NEE), ("n_rep", C.c_int),
+                ("nee_w", C.c_double), ("N", C.c_double), ("survived", C.c_int), ("psi", C.c_double)]
+
+
 class _ImageOut(C.Structure):
     _fields_ = [("sum", C.c_void_p), ("sumsq", C.c_void_p), ("events", C.c_void_p),
                 ("steps", C.c_void_p)]
@@ -128,6 +136,9 @@ def lib():
         L.or_build_sdf_grid.argtypes = [C.POINTER(_Scene), i32, vp, vp, vp]
         L.or_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Light),
                                 C.POINTER(_Medium), C.POINTER(_RenderDesc), C.POINTER(_ImageOut)]
+        L.or_sphere_step.argtypes = [C.POINTER(_RenderDesc), C.POINTER(_Medium), u64, u32, vp, vp, dbl,
+                                     C.POINTER(_StepResult)]
+        L.or_sphere_step.restype = u32
         _LIB = L
     return _LIB
 
@@ -347,6 +358,25 @@ def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLE
                   camera["height"])
     lt = _Light((C.c_double * 3)(*light["pos"]), light["intensity"])
     md = _Medium(medium["sigma_t"], medium["g"], medium["albedo"])
+    rd, keep = _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_samples, flags)
+    rd.spp, rd.sample_offset, rd.max_events = spp, sample_offset, max_events
+    npx = camera["width"] * camera["height"]
+    if pixels is not None:
+        px = np.ascontiguousarray(pixels, dtype=np.int32)
+        keep.append(px)
+        rd.pixels = px.ctypes.data
+        rd.n_pixels = px.size
+        npx = px.size
+    rd.n_threads = n_threads if n_threads else default_threads()
+    res = {k: np.zeros(npx) for k in ("sum", "sumsq", "events", "steps")}
+    img = _ImageOut(*[_p(res[k]) for k in ("sum", "sumsq", "events", "steps")])
+    lib().or_render(C.byref(scene.c), C.byref(cam), C.byref(lt), C.byref(md), C.byref(rd),
+                    C.byref(img))
+    return res
+
+
+def _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_samples, flags):
+    """Render descriptor and the arrays it points into (keep them alive)."""
     keep = []
     rd = _RenderDesc()
     rd.method, rd.sampler, rd.precision = method, sampler, precision
@@ -365,19 +395,28 @@ def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLE
                 rd.act_scales[i] = a.ctypes.data
         else:
             rd.shapes[i] = _shape(list(SHAPES.values())[i])
-    rd.tau_min, rd.st_max, rd.spp = tau_min, st_max, spp
-    rd.seed, rd.sample_offset, rd.max_events = seed, sample_offset, max_events
-    npx = camera["width"] * camera["height"]
-    if pixels is not None:
-        px = np.ascontiguousarray(pixels, dtype=np.int32)
-        keep.append(px)
-        rd.pixels = px.ctypes.data
-        rd.n_pixels = px.size
-        npx = px.size
-    rd.n_threads = n_threads if n_threads else default_threads()
+    rd.tau_min, rd.st_max, rd.seed = tau_min, st_max, seed
     rd.nee_samples, rd.flags = nee_samples, flags
-    res = {k: np.zeros(npx) for k in ("sum", "sumsq", "events", "steps")}
-    img = _ImageOut(*[_p(res[k]) for k in ("sum", "sumsq", "events", "steps")])
-    lib().or_render(C.byref(scene.c), C.byref(cam), C.byref(lt), C.byref(md), C.byref(rd),
-                    C.byref(img))
-    return res
+    rd.max_events = 1 << 20
+    return rd, keep
+
+
+def sphere_step(medium, p, d, r, path_id, c0=0, models=None, sampler=SAMPLER_CVAE, precision=PREC_FP64,
+                seed=0, nee_samples=1, flags=0):
+    """One sphere step around p (radius r, entered along unit d) for the path
+    with Philox id path_id, its draw counter at c0: the learned step (models as
+    for render) or the exact in-sphere walk.  Returns the world-frame exit,
+    representative events, weights, N, survival, psi and the counter after
+    the step."""
+    rd, keep = _render_desc(METHOD_ST, sampler, precision, models, 0.0, 200.0, seed, nee_samples, flags)
+    md = _Medium(medium["sigma_t"], medium["g"], medium["albedo"])
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    da = np.ascontiguousarray(d, dtype=np.float64)
+    out = _StepResult()
+    c_end = lib().or_sphere_step(C.byref(rd), C.byref(md), int(path_id), int(c0), _p(pa), _p(da), float(r),
+                                 C.byref(out))
+    k = max(1, nee_samples)
+    return dict(x=np.array(out.x[:]), w=np.array(out.w[:]), X=np.array([out.X[i][:] for i in range(k)]),
+                W=np.array([out.W[i][:] for i in range(k)]), first=np.array(out.first[:k], bool),
+                n_rep=out.n_rep, nee_w=out.nee_w, N=out.N, survived=bool(out.survived), psi=out.psi,
+                c0=int(c_end))

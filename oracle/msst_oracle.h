@@ -187,8 +187,28 @@ typedef struct {
 
 /* CVAE steps estimate their direct light before the absorption test, with
  * weight sum_{i<=N} albedo^i, for every step (default: survivors only, with
- * that sum divided by albedo^N). */
-enum { OR_NEE_BEFORE_ABSORPTION = 1 };
+ * that sum divided by albedo^N).  OR_STEP_PAPER: the learned step as the
+ * paper prints it -- PathGen for every lit step (also N = 1) and EventGen
+ * for every representative event (no exact first event). */
+enum { OR_NEE_BEFORE_ABSORPTION = 1, OR_STEP_PAPER = 2 };
+
+#define OR_MAX_NEE 16
+
+/* Outcome of one sphere step (world frame). */
+typedef struct {
+    double x[3], w[3];        /* exit position and direction */
+    double X[OR_MAX_NEE][3];  /* representative events */
+    double W[OR_MAX_NEE][3];
+    int first[OR_MAX_NEE];    /* 1 where the event is the exact first one */
+    int n_rep;                /* events whose direct light is added */
+    double nee_w;             /* weight of each of them */
+    double N;
+    int survived;
+    double psi;               /* azimuth of the exit about w_in */
+} or_step_result;
+
+uint32_t or_sphere_step(const or_render_desc* rd, const or_medium* md, uint64_t id, uint32_t c0,
+                        const double p[3], const double d[3], double r, or_step_result* out);
 
 typedef struct {
     double* sum;     /* per listed pixel */

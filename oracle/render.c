@@ -360,35 +360,30 @@ static double or_lambda_weight(double phi, double N) {
     return phi * expm1(-N * log(phi)) / (1.0 - phi);
 }
 
-#define OR_MAX_NEE 16
+typedef or_step_result or_step;
 
-typedef struct {
-    double x[3], w[3];               /* exit position and direction (world) */
-    double X[OR_MAX_NEE][3];         /* representative events (world) */
-    double W[OR_MAX_NEE][3];
-    int n_rep;                       /* events whose direct light is added */
-    double nee_w;                    /* weight of each of them */
-    double N;
-    int survived;
-} or_step;
-
-/* Learned step in the sphere of radius r around p entered along d. */
-/* Learned sphere step (Sec. 3.2 with the models of Sec. 4): LengthGen gives
- * N, the chain is absorbed with probability 1 - albedo^N, PathGen gives the
- * exit, and the direct light at K representative events is averaged.  Each
- * representative event is the first one (the centre, entered along w_in) with
- * probability albedo / Lambda^(N) (Sec. 4.3), taken exactly; EventGen samples
- * the others.  A single event (N = 1) is one HG scatter at the centre
- * (Sec. 3.1), sampled exactly instead of asking PathGen for a point mass.
+/* Learned sphere step (Sec. 3.2 with the models of Sec. 4) in the sphere of
+ * radius r around p entered along d: LengthGen gives N, the chain is absorbed
+ * with probability 1 - albedo^N, PathGen gives the exit, and the direct light
+ * at K representative events is averaged.  Each representative event is the
+ * first one (the centre, entered along w_in) with probability
+ * albedo / Lambda^(N) (Sec. 4.3), taken exactly; EventGen samples the others.
+ * A single event (N = 1) is one HG scatter at the centre (Sec. 3.1), sampled
+ * exactly instead of asking PathGen for a point mass.  With OR_STEP_PAPER the
+ * step is the paper's as printed: PathGen for every step that is lit and
+ * EventGen for every representative event, whatever N and k.
  * Random numbers are drawn in a fixed order: LengthGen normals; one block
  * (absorption, psi, HG, first-event test of sample 0); PathGen normals; then
  * per sample k: a block for its first-event test (k > 0) and EventGen
- * normals. */
+ * normals.  The paper's order draws the same blocks and leaves the HG and
+ * first-event uniforms unused. */
 static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t id, uint32_t* c0,
                          const double p[3], const double d[3], double r, or_step* out) {
     double str = md->sigma_t * r, lst = log(str), g = md->g, phi = md->albedo;
     int K = rd->nee_samples > 0 ? rd->nee_samples : 1;
     int before = (rd->flags & OR_NEE_BEFORE_ABSORPTION) != 0;
+    int paper = (rd->flags & OR_STEP_PAPER) != 0;
+    memset(out->first, 0, sizeof out->first);
     double nrm[16], y[8];
     /* LengthGen */
     double c_len[2] = {lst, g};
@@ -410,8 +405,9 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
     out->nee_w = (before ? lam : or_lambda_weight(phi, N)) / K;
     if (!lit) return;
     double psi = 2.0 * OR_PI * u[1];
+    out->psi = psi;
     double ct, al = 0.0, be = 0.0, ga = 1.0;
-    if (N < 2.0) {
+    if (N < 2.0 && !paper) {
         ct = or_hg_sample(g, u[2]);
     } else {
         /* PathGen */
@@ -439,7 +435,9 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
             uf = v[0];
         }
         double X[3] = {0.0, 0.0, 0.0}, W[3] = {0.0, 0.0, 1.0};
-        if (N >= 2.0 && !(uf <= p_first)) {
+        out->first[k] = 1;
+        if (paper || (N >= 2.0 && !(uf <= p_first))) {
+            out->first[k] = 0;
             double c_ev[7] = {lst, g, phi, ct, al, be, log(N)};
             or_draw_normals(rd, id, c0, rd->shapes[2].latent + rd->shapes[2].p_out, nrm);
             or_model_sample(rd, 2, c_ev, nrm, y);
@@ -519,6 +517,17 @@ static void or_exact_step(const or_render_desc* rd, const or_medium* md, uint64_
     out->survived = u[0] <= exp(out->N * log(phi));
     out->n_rep = out->survived;
     out->nee_w = or_lambda_weight(phi, out->N);
+}
+
+/* One sphere step on its own (test entry): the learned step, or the exact
+ * in-sphere walk with sampler OR_SAMPLER_EXACT_WALK, for path id `id` with
+ * its draw counter at c0; returns the counter after the step. */
+uint32_t or_sphere_step(const or_render_desc* rd, const or_medium* md, uint64_t id, uint32_t c0,
+                        const double p[3], const double d[3], double r, or_step_result* out) {
+    memset(out, 0, sizeof *out);
+    if (rd->sampler == OR_SAMPLER_EXACT_WALK) or_exact_step(rd, md, id, &c0, p, d, r, out);
+    else or_cvae_step(rd, md, id, &c0, p, d, r, out);
+    return c0;
 }
 
 /* ---------------- path ---------------- */
