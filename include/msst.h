@@ -223,6 +223,25 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
                           double kl_weight, void* workspace_dev, size_t workspace_bytes,
                           double* loss_dev, float* grad_dev, void* stream);
 
+/* cvae_train_step without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * cvae_train_step; the per-block partials live in a static device array of
+ * the library (about 2.2 MB per device, held until the process ends, sized
+ * for the largest batch (2^20) and network (n_linear 4) accepted; a
+ * larger batch fails with MS_ERR_INVALID_ARGUMENT and a larger network with
+ * MS_ERR_UNSUPPORTED before anything is launched).
+ * Nothing is allocated: the array's device address is looked up once per
+ * device on the first call with that device current.  Calls on one device
+ * share the array, so calls that overlap in time on one device (several
+ * streams, several threads) race; serialise them on one stream. */
+ms_status cvae_train_step_noalloc(const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev,
+                                  float* adam_v_dev, const ms_adam* adam, const float* cond_dev,
+                                  const float* target_dev, int64_t n_rows, int32_t batch,
+                                  int32_t sample_rows, uint64_t seed, int64_t step,
+                                  uint64_t id_offset, double kl_weight, double* loss_dev,
+                                  float* grad_dev, void* stream);
+
 /* Inference copy of one model's decoder: bfloat16 weights, or FP8 E4M3
  * weights with a per-layer scale max|W| / 448 (FP32 accumulation either
  * way), plus the standardisation constants.  The encoder is dropped

@@ -99,6 +99,8 @@ SIGNATURES = {
     "cvae_workspace_size": ([_P(CvaeShape), _i32, _P(_sz)], C.c_int32),
     "cvae_train_step": ([_P(CvaeShape), _vp, _vp, _vp, _P(Adam), _vp, _vp, _i64, _i32, _i32, _u64, _i64,
                          _u64, C.c_double, _vp, _sz, _vp, _vp, _vp], C.c_int32),
+    "cvae_train_step_noalloc": ([_P(CvaeShape), _vp, _vp, _vp, _P(Adam), _vp, _vp, _i64, _i32, _i32, _u64, _i64,
+                                 _u64, C.c_double, _vp, _vp, _vp], C.c_int32),
     "cvae_packed_bytes": ([], C.c_size_t),
     "cvae_pack": ([_P(CvaeShape), _vp, _vp, _i32, _vp, _sz, _vp], C.c_int32),
     "cvae_sample": ([_vp, _vp, _i64, _u64, _u64, _vp, _vp], C.c_int32),

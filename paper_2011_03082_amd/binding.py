@@ -180,6 +180,14 @@ def cvae_train_step(shape, master, adam_m, adam_v, adam, cond, target, n_rows, b
                                 _ptr(loss), _ptr(grad), _stream(stream)))
 
 
+def cvae_train_step_noalloc(shape, master, adam_m, adam_v, adam, cond, target, n_rows, batch, sample_rows, seed,
+                            step, id_offset, loss=None, grad=None, stream=None, kl_weight=1.0):
+    check(lib().cvae_train_step_noalloc(C.byref(cvae_shape(shape)), _ptr(master), _ptr(adam_m), _ptr(adam_v),
+                                        None if adam is None else C.byref(adam), _ptr(cond), _ptr(target), n_rows,
+                                        batch, sample_rows, seed, step, id_offset, kl_weight, _ptr(loss), _ptr(grad),
+                                        _stream(stream)))
+
+
 def cvae_packed_bytes():
     return lib().cvae_packed_bytes()
 

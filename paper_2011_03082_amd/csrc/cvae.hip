@@ -4,6 +4,8 @@
 // for inference, and decoder-only sampling.
 #include <math.h>
 
+#include <mutex>
+
 #include "host.hpp"
 #include "packed.hpp"
 
@@ -13,6 +15,7 @@ constexpr float kLvMin = -12.0f, kLvMax = 8.0f;
 constexpr float kLog2Pi = 1.83787706640934548f;
 constexpr int kTrainWaves = 4;  // waves per training block
 constexpr int kMaxNL = 4;       // linear maps per network: 2 .. 4 (one to three hidden layers)
+constexpr int kMaxDevices = 64; // devices whose noalloc scratch address is kept
 
 struct Shape {
     int model, p_in, p_out, latent, width, n_linear;
@@ -712,11 +715,31 @@ static ms_status check_shape(const ms_cvae_shape* sh, Shape* out) {
     return MS_OK;
 }
 
-static int train_blocks(int batch) {
-    const int tiles = batch / kTile;
-    int waves = tiles < 1024 ? tiles : 1024;
-    return (waves + kTrainWaves - 1) / kTrainWaves;
+constexpr int kMaxTrainBatch = 1 << 20;
+constexpr int kMaxTrainWaveCount = 1024;
+
+constexpr int train_blocks(int batch) {
+    return ((batch / kTile < kMaxTrainWaveCount ? batch / kTile : kMaxTrainWaveCount) + kTrainWaves - 1) /
+           kTrainWaves;
 }
+
+// Scratch of one training step: per-block gradient partials [blocks][params]
+// (FP32), then per-block loss partials [blocks][2] (FP64).  Every block
+// writes all of its partials on every step, so nothing needs clearing.
+constexpr size_t train_partial_bytes(int nb, int n_params) {
+    return ((size_t)nb * n_params * sizeof(float) + 255) / 256 * 256;
+}
+constexpr size_t train_scratch_bytes(int nb, int n_params) {
+    return train_partial_bytes(nb, n_params) + (size_t)nb * 2 * sizeof(double);
+}
+
+// Device-resident scratch of cvae_train_step_noalloc, sized for the largest
+// batch and network the training kernels accept (about 2.2 MB); each device
+// holds its own copy for the life of the process.  Host code must not pass
+// this name to a kernel: it is a host-side stand-in, not a device address.
+// Its per-device address comes from hipGetSymbolAddress (noalloc_scratch).
+constexpr size_t kTrainScratchBytes = train_scratch_bytes(train_blocks(kMaxTrainBatch), 2 * kMaxNL * kLayerFloats);
+static __device__ __align__(256) unsigned char scratch[kTrainScratchBytes];
 
 }  // namespace msst
 
@@ -838,44 +861,75 @@ ms_status cvae_workspace_size(const ms_cvae_shape* shape, int32_t batch, size_t*
     ms_status st = check_shape(shape, &s);
     if (st != MS_OK) return st;
     MS_REQUIRE(bytes != nullptr, "cvae_workspace_size: bytes is NULL");
-    MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= (1 << 20), "cvae_workspace_size: batch must be a positive multiple of 16, <= 2^20");
-    const int nb = train_blocks(batch);
-    const int n_params = 2 * s.n_linear * kLayerFloats;
-    *bytes = align_up((size_t)nb * n_params * sizeof(float), 256) + (size_t)nb * 2 * sizeof(double);
+    MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= kMaxTrainBatch, "cvae_workspace_size: batch must be a positive multiple of 16, <= 2^20");
+    *bytes = train_scratch_bytes(train_blocks(batch), 2 * s.n_linear * kLayerFloats);
     return MS_OK;
 }
 
-ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev, float* adam_v_dev,
-                          const ms_adam* adam, const float* cond_dev, const float* target_dev, int64_t n_rows,
-                          int32_t batch, int32_t sample_rows, uint64_t seed, int64_t step, uint64_t id_offset,
-                          double kl_weight, void* workspace_dev, size_t workspace_bytes, double* loss_dev,
-                          float* grad_dev, void* stream) {
-    using namespace msst;
+}  // extern "C"
+
+namespace msst {
+
+// Address of this device's noalloc scratch, looked up once per device
+// (hipGetSymbolAddress with the device current) and kept for the process.
+static ms_status noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = -1;
+    MS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(MS_ERR_UNSUPPORTED, "device %d is beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(mu);
+    if (ptr[dev] == nullptr) {
+        void* p = nullptr;
+        MS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (p == nullptr) return set_error(MS_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the training scratch");
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return MS_OK;
+}
+
+// Validation and launches of one training step on a scratch buffer of at
+// least train_scratch_bytes(train_blocks(batch), params) bytes: the caller's
+// workspace (ws_dev, ws_bytes), or with `noalloc` this device's scratch
+// array, looked up after the arguments have been validated.
+static ms_status train_step_launch(const char* who, bool noalloc, const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev,
+                                   float* adam_v_dev, const ms_adam* adam, const float* cond_dev,
+                                   const float* target_dev, int64_t n_rows, int32_t batch, int32_t sample_rows,
+                                   uint64_t seed, int64_t step, uint64_t id_offset, double kl_weight, void* ws_dev,
+                                   size_t ws_bytes, double* loss_dev, float* grad_dev, void* stream) {
     Shape s;
     ms_status st = check_shape(shape, &s);
     if (st != MS_OK) return st;
-    MS_REQUIRE(master_dev && cond_dev && target_dev, "cvae_train_step: NULL array");
-    MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= (1 << 20), "cvae_train_step: batch must be a positive multiple of 16, <= 2^20");
-    MS_REQUIRE(n_rows > 0 && n_rows < ((int64_t)1 << 32), "cvae_train_step: n_rows must be in [1, 2^32)");
-    MS_REQUIRE(sample_rows || n_rows >= batch, "cvae_train_step: n_rows < batch without row sampling");
-    MS_REQUIRE(step >= 0 && step < ((int64_t)1 << 30), "cvae_train_step: step must be in [0, 2^30)");
-    MS_REQUIRE(kl_weight >= 0.0 && kl_weight <= 1e6, "cvae_train_step: kl_weight must be in [0, 1e6]");
+    MS_REQUIRE(master_dev && cond_dev && target_dev, "%s: NULL array", who);
+    MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= kMaxTrainBatch, "%s: batch must be a positive multiple of 16, <= 2^20", who);
+    MS_REQUIRE(n_rows > 0 && n_rows < ((int64_t)1 << 32), "%s: n_rows must be in [1, 2^32)", who);
+    MS_REQUIRE(sample_rows || n_rows >= batch, "%s: n_rows < batch without row sampling", who);
+    MS_REQUIRE(step >= 0 && step < ((int64_t)1 << 30), "%s: step must be in [0, 2^30)", who);
+    MS_REQUIRE(kl_weight >= 0.0 && kl_weight <= 1e6, "%s: kl_weight must be in [0, 1e6]", who);
     if (adam) {
-        MS_REQUIRE(adam_m_dev && adam_v_dev, "cvae_train_step: AdamW moments are NULL");
-        MS_REQUIRE(adam->step >= 1, "cvae_train_step: AdamW step must be >= 1");
+        MS_REQUIRE(adam_m_dev && adam_v_dev, "%s: AdamW moments are NULL", who);
+        MS_REQUIRE(adam->step >= 1, "%s: AdamW step must be >= 1", who);
         MS_REQUIRE(adam->lr > 0 && adam->beta1 >= 0 && adam->beta1 < 1 && adam->beta2 >= 0 && adam->beta2 < 1 &&
                        adam->eps > 0 && adam->weight_decay >= 0,
-                   "cvae_train_step: invalid AdamW hyper-parameters");
+                   "%s: invalid AdamW hyper-parameters", who);
     }
-    size_t need = 0;
-    cvae_workspace_size(shape, batch, &need);
-    MS_REQUIRE(workspace_dev != nullptr, "cvae_train_step: workspace is NULL");
-    if (workspace_bytes < need) return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "cvae_train_step: workspace needs %zu bytes", need);
-    int cus;
-    if ((st = device_cu_count(&cus)) != MS_OK) return st;
-
     const int nb = train_blocks(batch);
     const int n_params = 2 * s.n_linear * kLayerFloats;
+    const size_t need = train_scratch_bytes(nb, n_params);
+    if (!noalloc) {
+        MS_REQUIRE(ws_dev != nullptr, "%s: workspace is NULL", who);
+        if (ws_bytes < need) return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "%s: workspace needs %zu bytes", who, need);
+    }
+    int cus;
+    if ((st = device_cu_count(&cus)) != MS_OK) return st;
+    if (noalloc) {
+        if (need > kTrainScratchBytes)
+            return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "%s: needs %zu bytes of scratch, the static maximum is %zu",
+                             who, need, kTrainScratchBytes);
+        if ((st = noalloc_scratch(&ws_dev)) != MS_OK) return st;
+    }
+
     TrainArgs ta{};
     ta.s = s;
     ta.master = master_dev;
@@ -888,9 +942,8 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
     ta.step = step;
     ta.id_offset = id_offset;
     ta.kl_weight = (float)kl_weight;
-    ta.partial = reinterpret_cast<float*>(workspace_dev);
-    ta.loss_partial = reinterpret_cast<double*>(reinterpret_cast<char*>(workspace_dev) +
-                                                align_up((size_t)nb * n_params * sizeof(float), 256));
+    ta.partial = reinterpret_cast<float*>(ws_dev);
+    ta.loss_partial = reinterpret_cast<double*>(reinterpret_cast<char*>(ws_dev) + train_partial_bytes(nb, n_params));
     hipStream_t hs = (hipStream_t)stream;
     switch (s.n_linear) {
         case 2: hipLaunchKernelGGL(cvae_train_kernel<2>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
@@ -925,6 +978,30 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
     MS_LAUNCHED();
     clear_error();
     return MS_OK;
+}
+
+}  // namespace msst
+
+extern "C" {
+
+ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev, float* adam_v_dev,
+                          const ms_adam* adam, const float* cond_dev, const float* target_dev, int64_t n_rows,
+                          int32_t batch, int32_t sample_rows, uint64_t seed, int64_t step, uint64_t id_offset,
+                          double kl_weight, void* workspace_dev, size_t workspace_bytes, double* loss_dev,
+                          float* grad_dev, void* stream) {
+    return msst::train_step_launch("cvae_train_step", false, shape, master_dev, adam_m_dev, adam_v_dev, adam, cond_dev,
+                                   target_dev, n_rows, batch, sample_rows, seed, step, id_offset, kl_weight,
+                                   workspace_dev, workspace_bytes, loss_dev, grad_dev, stream);
+}
+
+ms_status cvae_train_step_noalloc(const ms_cvae_shape* shape, float* master_dev, float* adam_m_dev,
+                                  float* adam_v_dev, const ms_adam* adam, const float* cond_dev,
+                                  const float* target_dev, int64_t n_rows, int32_t batch, int32_t sample_rows,
+                                  uint64_t seed, int64_t step, uint64_t id_offset, double kl_weight,
+                                  double* loss_dev, float* grad_dev, void* stream) {
+    return msst::train_step_launch("cvae_train_step_noalloc", true, shape, master_dev, adam_m_dev, adam_v_dev, adam,
+                                   cond_dev, target_dev, n_rows, batch, sample_rows, seed, step, id_offset, kl_weight,
+                                   nullptr, 0, loss_dev, grad_dev, stream);
 }
 
 size_t cvae_packed_bytes(void) { return sizeof(msst::PackedModel); }

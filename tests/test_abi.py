@@ -90,3 +90,22 @@ def test_training_walk_workspace_holds_the_photon_order(M):
     ws = C.c_void_p(0x1000)  # never dereferenced: the size check fails first
     assert M.lib().ms_random_walk(C.byref(d), C.byref(o), ws, 256, None) == M._abi.MS_ERR_WORKSPACE_TOO_SMALL
     assert "workspace" in M.lib().ms_last_error().decode()
+
+
+def test_train_step_noalloc_rejects_beyond_its_maximum(M):
+    """The no-allocation training step validates on the host: a batch above
+    2^20 (its static scratch maximum) or a shape beyond the largest network
+    fails before any device work."""
+    shape = M.cvae_shape(0)
+    adam = M.adam_params(1)
+    p = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    for batch in ((1 << 20) + 16, 0, 24):
+        st = M.lib().cvae_train_step_noalloc(C.byref(shape), p, p, p, C.byref(adam), p, p, 1 << 21, batch, 1, 0,
+                                             1, 0, 1.0, None, None, None)
+        assert st == M._abi.MS_ERR_INVALID_ARGUMENT
+        assert b"batch" in M.lib().ms_last_error()
+    big = M._abi.CvaeShape(0, 2, 1, 4, 16, 5)
+    st = M.lib().cvae_train_step_noalloc(C.byref(big), p, p, p, C.byref(adam), p, p, 4096, 4096, 1, 0, 1, 0, 1.0,
+                                         None, None, None)
+    assert st == M._abi.MS_ERR_UNSUPPORTED
+
