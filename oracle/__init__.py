@@ -126,6 +126,7 @@ def lib():
         L.or_adamw_step.argtypes = [i32, vp, vp, vp, vp, dbl, dbl, dbl, dbl, dbl, i64]
         L.or_cvae_sample.argtypes = [C.POINTER(_Shape), vp, vp, i32, vp, vp, i64, u64, u64, vp]
         L.or_cvae_decode.argtypes = [C.POINTER(_Shape), vp, i32, vp, vp, vp, vp, vp]
+        L.or_cvae_act_scales.argtypes = [C.POINTER(_Shape), vp, vp, vp, i64, vp]
         L.or_cvae_features.argtypes = [i32, i64, vp, vp, vp, vp, vp, u64, u64, vp, vp]
         L.or_scene_sdf.argtypes = [C.POINTER(_Scene), vp]
         L.or_scene_sdf.restype = dbl
@@ -292,6 +293,18 @@ def cvae_sample(shape, params, stats, cond, seed, id_offset=0, precision=PREC_FP
     lib().or_cvae_sample(C.byref(s), _p(params), _p(stats), precision, _p(a), _p(cond), n, seed,
                          id_offset, _p(out))
     return out
+
+
+def cvae_act_scales(shape, params, stats, cond):
+    """Per-layer FP8 activation scales (powers of two) of the decoder from raw
+    calibration conditions [n, p_in]; z of row i from the sampler's seed-0
+    stream, id i."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    stats = np.ascontiguousarray(stats, dtype=np.float64)
+    cond = np.ascontiguousarray(cond, dtype=np.float64)
+    out = np.zeros(8)
+    lib().or_cvae_act_scales(C.byref(_shape(shape)), _p(params), _p(stats), _p(cond), cond.shape[0], _p(out))
+    return out[: shape["n_linear"]].copy()
 
 
 def cvae_features(model, walk, seed, id_offset=0):

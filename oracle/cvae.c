@@ -318,6 +318,42 @@ void or_cvae_sample(const or_cvae_shape* s, const double* params, const double* 
     }
 }
 
+/* Per-layer activation scales of a decoder for FP8 inference (the per-layer
+ * scaling of low-precision decoder weights and activations): for decoder
+ * layer j, s_j is the smallest power of two with max |a_j| / s_j <= 448 (the
+ * largest E4M3 value), where a_j is the layer's input in exact arithmetic
+ * (FP64, unquantised weights), maximised over the calibration rows i < n:
+ * standardised condition cond[i] and latent z the first L normals of the
+ * sampler's stream for seed 0 and id i.  s_j = 1 where max |a_j| = 0.
+ * Powers of two make the scaling itself exact. */
+void or_cvae_act_scales(const or_cvae_shape* s, const double* params, const double* stats,
+                        const double* cond, int64_t n, double* scales) {
+    const int nl = or_n_linear(s);
+    const int L = s->latent, C = s->p_in;
+    or_dims dd;
+    or_net_dims(s, 1, &dd);
+    double mx[8] = {0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        double nrm[32];
+        for (int j = 0; 4 * j < L; ++j) or_normal4(0, OR_TAG_CVAE_SAMPLE, (uint64_t)i, (uint32_t)j, nrm + 4 * j);
+        or_trace td;
+        memset(&td, 0, sizeof td);
+        for (int k = 0; k < L; ++k) td.a[0][k] = nrm[k];
+        for (int k = 0; k < C; ++k) td.a[0][L + k] = (cond[i * C + k] - stats[k]) / stats[16 + k];
+        or_mlp_forward(params, nl, nl, &dd, OR_PREC_FP64, NULL, &td);
+        for (int j = 0; j < nl; ++j)
+            for (int k = 0; k < dd.n_in[j]; ++k) mx[j] = fmax(mx[j], fabs(td.a[j][k]));
+    }
+    for (int j = 0; j < nl; ++j) {
+        scales[j] = 1.0;
+        if (mx[j] > 0.0) {
+            int e;
+            double f = frexp(mx[j] / 448.0, &e); /* mx / 448 = f 2^e, f in [0.5, 1) */
+            scales[j] = ldexp(1.0, f == 0.5 ? e - 1 : e);
+        }
+    }
+}
+
 /* Condition and target vectors of one model from walk tuples (Sec. 4.2):
  * sigma_t r enters as its logarithm and N as log N; LengthGen's integer
  * target N is dequantised to log(N + u - 1/2) with u uniform on (0, 1]. */

@@ -125,6 +125,10 @@ void or_cvae_sample(const or_cvae_shape* s, const double* params, const double* 
                     uint64_t seed, uint64_t id_offset, double* out);
 
 /* Decoder-only evaluation with explicit standardised z, eps. */
+/* FP8 activation scales of decoder layers 0 .. n_linear - 1 (powers of two)
+ * from n raw calibration conditions (see cvae.c). */
+void or_cvae_act_scales(const or_cvae_shape* s, const double* params, const double* stats,
+                        const double* cond, int64_t n, double* scales);
 void or_cvae_decode(const or_cvae_shape* s, const double* params, int32_t precision,
                     const double* act_scales, const double* z, const double* cond_std,
                     double* mu, double* logvar);

@@ -252,3 +252,76 @@ def test_narrow_network_equals_wide_network_with_silent_units(oracle, model):
     assert abs(ln - lw) < 1e-12 * max(1.0, abs(ln))
     real = real_param_mask(narrow)
     np.testing.assert_allclose(gw[real], gn[real], rtol=1e-10, atol=1e-13)
+
+
+def _normals_seed0(oracle, i, L):
+    """The first L normals of the sampler's stream for seed 0, id i: Box-Muller
+    on the word pairs of Philox blocks (c0, id, tag CVAE_SAMPLE = 5)."""
+    out = []
+    for c0 in range((L + 3) // 4):
+        w = oracle.philox4x32_10([c0, i & 0xFFFFFFFF, i >> 32, 5], [0, 0])
+        u = (np.asarray(w, np.float64) // 256 + 1) * 2.0**-24
+        for a, b in ((u[0], u[1]), (u[2], u[3])):
+            r = math.sqrt(-2.0 * math.log(a))
+            out += [r * math.cos(2 * math.pi * b), r * math.sin(2 * math.pi * b)]
+    return np.array(out[:L])
+
+
+@pytest.mark.parametrize("name", ["length", "path", "event"])
+def test_fp8_activation_scales_bound_every_layer_input(oracle, name):
+    """FP8 calibration: each decoder layer's activation scale is a power of
+    two and the largest calibration input of that layer divided by it lies
+    in (224, 448] (so no input saturates E4M3 and the largest uses its top
+    binade) -- with the layer inputs recomputed here by a numpy forward pass
+    over the documented parameter layout."""
+    import workloads as W
+    shape = oracle.SHAPES[name]
+    model = shape["model"]
+    p = oracle.cvae_init(shape, seed=21)
+    stats = W.random_stats(model, seed=3)
+    cond = W.random_conditions(model, 300, seed=4)
+    sc = oracle.cvae_act_scales(shape, p, stats, cond)
+    nl, L, C = shape["n_linear"], shape["latent"], shape["p_in"]
+    mx = np.zeros(nl)
+    for i in range(cond.shape[0]):
+        a = np.zeros(16)
+        a[:L] = _normals_seed0(oracle, i, L)
+        a[L:L + C] = (cond[i] - stats[:C]) / stats[16:16 + C]
+        for j in range(nl):
+            n_in = L + C if j == 0 else shape["width"]
+            mx[j] = max(mx[j], np.abs(a[:n_in]).max())
+            lay = p[(nl + j) * 272:(nl + j + 1) * 272]
+            pre = lay[:256].reshape(16, 16) @ a + lay[256:]
+            a = np.logaddexp(0.0, pre)
+    for j in range(nl):
+        m, e = np.frexp(sc[j])
+        assert m == 0.5, sc  # a power of two
+        assert 224.0 < mx[j] / sc[j] <= 448.0, (j, mx[j], sc[j])
+
+
+def test_fp8_activation_scales_cut_the_error_of_small_activations(oracle):
+    """Hidden activations far below 1 (softplus of pre-activations near -7,
+    amplified by the next layer's weights) sit in E4M3's subnormal range
+    unless scaled: with calibrated scales the FP8 decoder's error against
+    FP64 is a fraction of the unscaled one."""
+    import workloads as W
+    shape = oracle.SHAPES["event"]
+    p = oracle.cvae_init(shape, seed=22)
+    stats = W.random_stats(2, seed=5)
+    width = shape["width"]
+    b0 = p[3 * 272 + 256:3 * 272 + 256 + width]
+    b0[:] = -7.0  # first decoder layer: softplus outputs ~1e-3
+    p[4 * 272:4 * 272 + 256] *= 300.0  # second decoder layer amplifies them
+    cond = W.random_conditions(2, 400, seed=6)
+    sc = oracle.cvae_act_scales(shape, p, stats, cond)
+    assert sc[1] <= 2.0**-12
+    e_s, e_u = [], []
+    for i in range(200):
+        z = _normals_seed0(oracle, 1000 + i, shape["latent"])
+        cs = (cond[i] - stats[:7]) / stats[16:23]
+        mu64, _ = oracle.cvae_decode(shape, p, z, cs)
+        mu_s, _ = oracle.cvae_decode(shape, p, z, cs, precision=oracle.PREC_FP8, act_scales=sc)
+        mu_u, _ = oracle.cvae_decode(shape, p, z, cs, precision=oracle.PREC_FP8)
+        e_s.append(np.abs(mu_s - mu64).max())
+        e_u.append(np.abs(mu_u - mu64).max())
+    assert np.median(e_s) < 0.5 * np.median(e_u), (np.median(e_s), np.median(e_u))
