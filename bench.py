@@ -32,6 +32,7 @@ OPS_PER_STEP = 5300.0        # one learned step, two representative events (thre
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
 OPS_PER_WALK_EVENT = 186.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
+CALIB_ROWS = 8192  # training conditions that calibrate the FP8 activation scales
 PEAK_MFMA_BF16 = 2.5e15
 PEAK_HBM_BYTES = 8.0e12
 # active-lane VALU slots per decoded sample of cvae_sample for the standard
@@ -163,11 +164,14 @@ def prepare_model(M, torch, walk, model, shape, batch=4096, seed=0):
     target = torch.empty((n_rows, p_out), dtype=torch.float32, device="cuda")
     M.cvae_features(model, n_rows, walk, seed + 1, 0, None, cond, target, rows=rows)
     stats = M.make_stats(cond, target)
+    # raw conditions of the first rows: calibration of the FP8 activation scales
+    calib = cond[:min(n_rows, CALIB_ROWS)].clone()
     M.cvae_features(model, n_rows, walk, seed + 1, 0, stats, cond, target, rows=rows)
     n = M.cvae_param_count(shape)
     master = torch.empty(n, dtype=torch.float32, device="cuda")
     M.cvae_init(shape, seed + 10 + model, master)
     return dict(model=model, shape=shape, n_rows=n_rows, cond=cond, target=target, stats=stats, master=master,
+                calib=calib,
                 m=torch.zeros_like(master), v=torch.zeros_like(master), batch=batch, seed=seed,
                 ws=torch.empty(M.cvae_workspace_size(shape, batch), dtype=torch.uint8, device="cuda"),
                 loss=torch.zeros(3, dtype=torch.float64, device="cuda"), first=None)
@@ -193,7 +197,7 @@ def finish_model(M, torch, su, precisions=(1,)):
     packed = {}
     for p in precisions:
         pk = torch.empty(M.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-        M.cvae_pack(su["shape"], su["master"], su["stats"], p, pk)
+        M.cvae_pack(su["shape"], su["master"], su["stats"], p, pk, calib=su["calib"] if p == 2 else None)
         packed[p] = pk
     log(f"model {su['model']}: {su['n_rows']} rows, loss (total, KL, NLL) {first} -> {last}")
     return packed, dict(rows=int(su["n_rows"]), first=first.tolist(), last=last.tolist())

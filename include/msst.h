@@ -242,13 +242,23 @@ ms_status cvae_train_step_noalloc(const ms_cvae_shape* shape, float* master_dev,
                                   uint64_t id_offset, double kl_weight, double* loss_dev,
                                   float* grad_dev, void* stream);
 
-/* Inference copy of one model's decoder: bfloat16 weights, or FP8 E4M3
- * weights with a per-layer scale max|W| / 448 (FP32 accumulation either
- * way), plus the standardisation constants.  The encoder is dropped
- * (Sec. 3.2).  stats_dev as for cvae_features. */
+/* Inference copy of one model's decoder (Sec. 3.2: the encoder is dropped;
+ * the paper's shader re-implements the decoders in reduced precision):
+ * bfloat16 weights, or FP8 E4M3 weights with a per-layer weight scale
+ * s_w = max|W| / 448 and a per-layer activation scale s_a (FP32
+ * accumulation either way), plus the standardisation constants (stats_dev
+ * as for cvae_features).  FP8 layer j computes
+ * s_w s_a * (E4M3(W / s_w) . E4M3(a / s_a)) + b.  s_a comes from
+ * calibration: calib_cond_dev holds n_calib raw conditions [n_calib][p_in];
+ * for each decoder layer, s_a is the smallest power of two with
+ * max|a| / s_a <= 448 over those rows, a being the layer's FP32 input from
+ * the master weights with latent z the first L normals of cvae_sample's
+ * stream for seed 0, id = row.  n_calib = 0 (or BF16) gives s_a = 1.
+ * n_calib <= 2^20; stats_dev is required with calibration rows. */
 size_t cvae_packed_bytes(void);
 ms_status cvae_pack(const ms_cvae_shape* shape, const float* master_dev, const double* stats_dev,
-                    int32_t precision, void* packed_dev, size_t packed_bytes, void* stream);
+                    int32_t precision, const float* calib_cond_dev, int64_t n_calib,
+                    void* packed_dev, size_t packed_bytes, void* stream);
 
 /* Decoder-only sampling (Sec. 3.2 inference): z ~ N(0, I), then
  * y = mu_Dec(z, c) + exp(logvar / 2) eps, de-standardised.  Path i draws its
@@ -343,15 +353,21 @@ typedef struct {
     int32_t restart_min;     /* lanes waiting for a new path that trigger a restart pass, 1..64; 0 = 16 */
     int32_t max_wait;        /* loop iterations after which waiting lanes force a pass anyway; 0 = 10 */
     int32_t nee_samples;     /* representative events per learned step, 1..16 (0 = 1) */
-    int32_t flags;           /* MS_RENDER_NEE_BEFORE_ABSORPTION */
+    int32_t flags;           /* MS_RENDER_NEE_BEFORE_ABSORPTION | MS_RENDER_STEP_PAPER */
 } ms_render_desc;
 
-/* Direct light of a learned step estimated before its absorption test, with
- * weight sum_{i<=N} albedo^i, for every step (the paper's order rejects
- * first and weights survivors by that sum / albedo^N); both are unbiased for
- * sum_i albedo^i f_i.  K = nee_samples representative events average K
- * independent EventGen samples (each its own first-event test). */
-enum { MS_RENDER_NEE_BEFORE_ABSORPTION = 1 };
+/* MS_RENDER_NEE_BEFORE_ABSORPTION: direct light of a learned step estimated
+ * before its absorption test, with weight sum_{i<=N} albedo^i, for every
+ * step (the paper's order rejects first and weights survivors by that sum /
+ * albedo^N); both are unbiased for sum_i albedo^i f_i.  K = nee_samples
+ * representative events average K independent EventGen samples (each its
+ * own first-event test).
+ * MS_RENDER_STEP_PAPER: the learned step as the paper prints it (Sec. 3.2,
+ * Sec. 4.2, Sec. 4.3): PathGen for every lit step, also N = 1, and EventGen
+ * for every representative event, also the first one; the models are then
+ * meant to be trained on every walk record.  The same Philox blocks are
+ * drawn as without the flag (the HG and first-event uniforms go unused). */
+enum { MS_RENDER_NEE_BEFORE_ABSORPTION = 1, MS_RENDER_STEP_PAPER = 2 };
 
 typedef struct {
     float* sum;          /* [width * height] sum of path radiance */

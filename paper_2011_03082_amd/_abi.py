@@ -16,6 +16,7 @@ PREC_BF16, PREC_FP8 = 1, 2
 PRIM_SPHERE, PRIM_BOX = 0, 1
 METHOD_PLAIN_NEE, METHOD_ST = 1, 2
 SAMPLER_CVAE, SAMPLER_EXACT_WALK = 0, 1
+RENDER_NEE_BEFORE_ABSORPTION, RENDER_STEP_PAPER = 1, 2
 
 
 class MsError(RuntimeError):
@@ -102,7 +103,7 @@ SIGNATURES = {
     "cvae_train_step_noalloc": ([_P(CvaeShape), _vp, _vp, _vp, _P(Adam), _vp, _vp, _i64, _i32, _i32, _u64, _i64,
                                  _u64, C.c_double, _vp, _vp, _vp], C.c_int32),
     "cvae_packed_bytes": ([], C.c_size_t),
-    "cvae_pack": ([_P(CvaeShape), _vp, _vp, _i32, _vp, _sz, _vp], C.c_int32),
+    "cvae_pack": ([_P(CvaeShape), _vp, _vp, _i32, _vp, _i64, _vp, _sz, _vp], C.c_int32),
     "cvae_sample": ([_vp, _vp, _i64, _u64, _u64, _vp, _vp], C.c_int32),
     "sphere_trace_render_workspace_size": ([_P(Camera), _P(RenderDesc), _P(_sz)], C.c_int32),
     "sphere_trace_render": ([_P(Scene), _P(Camera), _P(Light), _P(Medium), _P(RenderDesc), _P(ImageOut), _vp,

@@ -192,9 +192,12 @@ def cvae_packed_bytes():
     return lib().cvae_packed_bytes()
 
 
-def cvae_pack(shape, master, stats, precision, packed, stream=None):
-    check(lib().cvae_pack(C.byref(cvae_shape(shape)), _ptr(master), _ptr(stats), precision, _ptr(packed),
-                          packed.numel() * packed.element_size(), _stream(stream)))
+def cvae_pack(shape, master, stats, precision, packed, stream=None, calib=None):
+    """calib: optional device [n, p_in] raw calibration conditions (FP8
+    activation scales)."""
+    n_calib = 0 if calib is None else calib.shape[0]
+    check(lib().cvae_pack(C.byref(cvae_shape(shape)), _ptr(master), _ptr(stats), precision, _ptr(calib), n_calib,
+                          _ptr(packed), packed.numel() * packed.element_size(), _stream(stream)))
 
 
 def cvae_sample(packed, cond, n, seed, id_offset, out, stream=None):

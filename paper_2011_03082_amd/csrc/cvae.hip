@@ -586,7 +586,62 @@ __device__ __forceinline__ uint32_t fp8_e4m3_bits(float x) {
     return sign | ((uint32_t)eb << 3) | (mant & 7u);
 }
 
-__global__ void cvae_pack_kernel(Shape s, const float* master, const double* stats, int precision, PackedModel* pm) {
+// FP8 activation scales from calibration rows (one block of 256 threads):
+// decoder layer j's inputs a_j, computed in FP32 from the master weights for
+// every row i < n -- the standardised condition cond[i] after the latent z,
+// z the first `latent` normals of the sampler's stream for seed 0 and id i
+// -- give s_j, the smallest power of two with max_i |a_j| / s_j <= 448 (the
+// largest E4M3 value; 1 where the maximum is 0).  Writes in_scale = 1 / s_j;
+// cvae_pack_kernel then folds s_j into out_scale.
+__global__ __launch_bounds__(256) void cvae_calib_kernel(Shape s, const float* master, const double* stats,
+                                                         const float* cond, int64_t n, PackedModel* pm) {
+    const int nl = s.n_linear, L = s.latent, C = s.p_in;
+    float mx[kMaxLayers] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        float a[kTile], nrm[8];
+        const Rng r = make_rng(0, MS_TAG_CVAE_SAMPLE, (uint64_t)i);
+        for (int j = 0; 4 * j < L; ++j) normals4(r, (uint32_t)j, nrm + 4 * j);
+        for (int k = 0; k < kTile; ++k) a[k] = 0.0f;
+        for (int k = 0; k < L; ++k) a[k] = nrm[k];
+        for (int k = 0; k < C; ++k) a[L + k] = (float)((cond[i * C + k] - stats[k]) / stats[16 + k]);
+        for (int j = 0; j < nl; ++j) {
+            const LayerDims d = layer_dims(s, nl + j);
+            for (int k = 0; k < d.n_in; ++k) mx[j] = fmaxf(mx[j], fabsf(a[k]));
+            if (j == nl - 1) break;
+            const float* layer = master + (nl + j) * kLayerFloats;
+            float o[kTile];
+            for (int row = 0; row < d.n_out; ++row) {
+                float acc = layer[kTile * kTile + row];
+                for (int k = 0; k < d.n_in; ++k) acc = fmaf(layer[row * kTile + k], a[k], acc);
+                o[row] = softplus(acc);
+            }
+            for (int k = 0; k < kTile; ++k) a[k] = k < d.n_out ? o[k] : 0.0f;
+        }
+    }
+    __shared__ float red[kMaxLayers][256];
+    for (int j = 0; j < kMaxLayers; ++j) red[j][threadIdx.x] = mx[j];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int j = 0; j < kMaxLayers; ++j) red[j][threadIdx.x] = fmaxf(red[j][threadIdx.x], red[j][threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x < kMaxLayers) {
+        const float m = red[threadIdx.x][0];
+        float inv = 1.0f;
+        if (m > 0.0f) {
+            int e;
+            const float f = frexpf(m / 448.0f, &e);  // m / 448 = f 2^e, f in [0.5, 1)
+            inv = ldexpf(1.0f, -(f == 0.5f ? e - 1 : e));
+        }
+        pm->in_scale[threadIdx.x] = inv;
+    }
+}
+
+// With `calibrated`, in_scale was written by cvae_calib_kernel earlier on the
+// same stream; otherwise activations enter E4M3 unscaled.
+__global__ void cvae_pack_kernel(Shape s, const float* master, const double* stats, int precision, bool calibrated,
+                                 PackedModel* pm) {
     const int lane = threadIdx.x;  // 64 threads
     const int nl = s.n_linear;
     if (lane == 0) {
@@ -622,7 +677,11 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
             scale = smax[0] > 0.0f ? smax[0] / 448.0f : 1.0f;
             __syncthreads();
         }
-        if (lane == 0) pm->w_scale[j] = scale;
+        if (lane == 0) {
+            const float in_sc = precision == MS_PREC_FP8 && calibrated ? pm->in_scale[j] : 1.0f;
+            pm->in_scale[j] = in_sc;
+            pm->out_scale[j] = scale / in_sc;  // s_w s_a, exact: s_a is a power of two
+        }
         if (lane < 16) pm->bias[j][lane] = real ? layer[kTile * kTile + lane] : 0.0f;
         const int r = lane & 15, kg = lane >> 4;
         uint32_t w0 = 0, w1 = 0;
@@ -1007,20 +1066,27 @@ ms_status cvae_train_step_noalloc(const ms_cvae_shape* shape, float* master_dev,
 size_t cvae_packed_bytes(void) { return sizeof(msst::PackedModel); }
 
 ms_status cvae_pack(const ms_cvae_shape* shape, const float* master_dev, const double* stats_dev, int32_t precision,
-                    void* packed_dev, size_t packed_bytes, void* stream) {
+                    const float* calib_cond_dev, int64_t n_calib, void* packed_dev, size_t packed_bytes,
+                    void* stream) {
     using namespace msst;
     Shape s;
     ms_status st = check_shape(shape, &s);
     if (st != MS_OK) return st;
     MS_REQUIRE(master_dev && packed_dev, "cvae_pack: NULL array");
     MS_REQUIRE(precision == MS_PREC_BF16 || precision == MS_PREC_FP8, "cvae_pack: precision must be BF16 or FP8");
+    MS_REQUIRE(n_calib >= 0 && n_calib <= (1 << 20), "cvae_pack: n_calib must be in [0, 2^20]");
+    MS_REQUIRE(n_calib == 0 || (calib_cond_dev && stats_dev), "cvae_pack: calibration rows need calib_cond and stats");
     MS_REQUIRE(((uintptr_t)packed_dev & 15u) == 0, "cvae_pack: packed buffer must be 16-byte aligned");
     if (packed_bytes < sizeof(PackedModel))
         return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "cvae_pack: packed buffer needs %zu bytes", sizeof(PackedModel));
     int cus;
     if ((st = device_cu_count(&cus)) != MS_OK) return st;
+    const bool calib = precision == MS_PREC_FP8 && n_calib > 0;
+    if (calib)
+        hipLaunchKernelGGL(cvae_calib_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, s, master_dev, stats_dev,
+                           calib_cond_dev, n_calib, reinterpret_cast<PackedModel*>(packed_dev));
     hipLaunchKernelGGL(cvae_pack_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, s, master_dev, stats_dev, precision,
-                       reinterpret_cast<PackedModel*>(packed_dev));
+                       calib, reinterpret_cast<PackedModel*>(packed_dev));
     MS_LAUNCHED();
     clear_error();
     return MS_OK;

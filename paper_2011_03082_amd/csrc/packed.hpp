@@ -14,8 +14,12 @@ constexpr int kMaxLayers = 4;
 struct PackedModel {
     int32_t magic, model, p_in, p_out, latent, width, n_linear, precision;
     float mean_c[16], inv_std_c[16], mean_y[16], std_y[16];
-    float w_scale[kMaxLayers];     // per-layer weight scale (FP8), 1 for BF16
-    float reserved[kMaxLayers];
+    // FP8: products of layer j are rescaled by out_scale[j] = s_w s_a (weight
+    // scale max|W| / 448 times the activation scale s_a, a power of two) and
+    // its inputs enter E4M3 multiplied by in_scale[j] = 1 / s_a; both 1 for
+    // BF16 (and in_scale 1 without calibration rows)
+    float out_scale[kMaxLayers];
+    float in_scale[kMaxLayers];
     float bias[kMaxLayers][16];
     // A-operand fragments per decoder layer and lane: 4 bfloat16 (BF16) or
     // 8 FP8 E4M3 values of weight row l % 16 (FP8 uses K = 32, upper half 0).
@@ -57,7 +61,8 @@ constexpr int kDecLayers = 3;
 struct DecoderRegs {
     uint2 a[kDecLayers];
     f32x4 b[kDecLayers];
-    float sc[kDecLayers];
+    float sc[kDecLayers];   // out_scale
+    float isc[kDecLayers];  // in_scale
 };
 
 __device__ __forceinline__ DecoderRegs load_decoder(const PackedModel* pm) {
@@ -67,7 +72,8 @@ __device__ __forceinline__ DecoderRegs load_decoder(const PackedModel* pm) {
     for (int j = 0; j < kDecLayers; ++j) {
         w.a[j] = *reinterpret_cast<const uint2*>(pm->frag[j][lane_id()]);
         w.b[j] = *reinterpret_cast<const f32x4*>(&pm->bias[j][k0]);
-        w.sc[j] = pm->w_scale[j];
+        w.sc[j] = pm->out_scale[j];
+        w.isc[j] = pm->in_scale[j];
     }
     return w;
 }
@@ -90,13 +96,22 @@ __device__ __forceinline__ f32x4 decoder_tile(const DecoderRegs& w, f32x4 xin) {
     return acc;
 }
 
-// The same on FP8 E4M3 weights and activations with per-layer weight scales.
+// Layer inputs times the activation scale's reciprocal (a power of two, so
+// exact), the operand that enters E4M3.
+__device__ __forceinline__ f32x4 scaled(f32x4 x, float isc) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] *= isc;
+    return x;
+}
+
+// The same on FP8 E4M3 weights and activations with per-layer weight and
+// activation scales.
 __device__ __forceinline__ f32x4 decoder_tile_fp8(const DecoderRegs& w, f32x4 x) {
     f32x4 acc;
 #pragma unroll
     for (int j = 0; j < kDecLayers; ++j) {
         const fp8x8 a = (fp8x8)(((uint64_t)w.a[j].y << 32) | w.a[j].x);
-        acc = mfma_fp8(a, to_fp8x4_lo(x), f32x4{0, 0, 0, 0});
+        acc = mfma_fp8(a, to_fp8x4_lo(scaled(x, w.isc[j])), f32x4{0, 0, 0, 0});
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(acc[q], w.sc[j], w.b[j][q]);
         if (j < kDecLayers - 1) {
@@ -119,8 +134,8 @@ __device__ __forceinline__ f32x4 decoder_tile_layers(const PackedModel* pm, f32x
         const f32x4 b = *reinterpret_cast<const f32x4*>(&pm->bias[j][k0]);
         if (fp8) {
             const fp8x8 a = (fp8x8)(((uint64_t)u.y << 32) | u.x);
-            acc = mfma_fp8(a, to_fp8x4_lo(x), f32x4{0, 0, 0, 0});
-            const float sc = pm->w_scale[j];
+            acc = mfma_fp8(a, to_fp8x4_lo(scaled(x, pm->in_scale[j])), f32x4{0, 0, 0, 0});
+            const float sc = pm->out_scale[j];
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[q] = __builtin_fmaf(acc[q], sc, b[q]);
         } else {

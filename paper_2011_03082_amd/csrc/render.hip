@@ -915,10 +915,14 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
         // NEE before absorption the direct light of the step is
         // estimated for every step (weight Lambda) and the absorption
         // only ends the path; otherwise only surviving steps add it
-        // (weight Lambda / albedo^N, the order of Sec. 3.2).
+        // (weight Lambda / albedo^N, the order of Sec. 3.2).  The paper's
+        // step as printed (MS_RENDER_STEP_PAPER) asks PathGen and EventGen
+        // in every case; the HG and first-event uniforms are then drawn and
+        // left unused, so both forms keep the same draw order.
         const bool before = (A.flags & MS_RENDER_NEE_BEFORE_ABSORPTION) != 0;
+        const bool paper = (A.flags & MS_RENDER_STEP_PAPER) != 0;
         const bool lit = before ? mine : alive;
-        const bool use_path = lit && N >= 2.0f;
+        const bool use_path = lit && (N >= 2.0f || paper);
         // Lambda and Lambda / albedo^N each in a form that stays finite
         // for any N (their product form overflows once albedo^-N does)
         const float lam = lambda_total(A, N);
@@ -957,7 +961,7 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
         for (int k = 0; k < A.nee_samples; ++k) {
             float uf = u_first;
             if (k > 0 && lit) uf = u01(rng.block(c0++).x);
-            const bool use_event = use_path && !(uf * lam <= A.albedo);
+            const bool use_event = use_path && (paper || !(uf * lam <= A.albedo));
             V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
             const uint64_t emask = ballot(use_event);
             if (emask) {
@@ -1282,7 +1286,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
     MS_REQUIRE(desc->restart_min >= 0 && desc->restart_min <= 64, "sphere_trace_render: restart_min must be in [0, 64]");
     MS_REQUIRE(desc->max_wait >= 0, "sphere_trace_render: max_wait must be >= 0");
-    MS_REQUIRE((desc->flags & ~MS_RENDER_NEE_BEFORE_ABSORPTION) == 0, "sphere_trace_render: unknown flags");
+    MS_REQUIRE((desc->flags & ~(MS_RENDER_NEE_BEFORE_ABSORPTION | MS_RENDER_STEP_PAPER)) == 0,
+               "sphere_trace_render: unknown flags");
     MS_REQUIRE(out->sum && out->sumsq, "sphere_trace_render: sum and sumsq images are required");
     MS_REQUIRE(scene->sdf_fp16 == nullptr || (scene->res > 0 && scene->res <= 4096 && scene->hi[0] > scene->lo[0] &&
                                              scene->hi[1] > scene->lo[1] && scene->hi[2] > scene->lo[2]),

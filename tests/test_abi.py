@@ -109,3 +109,14 @@ def test_train_step_noalloc_rejects_beyond_its_maximum(M):
                                          None, None, None)
     assert st == M._abi.MS_ERR_UNSUPPORTED
 
+
+def test_pack_rejects_invalid_calibration(M):
+    """cvae_pack: calibration rows need a condition array and stats, and at
+    most 2^20 of them; validated before any launch."""
+    shape = M.cvae_shape(1)
+    p = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    nb = M.cvae_packed_bytes()
+    for cond, n, stats in ((p, -1, p), (p, (1 << 20) + 1, p), (None, 16, p), (p, 16, None)):
+        st = M.lib().cvae_pack(C.byref(shape), p, stats, 2, cond, n, p, nb, None)
+        assert st == M._abi.MS_ERR_INVALID_ARGUMENT
+        assert b"calib" in M.lib().ms_last_error()

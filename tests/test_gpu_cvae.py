@@ -11,6 +11,14 @@ from conftest import announce
 pytestmark = pytest.mark.gpu
 
 BF16_U = 2.0**-8  # unit roundoff of bfloat16 (8 significant bits)
+FP8_U = 2.0**-4  # unit roundoff of FP8 E4M3 (4 significant bits)
+# Gradients of the bfloat16 MFMA forward / backward against FP64: each
+# gradient entry sums products of a few rounded operands over the batch, so
+# independent roundings of size u average to ~u / 2 relative in L2 (measured
+# 1.0e-3 to 2.7e-3 over the standard and Table 1 shapes); the batch-mean
+# loss to ~u / 10.
+GRAD_REL = 5e-3
+LOSS_REL = 2e-3
 MODELS = [0, 1, 2]
 
 
@@ -109,8 +117,8 @@ def test_gradient_parity_bf16(msst, oracle, model):
     rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
     cos = g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64))
     print(f"model {model}: grad rel-L2 {rel:.3e}, cosine {cos:.6f}, loss {loss} vs {ref}")
-    assert rel < 10 * BF16_U and cos > 0.999
-    np.testing.assert_allclose(loss, ref, rtol=10 * BF16_U, atol=1e-3)
+    assert rel < GRAD_REL and cos > 0.999
+    np.testing.assert_allclose(loss, ref, rtol=LOSS_REL, atol=1e-3)
     assert abs(loss[0] - loss[1] - loss[2]) < 1e-9 * abs(loss[0])
 
 
@@ -118,15 +126,15 @@ def test_gradient_parity_kl_weight(msst, oracle):
     announce("cvae grad kl weight")
     g, g64, loss, ref = grad_case(msst, oracle, 1, B=128, kl_weight=0.3)
     rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
-    assert rel < 10 * BF16_U
+    assert rel < GRAD_REL
 
 
 def test_gradient_parity_sampled_rows_and_ragged(msst, oracle):
     announce("cvae grad sampled rows")
     g, g64, loss, ref = grad_case(msst, oracle, 2, B=16 * 37, sample_rows=1, n_rows=5000)
     rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
-    assert rel < 10 * BF16_U
-    np.testing.assert_allclose(loss, ref, rtol=10 * BF16_U, atol=1e-3)
+    assert rel < GRAD_REL
+    np.testing.assert_allclose(loss, ref, rtol=LOSS_REL, atol=1e-3)
 
 
 def test_adamw_step_matches_oracle(msst, oracle):
@@ -223,28 +231,55 @@ def test_sample_matches_bf16_emulating_oracle(msst, oracle, model):
     assert err.max() < 0.05
     ref64 = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 99, 1000)
     err64 = np.abs(got - ref64).max(axis=1) / scale.max()
-    print(f"model {model}: error against the FP64 decoder median {np.median(err64):.2e}, max {err64.max():.2e}")
-    assert np.median(err64) < 0.05
+    print(f"model {model}: error against the FP64 decoder median {np.median(err64):.2e}, p90 "
+          f"{np.quantile(err64, 0.9):.2e}, max {err64.max():.2e} (bfloat16 unit roundoff {BF16_U:.2e})")
+    # reduced-precision decoders against the exact one, in units of the
+    # output's standard deviation: each output sums ~16 products of rounded
+    # operands per layer over three layers, so a typical sample is off by a
+    # fraction of the format's unit roundoff u and nine in ten by at most u
+    # (measured median 0.23-0.35 u, p90 0.5-0.6 u)
+    assert np.median(err64) < 0.5 * BF16_U and np.quantile(err64, 0.9) < BF16_U
 
 
+def packed_scales(packed):
+    """(out_scale, in_scale) of a packed decoder: the 4 + 4 floats after the
+    header (8 int32) and the four 16-float standardisation blocks."""
+    f = packed.cpu().view(torch.float32).numpy()
+    return f[72:76].astype(np.float64), f[76:80].astype(np.float64)
+
+
+@pytest.mark.parametrize("calibrated", [False, True])
 @pytest.mark.parametrize("model", MODELS)
-def test_sample_fp8_matches_fp8_emulating_oracle(msst, oracle, model):
-    """FP8 E4M3 decoders (per-layer weight scale max|W|/448, FP32 accumulation)
-    against the oracle rounding weights and layer inputs to E4M3 the same way.
+def test_sample_fp8_matches_fp8_emulating_oracle(msst, oracle, model, calibrated):
+    """FP8 E4M3 decoders (per-layer weight scale max|W|/448, FP32 accumulation;
+    with calibration rows also per-layer activation scales, powers of two)
+    against the oracle rounding weights and layer inputs to E4M3 the same way,
+    with the activation scales of its own calibration on the same rows.
     E4M3 keeps 4 significant bits (unit roundoff 2^-4), so rounding flips from
     FP32-vs-FP64 differences are rare but each moves an activation by ~6 %."""
-    announce(f"cvae sample fp8 model={model}")
+    announce(f"cvae sample fp8 model={model} calibrated={calibrated}")
     shape = W.SHAPE_LIST[model]
     master64 = oracle.cvae_init(shape, seed=70 + model).astype(np.float32).astype(np.float64)
     stats = W.random_stats(model, seed=10 + model)
     n = 3000 + 21
     cond = W.random_conditions(model, n, seed=20 + model).astype(np.float32)
     packed = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
-    msst.cvae_pack(model, dev(master64), dev(stats, torch.float64), 2, packed)
+    calib = cond[:1500]
+    msst.cvae_pack(model, dev(master64), dev(stats, torch.float64), 2, packed,
+                   calib=dev(calib) if calibrated else None)
+    act = oracle.cvae_act_scales(shape, master64, stats, calib.astype(np.float64)) if calibrated else None
+    out_sc, in_sc = packed_scales(packed)
+    nl = shape["n_linear"]
+    if calibrated:
+        print(f"model {model}: activation scales {act}")
+        np.testing.assert_array_equal(in_sc[:nl], 1.0 / act)
+    else:
+        np.testing.assert_array_equal(in_sc, 1.0)
     out = torch.empty((n, shape["p_out"]), dtype=torch.float32, device="cuda")
     msst.cvae_sample(packed, dev(cond), n, 5, 0, out)
     got = out.cpu().numpy().astype(np.float64)
-    ref = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 5, 0, precision=oracle.PREC_FP8)
+    ref = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 5, 0, precision=oracle.PREC_FP8,
+                             act_scales=act)
     scale = stats[48:48 + shape["p_out"]].max()
     err = np.abs(got - ref).max(axis=1) / scale
     print(f"model {model}: median {np.median(err):.2e}, p99 {np.quantile(err, 0.99):.2e}, max {err.max():.2e}")
@@ -252,4 +287,10 @@ def test_sample_fp8_matches_fp8_emulating_oracle(msst, oracle, model):
     assert err.max() < 0.2
     ref16 = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 5, 0, precision=oracle.PREC_BF16)
     e16 = np.abs(got - ref16).max(axis=1) / scale
-    print(f"model {model}: FP8 against the BF16 decoder: median {np.median(e16):.2e}")
+    ref64 = oracle.cvae_sample(shape, master64, stats, cond.astype(np.float64), 5, 0)
+    e64 = np.abs(got - ref64).max(axis=1) / scale
+    print(f"model {model}: FP8 against the BF16 decoder: median {np.median(e16):.2e}; against FP64: median "
+          f"{np.median(e64):.2e}, p90 {np.quantile(e64, 0.9):.2e} (E4M3 unit roundoff {FP8_U:.2e})")
+    # the same rule as for bfloat16 with E4M3's unit roundoff (measured
+    # median 0.14-0.37 u, p90 0.34-0.68 u)
+    assert np.median(e64) < 0.5 * FP8_U and np.quantile(e64, 0.9) < FP8_U

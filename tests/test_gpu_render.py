@@ -15,6 +15,15 @@ pytestmark = pytest.mark.gpu
 PLAIN, ST = 1, 2
 CVAE, EXACT = 0, 1
 
+# Parity bars.  Plain tracing and exact in-sphere walks (FP32 against FP64
+# on the same draws) agree per path to 1e-4 relative; learned steps to 1e-3
+# (a bfloat16 or E4M3 rounding flipped by an FP32-vs-FP64 difference moves a
+# decoder output by one ulp).  The diverged fractions allowed are at most
+# two or three paths of the image beyond what was measured (0 to 9e-4); the
+# dense and many-primitive cases, with chains of 10^3 to 10^4 FP32 events,
+# carry their own, stated below.
+PLAIN_REL, LEARNED_REL = 1e-4, 1e-3
+
 
 def f32(v):
     return tuple(float(np.float32(x)) for x in v)
@@ -54,23 +63,29 @@ def models_for_test(oracle):
     return models, packed_src
 
 
-def pack_all(msst, packed_src, precision=1):
+def pack_all(msst, packed_src, precision=1, calib=None):
+    """calib: per model raw calibration conditions (FP8 activation scales)."""
     out = []
     for m, (master, stats) in enumerate(packed_src):
         p = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+        cal = None if calib is None else torch.as_tensor(calib[m], dtype=torch.float32).cuda()
         msst.cvae_pack(m, torch.as_tensor(master, dtype=torch.float32).cuda(),
-                       torch.as_tensor(stats, dtype=torch.float64).cuda(), precision, p)
+                       torch.as_tensor(stats, dtype=torch.float64).cuda(), precision, p, calib=cal)
         out.append(p)
     return out
 
 
 def compare_paths(g, o, rel=1e-3):
-    """Per pixel (spp = 1: per path) agreement; returns the diverged fraction."""
+    """Per pixel (spp = 1: per path) agreement; returns the diverged fraction
+    at relative error `rel` (and prints it at 1e-4, 1e-3 and 2e-3)."""
     gs, os_ = g["sum"].astype(np.float64) + g["comp"], o["sum"]
-    tol = rel * np.abs(os_) + 1e-7 * max(1e-30, np.abs(os_).max())
-    bad = np.abs(gs - os_) > tol
-    bad |= g["events"].astype(np.int64) != o["events"].astype(np.int64)
-    bad |= g["steps"].astype(np.int64) != o["steps"].astype(np.int64)
+    floor = 1e-7 * max(1e-30, np.abs(os_).max())
+    count = g["events"].astype(np.int64) != o["events"].astype(np.int64)
+    count |= g["steps"].astype(np.int64) != o["steps"].astype(np.int64)
+    at = {r: (count | (np.abs(gs - os_) > r * np.abs(os_) + floor)).mean() for r in (1e-4, 1e-3, 2e-3, rel)}
+    print("diverged at rel 1e-4 / 1e-3 / 2e-3: " + " / ".join(f"{at[r]:.2e}" for r in (1e-4, 1e-3, 2e-3))
+          + f"; counts differ {count.mean():.2e}")
+    bad = count | (np.abs(gs - os_) > rel * np.abs(os_) + floor)
     return bad.mean(), bad
 
 
@@ -85,9 +100,9 @@ def test_plain_nee_path_by_path(msst, oracle, sigma_t):
     prims, cam, light, med = c4_inputs(sigma_t, 48)
     g = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=1, seed=3)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=1, seed=3)
-    frac, bad = compare_paths(g, o)
+    frac, bad = compare_paths(g, o, rel=PLAIN_REL)
     print(f"diverged {frac:.2e}; lit pixels {(o['sum'] > 0).mean():.2f}")
-    assert frac < 2e-3
+    assert frac < 1.5e-3
     assert (o["sum"] > 0).mean() > 0.2
 
 
@@ -97,32 +112,43 @@ def test_exact_walk_sphere_tracing_path_by_path(msst, oracle):
     g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=EXACT, spp=1, seed=4)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST,
                       sampler=oracle.SAMPLER_EXACT_WALK, spp=1, seed=4)
-    frac, _ = compare_paths(g, o)
+    frac, _ = compare_paths(g, o, rel=PLAIN_REL)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}")
-    assert frac < 5e-3
+    assert frac < 1.5e-3
     assert o["steps"].sum() > 100
 
 
-@pytest.mark.parametrize("precision", [1, 2])
-def test_learned_sphere_tracing_path_by_path(msst, oracle, precision):
-    announce(f"render ST CVAE parity precision={precision}")
+@pytest.mark.parametrize("precision,calibrated", [(1, False), (2, False), (2, True)])
+def test_learned_sphere_tracing_path_by_path(msst, oracle, precision, calibrated):
+    """Learned steps with BF16 decoders, FP8 decoders with weight scales only,
+    and FP8 with per-layer activation scales from calibration rows (the
+    oracle calibrates on the same rows)."""
+    announce(f"render ST CVAE parity precision={precision} calibrated={calibrated}")
     prims, cam, light, med = c4_inputs(20.0, 40)
     models, src = models_for_test(oracle)
-    packed = pack_all(msst, src, precision)
+    calib = None
+    if calibrated:
+        calib = [W.random_conditions(m, 2048, seed=30 + m).astype(np.float32) for m in range(3)]
+        for m in range(3):
+            models[m]["act_scales"] = oracle.cvae_act_scales(models[m]["shape"], models[m]["params"],
+                                                             models[m]["stats"], calib[m].astype(np.float64))
+    packed = pack_all(msst, src, precision, calib)
     g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=5)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8, models=models, spp=1,
                       seed=5)
-    frac, _ = compare_paths(g, o, rel=2e-3)
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
     assert o["steps"].sum() > 100
-    assert frac < 0.03
+    assert frac < 1e-3
 
 
-@pytest.mark.parametrize("nee_samples,flags", [(2, 0), (3, 1)])
+@pytest.mark.parametrize("nee_samples,flags", [(2, 0), (3, 1), (1, 2), (2, 3)])
 def test_learned_steps_with_several_events_path_by_path(msst, oracle, nee_samples, flags):
     """K representative events per learned step, optionally lit before the
-    absorption test: same draws, same per-path values as the oracle."""
+    absorption test, and the paper's step as printed (flag 2: PathGen and
+    EventGen in every case, no exact single-event parts): same draws, same
+    per-path values as the oracle."""
     announce(f"render ST CVAE parity K={nee_samples} flags={flags}")
     prims, cam, light, med = c4_inputs(20.0, 40)
     med["albedo"] = float(np.float32(0.97))
@@ -133,10 +159,10 @@ def test_learned_steps_with_several_events_path_by_path(msst, oracle, nee_sample
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, spp=1, seed=15, nee_samples=nee_samples,
                       flags=flags)
-    frac, _ = compare_paths(g, o, rel=2e-3)
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
     assert o["steps"].sum() > 100
-    assert frac < 0.03
+    assert frac < 1e-3
 
 
 @pytest.mark.parametrize("flags", [0, 1])
@@ -154,17 +180,20 @@ def test_learned_steps_with_very_long_chains_path_by_path(msst, oracle, flags):
     assert np.isfinite(g["sum"]).all() and np.isfinite(g["comp"]).all()
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, spp=1, seed=16, nee_samples=2, flags=flags)
-    frac, _ = compare_paths(g, o, rel=2e-3)
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, lit sum {o['sum'].sum():.4g}")
     assert o["steps"].sum() > 100
-    assert frac < 0.03
+    assert frac < 1e-3
 
 
-@pytest.mark.parametrize("sigma_t", [320.0, 1280.0])
-def test_dense_nearly_white_medium_learned_path_by_path(msst, oracle, sigma_t):
+@pytest.mark.parametrize("sigma_t,rel,bar", [(320.0, 1e-3, 5e-3), (1280.0, 2e-3, 2e-2)])
+def test_dense_nearly_white_medium_learned_path_by_path(msst, oracle, sigma_t, rel, bar):
     """The density sweep's media (albedo 0.9999, sigma_t up to 1280): radii
     capped at st_max / sigma_t, long plain chains near the surface; same
-    per-path values as the oracle."""
+    per-path values as the oracle.  Paths here carry hundreds to thousands
+    of FP32 collisions before and between learned steps, so their positions
+    drift by more ulps and an occasional branch flips: measured 2.5e-3 of
+    the paths beyond 1e-3 at sigma_t 320, 1.1e-2 beyond 2e-3 at 1280."""
     announce(f"render ST CVAE parity, dense medium sigma_t={sigma_t}")
     prims, cam, light, med = c4_inputs(sigma_t, 40)
     med["albedo"] = float(np.float32(0.9999))
@@ -176,10 +205,10 @@ def test_dense_nearly_white_medium_learned_path_by_path(msst, oracle, sigma_t):
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, spp=1, seed=17, tau_min=6.0, nee_samples=2,
                       flags=1)
-    frac, _ = compare_paths(g, o, rel=2e-3)
+    frac, _ = compare_paths(g, o, rel=rel)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
     assert o["steps"].sum() > 100
-    assert frac < 0.03
+    assert frac < bar
 
 
 @pytest.mark.parametrize("sampler,tau_min", [(EXACT, 1e30), (CVAE, 1e30), (EXACT, 10.0), (CVAE, 10.0)])
@@ -261,7 +290,9 @@ def test_degenerate_media(msst, oracle):
     dense = f32_medium(dict(sigma_t=300.0, g=-0.5, albedo=0.9))
     g = gpu_render(msst, prims, cam, light, dense, method=PLAIN, spp=1, seed=12)
     o = oracle.render(oracle.Scene(prims), cam, light, dense, method=oracle.METHOD_PLAIN_NEE, spp=1, seed=12)
-    frac, _ = compare_paths(g, o)
+    # sigma_t 300 with back-scattering: chains of ~10^3 FP32 events; one path
+    # of the 576 measured beyond 1e-3
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     assert frac < 5e-3
 
 
@@ -276,9 +307,9 @@ def test_full_size_c4_sampled_pixels(msst, oracle):
     pix = np.sort(rng.choice(lit, 300, replace=False)).astype(np.int32)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=1, seed=13,
                       pixels=pix)
-    gs = g["sum"][pix].astype(np.float64) + g["comp"][pix]
-    bad = (np.abs(gs - o["sum"]) > 1e-3 * np.abs(o["sum"]) + 1e-9) | (g["events"][pix] != o["events"])
-    assert bad.mean() < 0.01
+    sub = {k: g[k][pix] for k in ("sum", "comp", "events", "steps")}
+    frac, _ = compare_paths(sub, o, rel=PLAIN_REL)
+    assert frac < 1e-2
 
 
 def test_full_size_c4_learned_sampled_pixels(msst, oracle):
@@ -297,9 +328,9 @@ def test_full_size_c4_learned_sampled_pixels(msst, oracle):
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, pixels=pix, **opts)
     sub = {k: g[k][pix] for k in ("sum", "comp", "events", "steps")}
-    frac, _ = compare_paths(sub, o, rel=2e-3)
+    frac, _ = compare_paths(sub, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e} of {pix.size} paths with learned steps")
-    assert frac < 0.05
+    assert frac < 1e-2
 
 
 @pytest.mark.parametrize("method,precision", [(PLAIN, 1), (ST, 1), (ST, 2)])
@@ -328,9 +359,9 @@ def test_full_size_c5_sampled_pixels(msst, oracle, method, precision):
         precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8)
     o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med, pixels=pix, **kw, **opts)
     sub = {k: g[k][pix] for k in ("sum", "comp", "events", "steps")}
-    frac, _ = compare_paths(sub, o, rel=2e-3)
+    frac, _ = compare_paths(sub, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; steps {o['steps'].sum()}, events {o['events'].sum()}")
-    assert frac < 0.05
+    assert frac < 1.4e-2
 
 
 def test_image_stats_fp64(msst):
@@ -388,10 +419,11 @@ def test_c5_path_by_path(msst, oracle, method, sampler):
     o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med,
                       method=oracle.METHOD_PLAIN_NEE if method == PLAIN else oracle.METHOD_ST,
                       sampler=oracle.SAMPLER_EXACT_WALK, spp=1, seed=21)
-    frac, _ = compare_paths(g, o)
+    # 64 spheres: measured 2.5e-3 / 3.8e-3 of the paths beyond 1e-4, none beyond 1e-3
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; lit {(o['sum'] > 0).mean():.2f}, events {o['events'].sum()}, steps {o['steps'].sum()}")
     assert (o["sum"] > 0).mean() > 0.1
-    assert frac < 1e-2
+    assert frac < 1.3e-3
     if method == ST:
         assert o["steps"].sum() > 50
 
@@ -412,10 +444,10 @@ def test_c5_learned_path_by_path(msst, oracle, precision):
     o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med, method=oracle.METHOD_ST,
                       sampler=oracle.SAMPLER_CVAE, precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8,
                       models=models, spp=1, seed=22)
-    frac, _ = compare_paths(g, o, rel=2e-3)
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; steps {o['steps'].sum()}")
     assert o["steps"].sum() > 50
-    assert frac < 0.05
+    assert frac < 2e-3
 
 
 @pytest.mark.parametrize("n,res", [(5, 0), (65, 0), (200, 64), (256, 0)])
@@ -436,10 +468,12 @@ def test_many_primitives_path_by_path(msst, oracle, n, res, method, sampler):
     o = oracle.render(scene_o, cam, light, med,
                       method=oracle.METHOD_PLAIN_NEE if method == PLAIN else oracle.METHOD_ST,
                       sampler=oracle.SAMPLER_EXACT_WALK, spp=1, seed=23, tau_min=4.0)
-    frac, _ = compare_paths(g, o)
+    # up to 256 spheres: up to 1.3e-2 of the paths beyond 1e-4 (long shadow
+    # segments through many overlapping spheres), 1.7e-3 beyond 1e-3
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; lit {(o['sum'] > 0).mean():.2f}, events {o['events'].sum()}, steps {o['steps'].sum()}")
     assert (o["sum"] > 0).mean() > 0.05
-    assert frac < 1e-2
+    assert frac < 4e-3
     if method == ST:
         assert o["steps"].sum() > 20
 
@@ -461,6 +495,6 @@ def test_rgb_media_channel_by_channel(msst, oracle):
         o = oracle.render(oracle.Scene(prims), cam, light, media[c], method=oracle.METHOD_ST,
                           sampler=oracle.SAMPLER_CVAE, precision=oracle.PREC_BF16, models=models, spp=1,
                           seed=31 + c, tau_min=2.0)
-        frac, _ = compare_paths(g, o, rel=2e-3)
+        frac, _ = compare_paths(g, o, rel=LEARNED_REL)
         print(f"channel {c}: diverged {frac:.2e}, mean {o['sum'].mean():.4e}")
-        assert frac < 0.03
+        assert frac < 3.5e-3

@@ -12,6 +12,7 @@ from conftest import announce
 pytestmark = pytest.mark.gpu
 
 BF16_U = 2.0**-8
+GRAD_REL, LOSS_REL = 5e-3, 2e-3  # as for the standard shapes (test_gpu_cvae)
 
 CASES = {f"final-{m}": W.TABLE1_SHAPES[m] for m in range(3)}
 CASES["D1-length-W4-L6"] = W.table1_shape(0, 1, 4, 6)
@@ -67,9 +68,9 @@ def test_init_and_gradient_parity(msst, oracle, name):
     rel = np.linalg.norm(g - g64) / np.linalg.norm(g64)
     cos = g @ g64 / (np.linalg.norm(g) * np.linalg.norm(g64))
     print(f"{name}: grad rel-L2 {rel:.3e}, cosine {cos:.6f}")
-    assert rel < 10 * BF16_U and cos > 0.999
+    assert rel < GRAD_REL and cos > 0.999
     assert np.all(g[~real_mask(shape)] == 0)
-    np.testing.assert_allclose(loss.cpu().numpy(), (l64, kl64, nll64), rtol=10 * BF16_U, atol=1e-3)
+    np.testing.assert_allclose(loss.cpu().numpy(), (l64, kl64, nll64), rtol=LOSS_REL, atol=1e-3)
 
 
 def test_training_keeps_missing_units_at_zero(msst):
@@ -123,7 +124,7 @@ def test_sphere_tracing_with_table1_decoders(msst, oracle, arch):
     """Path-by-path render parity (spp = 1) with Table 1 decoders: the latent
     size and depth change the number of normals each decoder draws."""
     announce(f"table1 render parity {arch}")
-    from test_gpu_render import c4_inputs, compare_paths, gpu_render
+    from test_gpu_render import LEARNED_REL, c4_inputs, compare_paths, gpu_render
     shapes = list(W.TABLE1_SHAPES) if arch == "final" else [W.table1_shape(0, 3, 8, 6), W.table1_shape(1, 1, 16, 5),
                                                             W.table1_shape(2, 3, 12, 5)]
     prims, cam, light, med = c4_inputs(20.0, 40)
@@ -139,7 +140,8 @@ def test_sphere_tracing_with_table1_decoders(msst, oracle, arch):
                    nee_samples=2, flags=1)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, spp=1, seed=25, nee_samples=2, flags=1)
-    frac, _ = compare_paths(g, o, rel=2e-3)
+    frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"{arch}: diverged {frac:.2e}; sphere steps {o['steps'].sum()}")
     assert o["steps"].sum() > 100
-    assert frac < 0.03
+    # measured: one of 1600 paths (a bfloat16 flip in a four-layer decoder)
+    assert frac < 2e-3
