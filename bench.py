@@ -20,15 +20,34 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU work per unit in 32-bit lane-operation slots, counted on the kernels
-# themselves: SQ_THREAD_CYCLES_VALU (active lanes x VALU cycles) of rocprofv3
-# runs, fitted per path / plain event / learned step over the four densities
-# (the counter summary and the fit are in profiles/).  Idle (masked) lanes are
-# not counted, so achieved / peak is the fraction of the chip's lane slots
-# that do the algorithm's work.
-OPS_PER_PATH = 400.0         # camera ray, primary intervals, banking the result
-OPS_PER_EVENT = 470.0        # one plain collision: Philox block, flight, NEE shadow ray, roulette, HG, new ray
-OPS_PER_STEP = 5300.0        # one learned step, two representative events (three decoders, 22+ normals, NEE x2)
+# Algorithmic VALU work per unit in 32-bit lane-operation slots (one per
+# full-rate lane operation, four per quarter-rate one: transcendentals and
+# 32-bit integer multiplies), from the operation count of the method:
+#   plain collision: Philox block (10 rounds, 20 quarter-rate multiplies) 100,
+#     uniforms 8, flight log 5, HG sample with its reciprocal 16, azimuth
+#     sin/cos 8, orthonormal frame 16, rotation with rsq 22, position update
+#     and exit test 13 (= 188, the walk event) plus the shadow ray to the
+#     light (two primitive intervals ~100, exp and HG phase ~30, weight and
+#     accumulation ~30) and the new ray's intervals: ~350;
+#   learned step with one representative event: 7 Philox blocks ~700, 22
+#     normals by Box-Muller ~240, 96 Softplus (two quarter-rate
+#     transcendentals each) ~1150, standardisation, posterior noise and
+#     de-standardisation ~250, exit frames ~120, shadow ray ~140: ~2600; each
+#     further representative event adds its first-event block and an
+#     EventGen decode (4 Philox blocks ~400, 10 normals ~110, 32 Softplus
+#     ~380) and a shadow ray ~140: ~1000;
+#   path: camera ray (one Philox block, pinhole direction) ~120, primary
+#     intervals ~65, banking the sample ~15: ~200.
+# achieved / peak is the fraction of the chip's lane slots the method's work
+# would fill; the kernels' own counted slots (SQ_THREAD_CYCLES_VALU fit, see
+# profiles/) are reported beside it.
+ALG_PER_PATH = 200.0
+ALG_PER_EVENT = 350.0
+ALG_PER_STEP_ONE_EVENT = 2600.0
+ALG_PER_EXTRA_EVENT = 1000.0
+OPS_PER_PATH = 400.0         # counted: camera ray, primary intervals, banking the result
+OPS_PER_EVENT = 470.0        # counted: one plain collision
+OPS_PER_STEP = 5300.0        # counted: one learned step with two representative events
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
 OPS_PER_WALK_EVENT = 186.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
@@ -87,6 +106,11 @@ def parse():
     ap.add_argument("--c5-width", type=int, default=1024)
     ap.add_argument("--c5-spp", type=int, default=1024)
     ap.add_argument("--c5-ref-spp", type=int, default=4096)
+    ap.add_argument("--no-oracle-anchor", action="store_true",
+                    help="skip the FP64 oracle's plain renders of every 16th pixel (z-test and RMSE anchor)")
+    ap.add_argument("--oracle-spp", type=int, default=4096)
+    ap.add_argument("--c5-oracle-spp", type=int, default=1024)
+    ap.add_argument("--no-paper-step", action="store_true", help="skip the paper's learned step as printed")
     ap.add_argument("--diagnostics", action="store_true",
                     help="also render sphere tracing with exact in-sphere walks and a tau_min sweep (untimed)")
     return ap.parse_args()
@@ -102,7 +126,7 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, 
 
 
 def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), shapes=None,
-                   walk_kw=None, timing=None):
+                   walk_kw=None, timing=None, all_rows=False):
     """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
 
     The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
@@ -122,7 +146,8 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
         timing["walk"] = dict(photons=n_samples, events=int(c[0]), seconds=e0.elapsed_time(e1) / 1e3)
     # the three models train at once, one stream each: a step is latency
     # bound (about one wave per CU), so their launches overlap on the GPU
-    setups = [prepare_model(M, torch, walk, model, model if shapes is None else shapes[model], batch, seed)
+    setups = [prepare_model(M, torch, walk, model, model if shapes is None else shapes[model], batch, seed,
+                            all_rows=all_rows)
               for model in range(3)]
     streams = [torch.cuda.Stream() for _ in setups]
     cur = torch.cuda.current_stream()
@@ -148,17 +173,24 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
             packs[p].append(pk[p])
         losses.append(loss)
     torch.cuda.synchronize()
+    if timing is not None:
+        # the trained FP32 masters and standardisation constants, for the oracle
+        timing["models"] = [dict(shape=dict(su["shape"]) if isinstance(su["shape"], dict) else
+                                 dict(M.STANDARD_SHAPES[su["shape"]]),
+                                 params=su["master"].double().cpu().numpy(), stats=su["stats"].cpu().numpy())
+                            for su in setups]
     return packs, losses, time.time() - t0
 
 
-def prepare_model(M, torch, walk, model, shape, batch=4096, seed=0):
+def prepare_model(M, torch, walk, model, shape, batch=4096, seed=0, all_rows=False):
     """Features, FP64 standardisation, initial weights and AdamW state of one
     CVAE on the walk records."""
     n_samples = walk["n_scatter"].numel()
     p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
     # PathGen learns N >= 2 records and EventGen k >= 2 records: the
-    # single-event cases are sampled exactly by the renderer
-    rows = None if model == 0 else M.select_rows(walk, 2, 2 if model == 2 else 0)
+    # single-event cases are sampled exactly by the renderer (all_rows: every
+    # record, for the paper's step as printed)
+    rows = None if model == 0 or all_rows else M.select_rows(walk, 2, 2 if model == 2 else 0)
     n_rows = n_samples if rows is None else rows.numel()
     cond = torch.empty((n_rows, p_in), dtype=torch.float32, device="cuda")
     target = torch.empty((n_rows, p_out), dtype=torch.float32, device="cuda")
@@ -321,6 +353,68 @@ def image_moments(img, spp):
     return mean, var.clamp_min(0)
 
 
+def oracle_threads():
+    """Host threads for the oracle: the process's CPU share (OMP_NUM_THREADS
+    where set, as on the GPU hosts), else the visible cores, at most 64."""
+    n = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, min(n if n > 0 else (os.cpu_count() or 1), 64))
+
+
+def cpu_model_name():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def subset_pixels(width, height, stride=16):
+    """Every stride-th pixel in x and y (the centre of each stride x stride block)."""
+    import numpy as np
+    return np.array([y * width + x for y in range(stride // 2, height, stride)
+                     for x in range(stride // 2, width, stride)], np.int32)
+
+
+def oracle_subset(oracle, scene, cam, light, med, spp, seed):
+    """FP64 plain path tracing with next-event estimation on every 16th
+    pixel: per-pixel mean and one-sample variance."""
+    import numpy as np
+    pix = subset_pixels(cam["width"], cam["height"])
+    t0 = time.time()
+    o = oracle.render(scene, cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=spp, seed=seed, pixels=pix,
+                      n_threads=oracle_threads())
+    mean = o["sum"] / spp
+    return dict(pix=pix, mean=mean, var=np.maximum(o["sumsq"] / spp - mean * mean, 0.0), spp=spp,
+                seconds=time.time() - t0)
+
+
+def anchor_stats(sub, ref_mean, ref_var, ref_spp, images):
+    """The GPU reference against the oracle subset: per-pixel z = (R - O) /
+    sqrt(var R / n_R + var O / n_O) over pixels with any light (RMS ~1 and a
+    global z of the summed difference within a few units when both estimate
+    the same image), and each image's RMSE against the oracle with the
+    oracle's own noise removed.  images: name -> per-pixel means (numpy)."""
+    import numpy as np
+    p = sub["pix"]
+    ov = sub["var"] / sub["spp"]
+    rv = ref_var[p] / ref_spp
+    d = ref_mean[p] - sub["mean"]
+    v = rv + ov
+    lit = v > 0
+    z = d[lit] / np.sqrt(v[lit])
+    out = dict(pixels=int(p.size), lit_pixels=int(lit.sum()), oracle_spp=sub["spp"], oracle_seconds=sub["seconds"],
+               z_rms=float(np.sqrt(np.mean(z * z))), z_mean=float(z.mean()), z_max=float(np.abs(z).max()),
+               z_global=float(d[lit].sum() / np.sqrt(v[lit].sum())),
+               reference_rmse_vs_oracle=float(np.sqrt(max(np.mean(d * d) - ov.mean(), 1e-30))))
+    for name, m in images.items():
+        e2 = float(np.mean((m[p] - sub["mean"]) ** 2) - ov.mean())
+        out[f"rmse_{name}_vs_oracle"] = float(np.sqrt(max(e2, 1e-30)))
+    return out
+
+
 def c5_section(M, W, torch, packs, args, timed):
     """64-sphere scene over a 256^3 FP16 distance grid, 1024^2 x 1024 spp,
     sigma_t = 100: sphere tracing with FP8 and BF16 decoders against the plain
@@ -334,6 +428,7 @@ def c5_section(M, W, torch, packs, args, timed):
     rend = M.Renderer(prims, cam, light, grid=grid)
     img, t_ref = timed(lambda: rend.render(med, method=1, spp=args.c5_ref_spp, seed=77), warm=False)
     ref, ref_var = image_moments(img, args.c5_ref_spp)
+    means = {}
     ref_noise2 = float(ref_var.mean()) / args.c5_ref_spp
     out = {"workload": f"64 spheres (seed 0) over a {res}^3 FP16 distance grid, {width}x{width}, {spp} spp, "
                        f"sigma_t=100, g=0.8, albedo=0.995, point light + NEE",
@@ -347,6 +442,7 @@ def c5_section(M, W, torch, packs, args, timed):
         img, t = timed(lambda: rend.render(med, spp=spp, seed=6, **opt))
         c = img["counters"].cpu().numpy()
         mean, var = image_moments(img, spp)
+        means[name] = mean.cpu().numpy()
         err2 = float(((mean - ref) ** 2).mean())
         rm = float(np.sqrt(max(err2 - ref_noise2, 1e-30)))
         out[name] = dict(ms=t * 1e3, paths_per_s=float(c[0] / t), events_per_path=float(c[1] / c[0]),
@@ -360,40 +456,61 @@ def c5_section(M, W, torch, packs, args, timed):
         r = out[name]
         s_star = pt["mean_var"] / max(r["rmse"] ** 2, 1e-30)
         r["speedup_matched_rmse"] = s_star * width * width / pt["paths_per_s"] / (r["ms"] / 1e3)
+    if not args.no_oracle_anchor:
+        import oracle
+        log(f"C5 oracle anchor: every 16th pixel at {args.c5_oracle_spp} spp")
+        sub = oracle_subset(oracle, oracle.Scene(prims), cam, light, med, args.c5_oracle_spp, 78)
+        out["oracle_anchor"] = anchor_stats(sub, ref.cpu().numpy(), ref_var.cpu().numpy(), args.c5_ref_spp, means)
+        a = out["oracle_anchor"]
+        for name in ("st_bf16", "st_fp8"):
+            r = out[name]
+            r["speedup_matched_rmse_oracle"] = (pt["mean_var"] / a[f"rmse_{name}_vs_oracle"] ** 2 * width * width
+                                                / pt["paths_per_s"] / (r["ms"] / 1e3))
+        log(f"C5 oracle anchor: z rms {a['z_rms']:.2f}, global z {a['z_global']:+.2f}; RMSE vs oracle "
+            + ", ".join(f"{n} {a[f'rmse_{n}_vs_oracle']:.3e}" for n in means))
     return out
 
 
-def cpu_baseline(oracle, W, args):
-    """Oracle sphere tracer with the CVAE step (FP64) on random pixel subsets
-    of the sigma_t = 40 image, same estimator options, all host cores; runs
-    for about args.cpu_seconds."""
+def cpu_baseline(oracle, W, args, models):
+    """The oracle's sphere tracer with the CVAE step (FP64 decoders on the same
+    trained FP32 masters and standardisation constants the GPU renders) on
+    random pixel subsets of the four timed images, same estimator options:
+    all host threads of the process's CPU share for about args.cpu_seconds,
+    then one thread for a quarter of that."""
     import numpy as np
-    cores = os.cpu_count() or 1
+    threads = oracle_threads()
     prims = W.scene_c4()
     cam = W.camera_c4(args.width, args.width)
     light = W.light_c4()
-    med = W.medium_c4(40.0)
-    models = []
-    for m in range(3):
-        shape = W.SHAPE_LIST[m]
-        models.append(dict(shape=shape, params=oracle.cvae_init(shape, 900 + m), stats=W.render_test_stats(m)))
-    rng = np.random.default_rng(0)
-    npx, spp = 256, 4
-    total_paths, t_total, it = 0, 0.0, 0
     scene = oracle.Scene(prims)
-    while t_total < args.cpu_seconds:
-        pix = rng.choice(args.width * args.width, npx, replace=False).astype(np.int32)
-        t0 = time.time()
-        oracle.render(scene, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
-                      models=models, tau_min=args.tau_min, spp=spp, seed=it, pixels=pix, n_threads=cores,
-                      nee_samples=args.nee_samples, flags=args.nee_flags)
-        t_total += time.time() - t0
-        total_paths += npx * spp
-        npx = min(2 * npx, 1 << 16)
-        it += 1
-    return {"value": total_paths / t_total, "unit": "paths/s", "cores": cores, "kind": "oracle",
-            "sample": f"{total_paths} paths (random pixel subsets x {spp} spp) of the sigma_t = 40 image, "
-                      f"ST + CVAE decoders in FP64 with oracle-initialised weights, {t_total:.1f} s"}
+    rng = np.random.default_rng(0)
+    spp = 4
+
+    def run(n_threads, seconds):
+        paths, t_total, it, npx = 0, 0.0, 0, 64
+        while t_total < seconds:
+            for s in W.C4_SIGMAS:
+                pix = np.sort(rng.choice(args.width * args.width, npx, replace=False)).astype(np.int32)
+                t0 = time.time()
+                oracle.render(scene, cam, light, W.medium_c4(s), method=oracle.METHOD_ST,
+                              sampler=oracle.SAMPLER_CVAE, models=models, tau_min=args.tau_min, spp=spp,
+                              seed=50 + it, pixels=pix, n_threads=n_threads, nee_samples=args.nee_samples,
+                              flags=args.nee_flags)
+                t_total += time.time() - t0
+                paths += npx * spp
+            npx = min(2 * npx, 1 << 14)
+            it += 1
+        return paths, t_total
+
+    paths, t_all = run(threads, args.cpu_seconds)
+    paths1, t_one = run(1, args.cpu_seconds / 4)
+    return {"value": paths / t_all, "unit": "paths/s", "cores": threads, "kind": "oracle",
+            "single_core_paths_per_s": paths1 / t_one, "cpu_model": cpu_model_name(),
+            "sample": f"{paths} paths (random pixel subsets x {spp} spp of each of the four sigma_t images, "
+                      f"sigma_t in {list(W.C4_SIGMAS)}) of the timed workload: ST + CVAE decoders in FP64 on the "
+                      f"trained FP32 masters and standardisation constants the GPU renders, tau_min "
+                      f"{args.tau_min}, {args.nee_samples} representative events; {t_all:.1f} s on {threads} "
+                      f"threads; single thread {paths1} paths in {t_one:.1f} s"}
 
 
 def main():
@@ -450,15 +567,17 @@ def main():
     packed = packs[1]
 
     # plain reference (debiased by its own noise) and plain timing per density
-    ref, ref_noise2, pt = {}, {}, {}
+    ref, ref_noise2, pt, ref_var_np, pt_mean_np = {}, {}, {}, {}, {}
     for s in sigmas:
         med = W.medium_c4(s)
         img = rend.render(med, method=1, spp=args.ref_spp, seed=1000, **kw)
         mean, var = image_moments(img, args.ref_spp)
         ref[s] = mean.float()
+        ref_var_np[s] = var.cpu().numpy()
         ref_noise2[s] = float(var.mean()) / args.ref_spp
         img, t = timed(lambda: rend.render(med, method=1, spp=spp, seed=2000, **kw))
-        _, var = image_moments(img, spp)
+        pm_, var = image_moments(img, spp)
+        pt_mean_np[s] = pm_.cpu().numpy()
         c = img["counters"].cpu().numpy()
         pt[s] = dict(time=t, paths=int(c[0]), events=int(c[1]), var=float(var.mean()), rmse=rmse(img, s))
         log(f"PT sigma_t={s}: {t * 1e3:.1f} ms, {c[0] / t:.3e} paths/s, events/path {c[1] / c[0]:.2f}")
@@ -531,6 +650,27 @@ def main():
                f"{confirm['ms']:.1f} ms ({confirm['speedup']:.2f})"))
         tot_st += t_sigma[s]
         tot_pt += t_pt_match
+    # FP64 oracle anchor: the oracle's plain tracer on every 16th pixel of each
+    # image; z-test of the GPU reference and RMSE of both tracers against it
+    if not args.no_oracle_anchor:
+        import oracle
+        o_scene = oracle.Scene(W.scene_c4())
+        tot_st_o, tot_pt_o = 0.0, 0.0
+        for i, s in enumerate(sigmas):
+            sub = oracle_subset(oracle, o_scene, W.camera_c4(width, width), W.light_c4(), W.medium_c4(s),
+                                args.oracle_spp, 11000 + i)
+            st_mean = image_moments(last[s], spp)[0].cpu().numpy()
+            a = anchor_stats(sub, ref[s].double().cpu().numpy(), ref_var_np[s], args.ref_spp,
+                             {"st": st_mean, "pt": pt_mean_np[s]})
+            t_pt_o = pt[s]["var"] / a["rmse_st_vs_oracle"] ** 2 * npix / (pt[s]["paths"] / pt[s]["time"])
+            a["speedup_matched_rmse_oracle"] = t_pt_o / t_sigma[s]
+            details[str(s)]["oracle_anchor"] = a
+            tot_st_o += t_sigma[s]
+            tot_pt_o += t_pt_o
+            log(f"oracle anchor sigma_t={s}: {a['lit_pixels']} lit of {a['pixels']} pixels at {args.oracle_spp} spp "
+                f"({a['oracle_seconds']:.1f} s): z rms {a['z_rms']:.2f}, global z {a['z_global']:+.2f}; RMSE vs oracle "
+                f"ST {a['rmse_st_vs_oracle']:.3e}, PT {a['rmse_pt_vs_oracle']:.3e}, speed-up "
+                f"{a['speedup_matched_rmse_oracle']:.2f}")
     pt_rate = sum(pt[s]["paths"] for s in sigmas) / sum(pt[s]["time"] for s in sigmas)
     # share of camera paths that hit the object: an opaque, black medium (albedo
     # below 2^-24: the roulette ends every path at its first collision)
@@ -556,6 +696,28 @@ def main():
                                   rmse_st_default_arch=details[str(s)]["rmse_st"])
             log(f"Table 1 sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default {details[str(s)]['rmse_st']:.3e}), "
                 f"speed-up {t_pt_match / t:.2f}")
+
+    # the paper's learned step as printed: PathGen and EventGen for every case
+    # (no exact single-event parts), models trained on every walk record
+    paper = None
+    if not args.no_paper_step:
+        log("the paper's learned step as printed")
+        pkp, _, tp = train_and_pack(M, torch, args.train_samples, args.train_steps, all_rows=True)
+        paper = {"flags": args.nee_flags | M._abi.RENDER_STEP_PAPER, "train_seconds": tp}
+        tot_p, tot_pm = 0.0, 0.0
+        for s in sigmas:
+            img, t = timed(lambda: st_render(s, 6201, packed=pkp[1], flags=paper["flags"]))
+            c = img["counters"].cpu().numpy()
+            r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
+            t_m = pt[s]["var"] / r_st**2 * npix / (pt[s]["paths"] / pt[s]["time"])
+            paper[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, steps_per_path=float(c[2] / c[0]),
+                                 mean_st=float(image_moments(img, spp)[0].mean()),
+                                 speedup_matched_rmse=t_m / t, rmse_st_exact_single_events=details[str(s)]["rmse_st"])
+            tot_p += t
+            tot_pm += t_m
+            log(f"paper step sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (exact single events "
+                f"{details[str(s)]['rmse_st']:.3e}), speed-up {t_m / t:.2f}")
+        paper["speedup_matched_rmse"] = tot_pm / tot_p
 
     # (sigma_t r, g)-weighted training data: half the walks from the region
     # the renders use (g near 0.8, sigma_t r above tau_min)
@@ -763,12 +925,20 @@ def main():
             log(f"diag sigma_t={s}: " + ", ".join(f"{k}: {v['rmse']:.3e} / {v['time_ms']:.1f} ms"
                                                   for k, v in diag.items() if k.endswith(f"_{s}")))
 
-    # roofline of the render kernel from the algorithmic VALU work of the timed step
+    # roofline of the render kernel from the algorithmic VALU work of the timed
+    # step (the method's operation count per path, collision and learned
+    # step), and beside it the kernel's own counted lane slots
+    alg_step = ALG_PER_STEP_ONE_EVENT + (args.nee_samples - 1) * ALG_PER_EXTRA_EVENT
+    alg = counters[0] * ALG_PER_PATH + counters[1] * ALG_PER_EVENT + counters[2] * alg_step
+    achieved = alg / (ms_per_step / 1e3)
     ops = counters[0] * OPS_PER_PATH + counters[1] * OPS_PER_EVENT + counters[2] * OPS_PER_STEP
-    achieved = ops / (ms_per_step / 1e3)
+    counted = ops / (ms_per_step / 1e3)
     traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_LANEOPS / 1e12,
                 "unit": "T lane-op/s", "frac": achieved / PEAK_VALU_LANEOPS, "traffic": traffic,
+                "work_per_unit": {"path": ALG_PER_PATH, "collision": ALG_PER_EVENT, "learned_step": alg_step},
+                "units": {"paths": int(counters[0]), "collisions": int(counters[1]), "learned_steps": int(counters[2])},
+                "counted_achieved": counted / 1e12, "counted_frac": counted / PEAK_VALU_LANEOPS,
                 "mfma_tflops": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / 1e12,
                 "mfma_frac": counters[2] * MFMA_FLOP_PER_STEP / (ms_per_step / 1e3) / PEAK_MFMA_BF16}
 
@@ -781,7 +951,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         log("timing the CPU oracle")
-        cpu = cpu_baseline(oracle, W, args)
+        cpu = cpu_baseline(oracle, W, args, tim["models"])
 
     result = {
         "metric": "sphere-traced paths/s (CVAE) vs plain random-walk paths/s at matched RMSE",
@@ -798,6 +968,7 @@ def main():
         "object_hitting_paths_per_s": value * hit_fraction,
         "plain_object_hitting_paths_per_s": pt_rate * hit_fraction,
         "speedup_matched_rmse": tot_pt / tot_st,
+        "speedup_matched_rmse_oracle": (tot_pt_o / tot_st_o) if not args.no_oracle_anchor else None,
         "per_sigma": details,
         "train": {"seconds": t_train, "loss_first_last": losses, "steps_per_model": args.train_steps,
                   "step_us_three_models_concurrent": tim.get("train_step_us_three_models"),
@@ -809,6 +980,7 @@ def main():
         "cpu_baseline": cpu,
         "c5": c5,
         "table1": table1,
+        "paper_step": paper,
         "table1_sweep": sweep,
         "cvae_sample": sample,
         "walk_full": None if walk_full is None else dict(

@@ -343,6 +343,9 @@ typedef struct {
 typedef struct {
     int32_t method, sampler;
     const void* packed[3];   /* LengthGen, PathGen, EventGen (ST with CVAE) */
+    /* learned steps where sigma_t r >= tau_min (> 0); r capped at st_max / sigma_t.
+     * The decoders are trained on sigma_t r in [0.1, 200] (the training walk's
+     * st_range): tau_min below 0.1 or st_max above 200 asks them to extrapolate. */
     float tau_min, st_max;
     int32_t spp;
     int32_t chunk;           /* samples per work unit; 0 = max(2, ceil(pixels spp / 2^24)) */

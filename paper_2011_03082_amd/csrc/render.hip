@@ -1282,7 +1282,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     MS_REQUIRE(desc->chunk >= 0 && desc->blocks_per_cu >= 0 && desc->blocks_per_cu <= 64 && desc->cvae_batch_min >= 0 &&
                    desc->cvae_batch_min <= 64,
                "sphere_trace_render: invalid launch parameters");
-    MS_REQUIRE(desc->tau_min >= 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min >= 0, st_max > 0");
+    // tau_min > 0 keeps every learned step off radius 0 (no log(0) condition)
+    MS_REQUIRE(desc->tau_min > 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min > 0, st_max > 0");
     MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
     MS_REQUIRE(desc->restart_min >= 0 && desc->restart_min <= 64, "sphere_trace_render: restart_min must be in [0, 64]");
     MS_REQUIRE(desc->max_wait >= 0, "sphere_trace_render: max_wait must be >= 0");

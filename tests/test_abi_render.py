@@ -52,14 +52,14 @@ def desc_with(M, **kw):
 
 
 @pytest.mark.parametrize("case", [
-    "method", "sampler", "spp0", "spp_big", "nee17", "flags", "tau", "st_max", "restart", "batch", "bpc",
+    "method", "sampler", "spp0", "spp_big", "nee17", "flags", "tau", "tau0", "st_max", "restart", "batch", "bpc",
     "cvae_no_models",
 ])
 def test_render_rejects_invalid_descriptor(M, case):
     d = {
         "method": dict(method=7), "sampler": dict(method=2, sampler=4), "spp0": dict(spp=0),
         "spp_big": dict(spp=(1 << 24) + 1), "nee17": dict(nee_samples=17), "flags": dict(flags=8),
-        "tau": dict(tau_min=-1.0), "st_max": dict(st_max=0.0), "restart": dict(restart_min=65),
+        "tau": dict(tau_min=-1.0), "tau0": dict(tau_min=0.0), "st_max": dict(st_max=0.0), "restart": dict(restart_min=65),
         "batch": dict(cvae_batch_min=65), "bpc": dict(blocks_per_cu=65), "cvae_no_models": dict(method=2, sampler=0),
     }[case]
     assert status(M, desc=desc_with(M, **d)) == M._abi.MS_ERR_INVALID_ARGUMENT
