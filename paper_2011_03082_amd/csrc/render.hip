@@ -25,9 +25,10 @@ namespace msst {
 
 constexpr int kRenderWaves = 4;
 
-// Lane states: out of samples (IDLE), tracing (FLY), waiting for a learned
-// step (WAIT), path finished and not yet banked (END), no work left (DONE).
-enum : int { S_IDLE = 0, S_FLY = 2, S_WAIT = 3, S_DONE = 4, S_END = 5 };
+// Lane states: no path in flight (NEED: start a sample, take a work unit,
+// or wait for the parked path), tracing (FLY), waiting for a learned step
+// (WAIT), path finished and not yet banked (END), no work left (DONE).
+enum : int { S_NEED = 0, S_FLY = 2, S_WAIT = 3, S_DONE = 4, S_END = 5 };
 
 // Result of one work unit (one pixel, `chunk` consecutive samples): the
 // compensated radiance sum folded to binary32, the sum of squares and the
@@ -56,7 +57,8 @@ struct RenderArgs {
     const PackedModel* pm[3];
     float tau_min, st_max;
     int spp, chunk, n_chunks;
-    int64_t n_units;
+    int64_t n_units;                      // below 2^32
+    double inv_n_chunks, inv_width;       // reciprocals for the unit -> (pixel, chunk) split
     uint64_t seed, sample_offset;
     uint32_t max_events;
     int batch_min;
@@ -78,7 +80,7 @@ struct Prims {
 
 struct RenderLds {
     float x[64][kTile];  // decoder input rows of the compacted lanes; outputs overwrite them
-    float eps[64][8];    // decoder posterior noise of each row
+    float eps[64][6];    // decoder posterior noise of each row (at most 6 outputs)
     uint4 rid[64];       // Philox stream (id_lo, id_hi) and first block of each row's normals
 };
 
@@ -336,6 +338,7 @@ struct GeoMany {
     }
     __device__ __forceinline__ float flight_bound(const RenderArgs& A, V3 p) const { return radius(A, p); }
     __device__ __forceinline__ float max_radius() const { return INFINITY; }
+
     // Primitives the shadow segments of this wave can meet.  Called by every
     // lane of the wave (converged); lanes with `active` will trace a segment
     // from x to the light.  All segments lie in the union of balls around the
@@ -496,6 +499,7 @@ struct GeoMesh {
     __device__ __forceinline__ float radius(const RenderArgs& A, V3 p) const { return grid_radius(A, p); }
     __device__ __forceinline__ float max_radius() const { return INFINITY; }
     __device__ __forceinline__ float flight_bound(const RenderArgs&, V3) const { return 0.0f; }
+
     __device__ __forceinline__ float light(const RenderArgs& A, V3 x, V3 d) const {
         V3 wl = v3(A.light[0] - x.x, A.light[1] - x.y, A.light[2] - x.z);
         const float dist2 = dot(wl, wl);
@@ -584,6 +588,18 @@ __device__ __forceinline__ void stage_row(const PackedModel* pm, RenderLds& L, i
     c0 += (uint32_t)((lat + PO + 3) >> 2);
 }
 
+// floor(n / d) for n < 2^32: the double-precision quotient through the
+// rounded reciprocal is within one of it (relative error 2^-52), and one
+// integer check makes it exact -- a few instructions instead of the long
+// integer division sequence.
+__device__ __forceinline__ uint32_t udiv_exact(uint32_t n, uint32_t d, double inv_d) {
+    uint32_t q = (uint32_t)((double)n * inv_d);
+    const int64_t r = (int64_t)n - (int64_t)q * (int64_t)d;
+    if (r < 0) --q;
+    else if (r >= (int64_t)d) ++q;
+    return q;
+}
+
 // q / nb for q < 2^15 and nb in 1 .. 4.
 __device__ __forceinline__ int div_small(int q, int nb) {
     return nb == 1 ? q : nb == 2 ? q >> 1 : nb == 4 ? q >> 2 : (q * 0xAAAB) >> 17;
@@ -620,12 +636,9 @@ __device__ __forceinline__ void stage_normals(const RenderArgs& A, const PackedM
     }
 }
 
-// Runs one decoder over the first n compacted rows (16-path MFMA tiles) and
-// returns the de-standardised sample y[0..PO) of slot `slot` for lanes that
-// staged an input.
-template <int PO>
-__device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
-                                            float* y) {
+// Runs one decoder over the first n compacted rows (16-path MFMA tiles);
+// each row's (mean, log variance) outputs overwrite its inputs.
+__device__ __forceinline__ void decode_tiles(const PackedModel* pm, RenderLds& L, int n) {
     wave_sync();
     const int n_tiles = (n + 15) >> 4;
     if (pm->n_linear == kDecLayers) {
@@ -646,51 +659,98 @@ __device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L,
         }
     }
     wave_sync();
-    if (mine) {
+}
+
+// The de-standardised sample y[0..PO) of decoded row `slot`:
+// mu + exp(log variance / 2) eps.
+template <int PO>
+__device__ __forceinline__ void read_row(const PackedModel* pm, const RenderLds& L, int slot, float* y) {
 #pragma unroll
-        for (int k = 0; k < PO; ++k) {
-            const float mu = L.x[slot][k];
-            const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.x[slot][PO + k]));
-            const float ys = __builtin_fmaf(fast_exp(0.5f * lv), L.eps[slot][k], mu);
-            y[k] = __builtin_fmaf(ys, pm->std_y[k], pm->mean_y[k]);
-        }
+    for (int k = 0; k < PO; ++k) {
+        const float mu = L.x[slot][k];
+        const float lv = __builtin_fminf(8.0f, __builtin_fmaxf(-12.0f, L.x[slot][PO + k]));
+        const float ys = __builtin_fmaf(fast_exp(0.5f * lv), L.eps[slot][k], mu);
+        y[k] = __builtin_fmaf(ys, pm->std_y[k], pm->mean_y[k]);
     }
+}
+
+// decode_tiles, then the sample of row `slot` for lanes that staged one.
+template <int PO>
+__device__ __forceinline__ void decode_rows(const PackedModel* pm, RenderLds& L, bool mine, int slot, int n,
+                                            float* y) {
+    decode_tiles(pm, L, n);
+    if (mine) read_row<PO>(pm, L, slot, y);
     wave_sync();
 }
 
+// Exclusive prefix sum over the wave of small per-lane counts (< 2^5) and
+// their total.
+__device__ __forceinline__ int wave_prefix_small(int cnt, int& total) {
+    int pre = 0;
+    total = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const uint64_t m = ballot((cnt >> b) & 1);
+        pre += rank_in(m) << b;
+        total += __popcll(m) << b;
+    }
+    return pre;
+}
+
 // The persistent render loop of one kernel instance (MODE fixes the
-// method); the whole body of render_kernel below.
+// method); the whole body of render_kernel below.  A lane traces the
+// samples of its work unit one after the other and banks them in order.
 template <int MODE, int NP, bool GRID>
 __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, const float* lds_prims,
-                                            uint32_t (*cnt)[64 * kRenderWaves]) {
+                                            uint32_t (*tot)[64 * kRenderWaves]) {
     typename GeoSel<NP, GRID>::type G;
     constexpr bool kWaveLight = GeoSel<NP, GRID>::type::kWaveLight;
     G.init(A, lds_prims);
 
     TicketPool pool;
     pool.reset();
-    int state = S_IDLE;
-    // unit state
-    int64_t unit = 0;
+    int state = S_NEED;
+    // unit state: the next sample to start and the end of the unit's range
+    int64_t unit = -1;
     int px = 0, py = 0;
-    int s = 0, s_end = 0;
+    int s_next = 0, s_end = 0;
     float acc_sum = 0.0f, acc_comp = 0.0f, acc_sq = 0.0f;
     uint32_t acc_ev = 0, acc_st = 0;
-    // path state
+    // current path
     Rng rng = make_rng(A.seed, MS_TAG_RENDER_PATH, 0);
     V3 o = v3(0, 0, 0), d = v3(0, 0, 1);
     float t = 0.0f, Lp = 0.0f, r_step = 0.0f;
-    uint32_t c0 = 0, iters = 0, p_ev = 0, p_st = 0;
-    bool p_trunc = false;
-    // the lane's diagnostic counters (paths, events, steps, truncated paths)
-    // live in LDS: touched once per path, they would otherwise hold four
-    // registers through the whole loop
-    const int tid = threadIdx.x;
-    for (int q = 0; q < 4; ++q) cnt[q][tid] = 0;
+    uint32_t c0 = 0, p_ev = 0, p_st = 0;
     // iterations for which lanes have been waiting for a restart / a learned
     // step (wave-uniform): a pass also runs once the oldest wait reaches
     // max_wait, so rare steps do not idle lanes for long
     int end_age = 0, wait_age = 0;
+    // the lane's totals of events, learned steps and truncated paths for the
+    // launch counters live in LDS: touched once per work unit (truncations:
+    // once per truncated path), they would otherwise hold registers through
+    // the whole loop
+    const int tid = threadIdx.x;
+    for (int q = 0; q < 3; ++q) tot[q][tid] = 0;
+
+    auto start_path = [&](int q) __attribute__((always_inline)) {
+        const uint64_t sample = A.sample_offset + (uint64_t)q;
+        const uint64_t id = (uint64_t)(uint32_t)(py * A.width + px) | (sample << 32);
+        const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
+        const uint4 jw = rp.block(0);
+        rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
+        const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
+        const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
+        o = v3(A.eye[0], A.eye[1], A.eye[2]);
+        d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0], A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
+                         A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
+        G.set_camera_ray(o, d);
+        t = 0.0f;
+        Lp = 0.0f;
+        c0 = 0;
+        p_ev = 0;
+        p_st = 0;
+        state = S_FLY;
+    };
 
     // ---- restart phase, batched: lanes whose path ended bank it, lanes out
     // of samples take a work unit, then every lane with a sample to trace
@@ -698,7 +758,7 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
     // else is in flight, or the oldest wait reaches max_wait, so that its
     // code is not issued for a handful of lanes on most iterations.
     auto restart_now = [&]() __attribute__((always_inline)) -> bool {
-        const uint64_t rmask = ballot(state == S_END || state == S_IDLE);
+        const uint64_t rmask = ballot(state == S_END || state == S_NEED);
         const uint64_t amask = ballot(state == S_FLY || state == S_WAIT);
         end_age = rmask != 0 ? end_age + 1 : 0;
         return rmask != 0 && (__popcll(rmask) >= A.restart_min || amask == 0 || end_age > A.max_wait);
@@ -711,35 +771,34 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
             acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
             acc_ev += p_ev;
             acc_st += p_st;
-            cnt[0][tid] += 1;
-            cnt[1][tid] += p_ev;
-            cnt[2][tid] += p_st;
-            cnt[3][tid] += p_trunc;
-            ++s;
-            if (s >= s_end) {
+            if (s_next < s_end) {
+                start = true;
+            } else {
+                // the unit's last sample: its record
                 UnitRecord rec;
                 rec.sum = acc_sum + acc_comp;
                 rec.sumsq = acc_sq;
                 rec.events = acc_ev;
                 rec.steps = acc_st;
                 A.part[unit] = rec;
-                state = S_IDLE;
-            } else {
-                start = true;
+                tot[0][tid] += acc_ev;
+                tot[1][tid] += acc_st;
+                unit = -1;
             }
+            state = S_NEED;
         }
-        const bool need = state == S_IDLE;
+        const bool need = state == S_NEED && unit < 0;
         const uint64_t tk = pool.take(need, A.ticket, 64);
         if (need) {
             if (tk < (uint64_t)A.n_units) {
                 unit = (int64_t)tk;
                 // pixel-major: a wave's block of tickets covers few pixels
-                const int pixel = (int)(unit / A.n_chunks);
-                const int ch = (int)(unit - (int64_t)pixel * A.n_chunks);
-                py = pixel / A.width;
-                px = pixel - py * A.width;
-                s = ch * A.chunk;
-                s_end = s + A.chunk < A.spp ? s + A.chunk : A.spp;
+                const uint32_t pixel = udiv_exact((uint32_t)tk, (uint32_t)A.n_chunks, A.inv_n_chunks);
+                const int ch = (int)((uint32_t)tk - pixel * (uint32_t)A.n_chunks);
+                py = (int)udiv_exact(pixel, (uint32_t)A.width, A.inv_width);
+                px = (int)pixel - py * A.width;
+                s_next = ch * A.chunk;
+                s_end = s_next + A.chunk < A.spp ? s_next + A.chunk : A.spp;
                 acc_sum = acc_comp = acc_sq = 0.0f;
                 acc_ev = acc_st = 0;
                 start = true;
@@ -748,25 +807,8 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
             }
         }
         if (start) {
-            const uint64_t sample = A.sample_offset + (uint64_t)s;
-            const uint64_t id = (uint64_t)(uint32_t)(py * A.width + px) | (sample << 32);
-            const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
-            const uint4 jw = rp.block(0);
-            rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
-            const float sx = 2.0f * ((float)px + u01(jw.x)) / (float)A.width - 1.0f;
-            const float sy = 1.0f - 2.0f * ((float)py + u01(jw.y)) / (float)A.height;
-            o = v3(A.eye[0], A.eye[1], A.eye[2]);
-            d = normalize(v3(A.fwd[0] + sx * A.right[0] + sy * A.upv[0],
-                             A.fwd[1] + sx * A.right[1] + sy * A.upv[1],
-                             A.fwd[2] + sx * A.right[2] + sy * A.upv[2]));
-            G.set_camera_ray(o, d);
-            t = 0.0f;
-            Lp = 0.0f;
-            c0 = 0;
-            iters = 0;
-            p_ev = 0;
-            p_st = 0;
-            state = S_FLY;
+            start_path(s_next);
+            ++s_next;
         }
     };
 
@@ -794,7 +836,9 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                 } else {
                     t += l;
                     const V3 p = fma3(t, d, o);
-                    if (++iters > A.max_events) {
+                    // every collision is a plain event or a learned step, so
+                    // p_ev + p_st counts the path's collisions so far
+                    if (p_ev + p_st >= A.max_events) {
                         path_end = true;
                         truncated = true;
                     } else {
@@ -879,35 +923,38 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
         }
     };
 
-    // ---- MFMA phase: learned sphere steps for the waiting lanes (wmask)
-    auto learned_pass = [&](uint64_t wmask, bool& path_end) __attribute__((always_inline)) {
-        wait_age = 0;
+    // ---- MFMA phase: one learned sphere step for every lane with `mine`
+    // (wmask = ballot(mine)), on the path state passed in: position po (the
+    // collision, the sphere's centre), direction pd, radius pr, Philox stream
+    // prng at block pc0, radiance pLp, step count pst.  Returns whether the
+    // path survives the step; a survivor's po, pd become the exit point and
+    // direction.
+    auto learned_core = [&](uint64_t wmask, bool mine, V3& po, V3& pd, float pr, const Rng& prng, uint32_t& pc0,
+                            float& pLp, uint32_t& pst) __attribute__((always_inline)) -> bool {
         const int n_wait = __popcll(wmask);
-        const bool mine = state == S_WAIT;
         float y[6];
         float N = 1.0f, psi = 0.0f;
-        const float lst = fast_ln(A.sigma_t * r_step);
+        const float lst = fast_ln(A.sigma_t * pr);
         // LengthGen (sigma_t r, g) -> N
         const int slot0 = rank_in(wmask);
         if (mine) {
             const float c2[2] = {lst, A.g};
-            stage_row<1, 2>(A.pm[0], L, slot0, rng, c0, c2);
+            stage_row<1, 2>(A.pm[0], L, slot0, prng, pc0, c2);
         }
         stage_normals<1>(A, A.pm[0], L, n_wait);
         decode_rows<1>(A.pm[0], L, mine, slot0, n_wait, y);
         bool alive = false;
         float u_hg = 0.5f, u_first = 1.0f, phiN = 1.0f;
         if (mine) {
-            ++p_st;
+            ++pst;
             N = __builtin_fmaxf(1.0f, floorf(fast_exp(__builtin_fminf(y[0], 20.0f)) + 0.5f));
-            const uint4 wa = rng.block(c0++);
+            const uint4 wa = prng.block(pc0++);
             psi = u01(wa.y);
             u_hg = u01(wa.z);
             u_first = u01(wa.w);
             // absorption along the bypassed chain (Sec. 3.2)
             phiN = fast_exp(N * A.ln_albedo);
             alive = u01(wa.x) <= phiN;
-            if (!alive) path_end = true;
         }
         // N = 1: a single HG scatter at the centre, sampled exactly;
         // N >= 2: PathGen, then each representative event is the centre
@@ -932,14 +979,14 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
         const uint64_t pmask = ballot(use_path);
         const float lnN = fast_ln(N);
         if (pmask) {
-            const int slot = rank_in(pmask);
+            const int row = rank_in(pmask);
             // PathGen (sigma_t r, g, N) -> (cos theta, alpha, beta)
             if (use_path) {
                 const float c3[3] = {lst, A.g, lnN};
-                stage_row<3, 3>(A.pm[1], L, slot, rng, c0, c3);
+                stage_row<3, 3>(A.pm[1], L, row, prng, pc0, c3);
             }
             stage_normals<3>(A, A.pm[1], L, __popcll(pmask));
-            decode_rows<3>(A.pm[1], L, use_path, slot, __popcll(pmask), y);
+            decode_rows<3>(A.pm[1], L, use_path, row, __popcll(pmask), y);
             if (use_path) {
                 ct = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, y[0]));
                 al = y[1];
@@ -954,26 +1001,49 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
         V3 e1 = v3(1, 0, 0), e2 = v3(0, 1, 0);
         float cp = 1.0f, sp = 0.0f;
         if (lit) {
-            onb(d, e1, e2);
+            onb(pd, e1, e2);
             cp = cos_rev(psi);
             sp = sin_rev(psi);
         }
-        for (int k = 0; k < A.nee_samples; ++k) {
-            float uf = u_first;
-            if (k > 0 && lit) uf = u01(rng.block(c0++).x);
-            const bool use_event = use_path && (paper || !(uf * lam <= A.albedo));
-            V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
-            const uint64_t emask = ballot(use_event);
-            if (emask) {
-                const int slot = rank_in(emask);
-                // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
-                if (use_event) {
-                    const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-                    stage_row<6, 7>(A.pm[2], L, slot, rng, c0, c7);
+        // The K representative events: event k's first-event test draws a
+        // block (k > 0) and, where EventGen answers, its normals follow; the
+        // EventGen rows of a group of events are decoded together (a lane's
+        // rows consecutive), as many events per group as 64 rows hold.
+        const int n_cand = __popcll(ballot(use_path));
+        const int group = n_cand > 0 ? (64 / n_cand < 1 ? 1 : 64 / n_cand) : A.nee_samples;
+        const int nb_ev = (A.pm[2]->latent + 6 + 3) >> 2;
+        const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
+        for (int ka = 0; ka < A.nee_samples; ka += group) {
+            const int kb = ka + group < A.nee_samples ? ka + group : A.nee_samples;
+            // decisions and draw positions of the group's events
+            uint32_t evbits = 0;
+            const uint32_t c0_group = pc0;
+            for (int k = ka; k < kb; ++k) {
+                float uf = u_first;
+                if (k > 0 && lit) uf = u01(prng.block(pc0++).x);
+                if (use_path && (paper || !(uf * lam <= A.albedo))) {
+                    evbits |= 1u << (k - ka);
+                    pc0 += (uint32_t)nb_ev;
                 }
-                stage_normals<6>(A, A.pm[2], L, __popcll(emask));
-                decode_rows<6>(A.pm[2], L, use_event, slot, __popcll(emask), y);
-                if (use_event) {
+            }
+            int n_rows;
+            const int base = wave_prefix_small(__popc(evbits), n_rows);
+            if (n_rows > 0) {
+                // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
+                uint32_t c = c0_group;
+                int j = 0;
+                for (int k = ka; k < kb; ++k) {
+                    if (k > 0 && lit) ++c;
+                    if ((evbits >> (k - ka)) & 1u) stage_row<6, 7>(A.pm[2], L, base + j++, prng, c, c7);
+                }
+                stage_normals<6>(A, A.pm[2], L, n_rows);
+                decode_tiles(A.pm[2], L, n_rows);
+            }
+            int j = 0;
+            for (int k = ka; k < kb; ++k) {
+                V3 X = v3(0, 0, 0), W = v3(0, 0, 1);
+                if ((evbits >> (k - ka)) & 1u) {
+                    read_row<6>(A.pm[2], L, base + j++, y);
                     X = v3(y[0], y[1], y[2]);
                     W = v3(y[3], y[4], y[5]);
                     const float xl2 = dot(X, X);
@@ -981,21 +1051,22 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                     const float wl2 = dot(W, W);
                     W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
                 }
+                V3 Xw = v3(0, 0, 0), Ww = v3(0, 0, 1);
+                if (lit) {
+                    // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
+                    const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
+                    const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
+                    Xw = po + pr * (Xt.x * e1 + Xt.y * e2 + Xt.z * pd);
+                    Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * pd);
+                    if constexpr (!kWaveLight) pLp += w_nee * G.light(A, Xw, Ww);
+                }
+                if constexpr (kWaveLight) {
+                    uint64_t mk[kMaxManyPrims / 64];
+                    G.light_mask(A, lit, Xw, mk);
+                    if (lit) pLp += w_nee * G.light_masked(A, Xw, Ww, mk);
+                }
             }
-            V3 Xw = v3(0, 0, 0), Ww = v3(0, 0, 1);
-            if (lit) {
-                // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
-                const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
-                const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
-                Xw = o + r_step * (Xt.x * e1 + Xt.y * e2 + Xt.z * d);
-                Ww = normalize(Wt.x * e1 + Wt.y * e2 + Wt.z * d);
-                if constexpr (!kWaveLight) Lp += w_nee * G.light(A, Xw, Ww);
-            }
-            if constexpr (kWaveLight) {
-                uint64_t mk[kMaxManyPrims / 64];
-                G.light_mask(A, lit, Xw, mk);
-                if (lit) Lp += w_nee * G.light_masked(A, Xw, Ww, mk);
-            }
+            wave_sync();
         }
         if (alive) {
             // Eq. (transform) with R = [e1 e2 d] and the exit frame of Sec. 4.1
@@ -1003,14 +1074,27 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
             const V3 xt = v3(st * cp, st * sp, ct);
             const V3 w0 = v3(be * ct + ga * st, al, -be * st + ga * ct);
             const V3 wt = v3(cp * w0.x - sp * w0.y, sp * w0.x + cp * w0.y, w0.z);
-            o = o + r_step * (xt.x * e1 + xt.y * e2 + xt.z * d);
-            d = normalize(wt.x * e1 + wt.y * e2 + wt.z * d);
-            G.set_ray(o, d);
-            t = 0.0f;
-            state = S_FLY;
+            po = po + pr * (xt.x * e1 + xt.y * e2 + xt.z * pd);
+            pd = normalize(wt.x * e1 + wt.y * e2 + wt.z * pd);
         }
+        return alive;
     };
 
+    // learned steps of the lanes waiting for one
+    auto learned_pass = [&](uint64_t wmask, bool& path_end) __attribute__((always_inline)) {
+        wait_age = 0;
+        const bool mine = state == S_WAIT;
+        const bool alive = learned_core(wmask, mine, o, d, r_step, rng, c0, Lp, p_st);
+        if (mine) {
+            if (alive) {
+                G.set_ray(o, d);
+                t = 0.0f;
+                state = S_FLY;
+            } else {
+                path_end = true;
+            }
+        }
+    };
     // Collisions, and for the learned method the decoder passes, repeat in a
     // loop of their own until a restart is due, so that the restart phase's
     // working set does not weigh on them (measured 5-6 % faster for plain
@@ -1032,20 +1116,18 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                     learned_pass(wmask, path_end);
             }
             if (path_end) {
-                p_trunc = truncated;
+                if (truncated) tot[2][tid] += 1;
                 state = S_END;
             }
             restart_due = restart_now();
         } while (!restart_due);
     }
     if (A.counters) {
-        const uint64_t a0 = wave_sum_u64(cnt[0][tid]), a1 = wave_sum_u64(cnt[1][tid]);
-        const uint64_t a2 = wave_sum_u64(cnt[2][tid]), a3 = wave_sum_u64(cnt[3][tid]);
+        const uint64_t a1 = wave_sum_u64(tot[0][tid]), a2 = wave_sum_u64(tot[1][tid]), a3 = wave_sum_u64(tot[2][tid]);
         if (lane_id() == 0) {
-            atomicAdd(A.counters + 0, (unsigned long long)a0);
-            atomicAdd(A.counters + 1, (unsigned long long)a1);
-            atomicAdd(A.counters + 2, (unsigned long long)a2);
-            atomicAdd(A.counters + 3, (unsigned long long)a3);
+            if (a1) atomicAdd(A.counters + 1, (unsigned long long)a1);
+            if (a2) atomicAdd(A.counters + 2, (unsigned long long)a2);
+            if (a3) atomicAdd(A.counters + 3, (unsigned long long)a3);
         }
     }
 }
@@ -1056,7 +1138,7 @@ template <int MODE, int NP, bool GRID>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
     __shared__ RenderLds lds_all[kRenderWaves];
     __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
-    __shared__ uint32_t lds_cnt[4][64 * kRenderWaves];
+    __shared__ uint32_t lds_tot[3][64 * kRenderWaves];
     RenderLds& L = lds_all[threadIdx.x >> 6];
     if (NP == 0) {
         for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
@@ -1070,11 +1152,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
         typename GeoSel<NP, GRID>::type G;
         G.init(A, lds_prims);
         if (!(A.sigma_t * __builtin_fminf(G.max_radius(), A.st_max * A.inv_sigma_t) >= A.tau_min)) {
-            render_loop<kModePlain, NP, GRID>(A, L, lds_prims, lds_cnt);
+            render_loop<kModePlain, NP, GRID>(A, L, lds_prims, lds_tot);
             return;
         }
     }
-    render_loop<MODE, NP, GRID>(A, L, lds_prims, lds_cnt);
+    render_loop<MODE, NP, GRID>(A, L, lds_prims, lds_tot);
 }
 
 // Per-pixel fixed-order reduction of the unit partials, added to the image
@@ -1082,9 +1164,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
 // One wave per pixel: lane c adds the records of chunks c, c + 64, ... in
 // order (coalesced 16-byte loads), then a fixed butterfly combines the lanes,
 // so the result depends only on n_chunks.
-__global__ void render_reduce_kernel(int64_t npix, int n_chunks, const UnitRecord* part, float* sum, float* comp,
-                                     float* sumsq, uint32_t* events, uint32_t* steps,
-                                     const unsigned long long* bad_models) {
+// The launch's path count (every sample of every pixel) goes to the optional
+// counters; the render kernel's waves add the other totals.
+__global__ void render_reduce_kernel(int64_t npix, int n_chunks, int spp, const UnitRecord* part, float* sum,
+                                     float* comp, float* sumsq, uint32_t* events, uint32_t* steps,
+                                     const unsigned long long* bad_models, unsigned long long* counters) {
     const int64_t wave0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int lane = lane_id();
@@ -1094,6 +1178,7 @@ __global__ void render_reduce_kernel(int64_t npix, int n_chunks, const UnitRecor
             if (lane == 0) sum[p] = __builtin_nanf("");
         return;
     }
+    if (counters && wave0 == 0 && lane == 0) atomicAdd(counters, (unsigned long long)(npix * spp));
     for (int64_t p = wave0; p < npix; p += n_waves) {
         const UnitRecord* r = part + p * n_chunks;
         double s = 0.0, q = 0.0;
@@ -1295,6 +1380,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                "sphere_trace_render: invalid SDF grid description");
     size_t need = 0;
     sphere_trace_render_workspace_size(cam, desc, &need);
+    MS_REQUIRE(need - 256 < ((size_t)1 << 32) * sizeof(UnitRecord),
+               "sphere_trace_render: more than 2^32 work units (raise chunk)");
     MS_REQUIRE(workspace_dev != nullptr, "sphere_trace_render: workspace is NULL");
     if (workspace_bytes < need)
         return set_error(MS_ERR_WORKSPACE_TOO_SMALL, "sphere_trace_render: workspace needs %zu bytes", need);
@@ -1356,6 +1443,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(A.npix, desc->spp);
     A.n_chunks = (desc->spp + A.chunk - 1) / A.chunk;
     A.n_units = A.npix * A.n_chunks;
+    A.inv_n_chunks = 1.0 / A.n_chunks;
+    A.inv_width = 1.0 / A.width;
     A.seed = desc->seed;
     A.sample_offset = desc->sample_offset;
     A.max_events = desc->max_events ? desc->max_events : (1u << 20);
@@ -1394,8 +1483,8 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     MS_LAUNCHED();
     int64_t rb = (A.npix + 3) / 4;  // four pixels (waves) per block
     if (rb > cus * 16) rb = cus * 16;
-    hipLaunchKernelGGL(render_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, hs, A.npix, A.n_chunks, A.part,
-                       out->sum, out->comp, out->sumsq, out->events, out->steps, flag);
+    hipLaunchKernelGGL(render_reduce_kernel, dim3((unsigned)rb), dim3(256), 0, hs, A.npix, A.n_chunks, A.spp, A.part,
+                       out->sum, out->comp, out->sumsq, out->events, out->steps, flag, A.counters);
     MS_LAUNCHED();
     clear_error();
     return MS_OK;

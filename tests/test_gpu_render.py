@@ -498,3 +498,4 @@ def test_rgb_media_channel_by_channel(msst, oracle):
         frac, _ = compare_paths(g, o, rel=LEARNED_REL)
         print(f"channel {c}: diverged {frac:.2e}, mean {o['sum'].mean():.4e}")
         assert frac < 3.5e-3
+
