@@ -78,8 +78,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--batch-min", type=int, default=0)
-    ap.add_argument("--nee-samples", type=int, default=2)
-    ap.add_argument("--nee-flags", type=int, default=1, help="1 = direct light of learned steps before absorption")
+    ap.add_argument("--nee-samples", type=int, default=1)
+    ap.add_argument("--nee-flags", type=int, default=3,
+                    help="1 = direct light of learned steps before absorption, 2 = the paper's step as printed "
+                         "(PathGen and EventGen for every step; the models are then trained on every walk record)")
+    ap.add_argument("--min-chain", type=float, default=64.0,
+                    help="cost rule: learned steps only where the deepest possible step bypasses at least this many "
+                         "collisions (0 = always)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--no-table1", action="store_true")
@@ -110,7 +115,8 @@ def parse():
                     help="skip the FP64 oracle's plain renders of every 16th pixel (z-test and RMSE anchor)")
     ap.add_argument("--oracle-spp", type=int, default=4096)
     ap.add_argument("--c5-oracle-spp", type=int, default=1024)
-    ap.add_argument("--no-paper-step", action="store_true", help="skip the paper's learned step as printed")
+    ap.add_argument("--no-exact-parts", action="store_true",
+                    help="skip the learned step with exact single-event parts (the other estimator form)")
     ap.add_argument("--diagnostics", action="store_true",
                     help="also render sphere tracing with exact in-sphere walks and a tau_min sweep (untimed)")
     return ap.parse_args()
@@ -437,7 +443,8 @@ def c5_section(M, W, torch, packs, args, timed):
             ("st_fp8", dict(method=2, packed=packs[2]))]
     for name, opt in runs:
         if opt["method"] == 2:
-            opt.update(tau_min=args.tau_min, nee_samples=args.nee_samples, flags=args.nee_flags)
+            opt.update(tau_min=args.tau_min, nee_samples=args.nee_samples, flags=args.nee_flags,
+                       min_chain=args.min_chain)
         rend.render(med, spp=16, seed=5, **opt)  # warm-up
         img, t = timed(lambda: rend.render(med, spp=spp, seed=6, **opt))
         c = img["counters"].cpu().numpy()
@@ -471,6 +478,17 @@ def c5_section(M, W, torch, packs, args, timed):
     return out
 
 
+def c4_tau(sigma_t, args, g=0.8, r_max=0.999):
+    """tau_min of a sphere + box launch as the render kernel applies it: the
+    cost rule (min_chain) turns learned steps off where even the deepest
+    sphere (the unit sphere's centre, radius 0.999 after the 0.1 % shrink)
+    bypasses too few collisions."""
+    t_max = sigma_t * min(r_max, 200.0 / sigma_t)
+    if args.min_chain > 0 and 0.5 * t_max * t_max * (1.0 - g) < args.min_chain:
+        return 1e30
+    return args.tau_min
+
+
 def cpu_baseline(oracle, W, args, models):
     """The oracle's sphere tracer with the CVAE step (FP64 decoders on the same
     trained FP32 masters and standardisation constants the GPU renders) on
@@ -493,7 +511,7 @@ def cpu_baseline(oracle, W, args, models):
                 pix = np.sort(rng.choice(args.width * args.width, npx, replace=False)).astype(np.int32)
                 t0 = time.time()
                 oracle.render(scene, cam, light, W.medium_c4(s), method=oracle.METHOD_ST,
-                              sampler=oracle.SAMPLER_CVAE, models=models, tau_min=args.tau_min, spp=spp,
+                              sampler=oracle.SAMPLER_CVAE, models=models, tau_min=c4_tau(s, args), spp=spp,
                               seed=50 + it, pixels=pix, n_threads=n_threads, nee_samples=args.nee_samples,
                               flags=args.nee_flags)
                 t_total += time.time() - t0
@@ -562,8 +580,9 @@ def main():
 
     log("training CVAEs on GPU random-walk data")
     tim = {}
+    paper_step = bool(args.nee_flags & 2)
     packs, losses, t_train = train_and_pack(M, torch, args.train_samples, args.train_steps, precisions=(1, 2),
-                                            timing=tim)
+                                            timing=tim, all_rows=paper_step)
     packed = packs[1]
 
     # plain reference (debiased by its own noise) and plain timing per density
@@ -584,7 +603,7 @@ def main():
 
     def st_render(s, seed, **extra):
         opts = dict(method=2, sampler=0, packed=packed, spp=spp, seed=seed, tau_min=args.tau_min,
-                    nee_samples=args.nee_samples, flags=args.nee_flags)
+                    nee_samples=args.nee_samples, flags=args.nee_flags, min_chain=args.min_chain)
         opts.update(kw)
         opts.update(extra)
         return rend.render(W.medium_c4(s), **opts)
@@ -684,7 +703,7 @@ def main():
     if not args.no_table1:
         log("Table 1 final architectures")
         pk1, losses1, t1 = train_and_pack(M, torch, args.train_samples, args.train_steps,
-                                          shapes=W.TABLE1_SHAPES)
+                                          shapes=W.TABLE1_SHAPES, all_rows=paper_step)
         table1 = {"shapes": W.TABLE1_SHAPES, "train_seconds": t1,
                   "loss_last": [l["last"] for l in losses1]}
         for s in sigmas:
@@ -697,27 +716,28 @@ def main():
             log(f"Table 1 sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default {details[str(s)]['rmse_st']:.3e}), "
                 f"speed-up {t_pt_match / t:.2f}")
 
-    # the paper's learned step as printed: PathGen and EventGen for every case
-    # (no exact single-event parts), models trained on every walk record
-    paper = None
-    if not args.no_paper_step:
-        log("the paper's learned step as printed")
-        pkp, _, tp = train_and_pack(M, torch, args.train_samples, args.train_steps, all_rows=True)
-        paper = {"flags": args.nee_flags | M._abi.RENDER_STEP_PAPER, "train_seconds": tp}
-        tot_p, tot_pm = 0.0, 0.0
+    # the other form of the learned step: its single-event parts sampled
+    # exactly (N = 1 by HG, the first event at the centre), PathGen and
+    # EventGen trained on the remaining records, two representative events
+    exact_parts = None
+    if not args.no_exact_parts:
+        log("learned step with exact single-event parts")
+        pke, _, te = train_and_pack(M, torch, args.train_samples, args.train_steps, all_rows=False)
+        exact_parts = {"flags": args.nee_flags & 1, "nee_samples": 2, "train_seconds": te}
+        tot_e, tot_em = 0.0, 0.0
         for s in sigmas:
-            img, t = timed(lambda: st_render(s, 6201, packed=pkp[1], flags=paper["flags"]))
+            img, t = timed(lambda: st_render(s, 6201, packed=pke[1], flags=exact_parts["flags"], nee_samples=2))
             c = img["counters"].cpu().numpy()
             r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
             t_m = pt[s]["var"] / r_st**2 * npix / (pt[s]["paths"] / pt[s]["time"])
-            paper[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, steps_per_path=float(c[2] / c[0]),
-                                 mean_st=float(image_moments(img, spp)[0].mean()),
-                                 speedup_matched_rmse=t_m / t, rmse_st_exact_single_events=details[str(s)]["rmse_st"])
-            tot_p += t
-            tot_pm += t_m
-            log(f"paper step sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (exact single events "
+            exact_parts[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, steps_per_path=float(c[2] / c[0]),
+                                       mean_st=float(image_moments(img, spp)[0].mean()),
+                                       speedup_matched_rmse=t_m / t, rmse_st_default=details[str(s)]["rmse_st"])
+            tot_e += t
+            tot_em += t_m
+            log(f"exact single-event parts sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default "
                 f"{details[str(s)]['rmse_st']:.3e}), speed-up {t_m / t:.2f}")
-        paper["speedup_matched_rmse"] = tot_pm / tot_p
+        exact_parts["speedup_matched_rmse"] = tot_em / tot_e
 
     # (sigma_t r, g)-weighted training data: half the walks from the region
     # the renders use (g near 0.8, sigma_t r above tau_min)
@@ -725,7 +745,8 @@ def main():
     if not args.no_focus:
         log("focus-weighted training data")
         fkw = dict(focus_fraction=0.5, focus_st_range=(args.tau_min, 200.0), focus_g_range=(0.7, 0.9))
-        pkf, _, tf = train_and_pack(M, torch, args.train_samples, args.train_steps, walk_kw=fkw)
+        pkf, _, tf = train_and_pack(M, torch, args.train_samples, args.train_steps, walk_kw=fkw,
+                                    all_rows=paper_step)
         focus = dict(fkw, train_seconds=tf)
         for s in sigmas:
             img, t = timed(lambda: st_render(s, 6101, packed=pkf[1]))
@@ -746,7 +767,7 @@ def main():
         img_pt, t_pt = timed(lambda: rend.render_rgb(media, method=1, spp=spp, seed=9100, **kw))
         img_st, t_st = timed(lambda: rend.render_rgb(media, method=2, sampler=0, packed=packed, spp=spp, seed=9200,
                                                      tau_min=args.tau_min, nee_samples=args.nee_samples,
-                                                     flags=args.nee_flags, **kw))
+                                                     flags=args.nee_flags, min_chain=args.min_chain, **kw))
         e2_st = e2_pt = v_pt = 0.0
         for c in range(3):
             pick = lambda im: {k: v[c] for k, v in im.items() if k != "counters"}
@@ -783,7 +804,7 @@ def main():
             pm, pv = image_moments(img_pt, spp)
             img_st, t_st = timed(lambda: mr.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=9500,
                                                    tau_min=args.tau_min, nee_samples=args.nee_samples,
-                                                   flags=args.nee_flags, **kw))
+                                                   flags=args.nee_flags, min_chain=args.min_chain, **kw))
             sm, _ = image_moments(img_st, spp)
             e_st = max(float(((sm - rm) ** 2).mean()) - noise2, 1e-30)
             e_pt = max(float(((pm - rm) ** 2).mean()) - noise2, 1e-30)
@@ -811,7 +832,7 @@ def main():
             pm, pv = image_moments(img_pt, spp)
             img_st, t_st = timed(lambda: rend.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=7200 + k,
                                                      tau_min=args.tau_min, nee_samples=args.nee_samples,
-                                                     flags=args.nee_flags, **kw))
+                                                     flags=args.nee_flags, min_chain=args.min_chain, **kw))
             sm, _ = image_moments(img_st, spp)
             e_st = float(np.sqrt(max(float(((sm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
             e_pt = float(np.sqrt(max(float(((pm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
@@ -889,7 +910,7 @@ def main():
             pm, pv = image_moments(img_pt, spp)
             img_st, t_st = timed(lambda: drend.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=9200 + k,
                                                       tau_min=args.tau_min, nee_samples=args.nee_samples,
-                                                      flags=args.nee_flags, **kw))
+                                                      flags=args.nee_flags, min_chain=args.min_chain, **kw))
             sm, _ = image_moments(img_st, spp)
             e_st = float(np.sqrt(max(float(((sm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
             e_pt = float(np.sqrt(max(float(((pm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
@@ -960,8 +981,11 @@ def main():
         "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": f"sphere+box SDF scene {width}x{width}, {spp} spp, g=0.8, albedo=0.995, "
                                f"sigma_t in {list(sigmas)}, point light + NEE, CVAE decoders BF16 on MFMA, "
-                               f"tau_min={args.tau_min}, {args.nee_samples} representative events per step"
-                               + (", direct light before absorption" if args.nee_flags & 1 else ""),
+                               f"tau_min={args.tau_min}, {args.nee_samples} representative event(s) per step"
+                               + (", direct light before absorption" if args.nee_flags & 1 else "")
+                               + (", the paper's step as printed" if args.nee_flags & 2 else "")
+                               + (f", learned steps only where the deepest step bypasses >= {args.min_chain:g} "
+                                  "collisions" if args.min_chain > 0 else ""),
                    "paths_per_step": paths_per_step, "parallelism": "single GPU"},
         "plain_paths_per_s": pt_rate,
         "object_hit_fraction": hit_fraction,
@@ -980,7 +1004,7 @@ def main():
         "cpu_baseline": cpu,
         "c5": c5,
         "table1": table1,
-        "paper_step": paper,
+        "exact_single_event_parts": exact_parts,
         "table1_sweep": sweep,
         "cvae_sample": sample,
         "walk_full": None if walk_full is None else dict(

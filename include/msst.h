@@ -357,6 +357,14 @@ typedef struct {
     int32_t max_wait;        /* loop iterations after which waiting lanes force a pass anyway; 0 = 10 */
     int32_t nee_samples;     /* representative events per learned step, 1..16 (0 = 1) */
     int32_t flags;           /* MS_RENDER_NEE_BEFORE_ABSORPTION | MS_RENDER_STEP_PAPER */
+    /* Cost rule for a launch (0 = off): learned steps are taken only if the
+     * deepest sphere the scene allows, of optical radius T = sigma_t *
+     * min(deepest interior distance, st_max / sigma_t), holds a chain of
+     * about T^2 (1 - g) / 2 collisions (the diffusion estimate of E[N]) of at
+     * least min_chain; otherwise the launch traces plainly (the same paths as
+     * PLAIN_NEE).  Scenes whose deepest distance is not known in closed form
+     * (a distance grid, many primitives, a mesh) always allow steps. */
+    float min_chain;
 } ms_render_desc;
 
 /* MS_RENDER_NEE_BEFORE_ABSORPTION: direct light of a learned step estimated

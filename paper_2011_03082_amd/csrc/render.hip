@@ -55,7 +55,7 @@ struct RenderArgs {
     uint32_t surv_thr;
     int method, sampler;
     const PackedModel* pm[3];
-    float tau_min, st_max;
+    float tau_min, st_max, min_chain;
     int spp, chunk, n_chunks;
     int64_t n_units;                      // below 2^32
     double inv_n_chunks, inv_width;       // reciprocals for the unit -> (pixel, chunk) split
@@ -1146,12 +1146,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void r
     }
     if (MODE != kModePlain) {
         // No point of the scene reaches tau_min (the deepest point of the
-        // deepest primitive, or the step cap, is too shallow): every collision
-        // is a plain one, so the plain loop runs -- the same paths and draws,
-        // without the learned step's checks and register pressure.
+        // deepest primitive, or the step cap, is too shallow), or the deepest
+        // possible step would bypass fewer than min_chain collisions (the
+        // launch's cost rule): every collision is a plain one, so the plain
+        // loop runs -- the same paths and draws, without the learned step's
+        // checks and register pressure.
         typename GeoSel<NP, GRID>::type G;
         G.init(A, lds_prims);
-        if (!(A.sigma_t * __builtin_fminf(G.max_radius(), A.st_max * A.inv_sigma_t) >= A.tau_min)) {
+        const float t_max = A.sigma_t * __builtin_fminf(G.max_radius(), A.st_max * A.inv_sigma_t);
+        const bool pays = !(A.min_chain > 0.0f) || 0.5f * t_max * t_max * (1.0f - A.g) >= A.min_chain;
+        if (!(t_max >= A.tau_min) || !pays) {
             render_loop<kModePlain, NP, GRID>(A, L, lds_prims, lds_tot);
             return;
         }
@@ -1369,6 +1373,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
                "sphere_trace_render: invalid launch parameters");
     // tau_min > 0 keeps every learned step off radius 0 (no log(0) condition)
     MS_REQUIRE(desc->tau_min > 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min > 0, st_max > 0");
+    MS_REQUIRE(desc->min_chain >= 0.0f, "sphere_trace_render: min_chain must be >= 0");
     MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
     MS_REQUIRE(desc->restart_min >= 0 && desc->restart_min <= 64, "sphere_trace_render: restart_min must be in [0, 64]");
     MS_REQUIRE(desc->max_wait >= 0, "sphere_trace_render: max_wait must be >= 0");
@@ -1439,6 +1444,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     for (int m = 0; m < 3; ++m) A.pm[m] = reinterpret_cast<const PackedModel*>(desc->packed[m]);
     A.tau_min = desc->tau_min;
     A.st_max = desc->st_max;
+    A.min_chain = desc->min_chain;
     A.spp = desc->spp;
     A.chunk = desc->chunk > 0 ? (desc->chunk < desc->spp ? desc->chunk : desc->spp) : default_chunk(A.npix, desc->spp);
     A.n_chunks = (desc->spp + A.chunk - 1) / A.chunk;

@@ -122,3 +122,8 @@ def test_mesh_bvh_rejects_invalid(M):
                                C.byref(nn)) == M._abi.MS_ERR_WORKSPACE_TOO_SMALL
     assert L.ms_build_mesh_bvh(tris.ctypes.data, 4, nodes.ctypes.data, nb.value, out.ctypes.data, C.byref(nn)) == 0
     assert 1 <= nn.value <= 8
+
+
+def test_render_rejects_negative_min_chain(M):
+    assert status(M, desc=desc_with(M, min_chain=-1.0)) == M._abi.MS_ERR_INVALID_ARGUMENT
+    assert b"min_chain" in M.lib().ms_last_error()

@@ -211,6 +211,26 @@ def test_dense_nearly_white_medium_learned_path_by_path(msst, oracle, sigma_t, r
     assert frac < bar
 
 
+@pytest.mark.parametrize("sigma_t,min_chain,plain", [(20.0, 64.0, True), (40.0, 64.0, False)])
+def test_cost_rule_turns_learned_steps_off_where_they_cannot_pay(msst, oracle, sigma_t, min_chain, plain):
+    """min_chain: the deepest sphere of the unit sphere + box (optical radius
+    0.999 sigma_t) bypasses about T^2 (1 - g) / 2 collisions -- 40 at sigma_t
+    20, 160 at 40 -- so with min_chain 64 the first launch traces plainly
+    (the plain tracer's image, no steps) and the second takes steps."""
+    announce(f"render cost rule sigma_t={sigma_t} min_chain={min_chain}")
+    prims, cam, light, med = c4_inputs(sigma_t, 32)
+    packed = pack_all(msst, models_for_test(oracle)[1])
+    b = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, tau_min=6.0, spp=3, seed=6,
+                   nee_samples=1, flags=3, min_chain=min_chain)
+    if plain:
+        a = gpu_render(msst, prims, cam, light, med, method=PLAIN, spp=3, seed=6)
+        np.testing.assert_allclose(a["sum"], b["sum"], rtol=1e-5, atol=1e-9)
+        np.testing.assert_array_equal(a["events"], b["events"])
+        assert b["steps"].sum() == 0
+    else:
+        assert b["steps"].sum() > 50
+
+
 @pytest.mark.parametrize("sampler,tau_min", [(EXACT, 1e30), (CVAE, 1e30), (EXACT, 10.0), (CVAE, 10.0)])
 def test_tau_above_all_radii_is_plain(msst, oracle, sampler, tau_min):
     """No point of the scene reaches tau_min -- a huge threshold, or sigma_t
