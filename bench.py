@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--batch-min", type=int, default=0)
     ap.add_argument("--nee-samples", type=int, default=1)
-    ap.add_argument("--nee-flags", type=int, default=3,
+    ap.add_argument("--nee-flags", type=int, default=1,
                     help="1 = direct light of learned steps before absorption, 2 = the paper's step as printed "
                          "(PathGen and EventGen for every step; the models are then trained on every walk record)")
     ap.add_argument("--min-chain", type=float, default=64.0,
@@ -115,8 +115,9 @@ def parse():
                     help="skip the FP64 oracle's plain renders of every 16th pixel (z-test and RMSE anchor)")
     ap.add_argument("--oracle-spp", type=int, default=4096)
     ap.add_argument("--c5-oracle-spp", type=int, default=1024)
-    ap.add_argument("--no-exact-parts", action="store_true",
-                    help="skip the learned step with exact single-event parts (the other estimator form)")
+    ap.add_argument("--no-other-form", action="store_true",
+                    help="skip the other form of the learned step (the paper's as printed when the default samples "
+                         "the single-event parts exactly, and the reverse)")
     ap.add_argument("--diagnostics", action="store_true",
                     help="also render sphere tracing with exact in-sphere walks and a tau_min sweep (untimed)")
     return ap.parse_args()
@@ -658,6 +659,7 @@ def main():
             pt_confirm=confirm,
             rmse_st=r_st, rmse_pt_same_spp=r_pt, ref_noise_rms=float(np.sqrt(ref_noise2[s])),
             mean_st=mean_st, mean_ref=float(ref[s].double().mean()),
+            mean_bias=mean_st / float(ref[s].double().mean()) - 1.0,
             st_paths_per_s=float(c[0] / t_sigma[s]), st_steps_per_path=float(c[2] / c[0]),
             st_events_per_path=float(c[1] / c[0]), pt_events_per_path=pt[s]["events"] / pt[s]["paths"],
             pt_paths_per_s=pt[s]["paths"] / pt[s]["time"], matched_spp_pt=s_star,
@@ -716,28 +718,33 @@ def main():
             log(f"Table 1 sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default {details[str(s)]['rmse_st']:.3e}), "
                 f"speed-up {t_pt_match / t:.2f}")
 
-    # the other form of the learned step: its single-event parts sampled
-    # exactly (N = 1 by HG, the first event at the centre), PathGen and
-    # EventGen trained on the remaining records, two representative events
-    exact_parts = None
-    if not args.no_exact_parts:
-        log("learned step with exact single-event parts")
-        pke, _, te = train_and_pack(M, torch, args.train_samples, args.train_steps, all_rows=False)
-        exact_parts = {"flags": args.nee_flags & 1, "nee_samples": 2, "train_seconds": te}
-        tot_e, tot_em = 0.0, 0.0
+    # the other form of the learned step, same images and estimator options
+    # otherwise: the paper's step as printed (PathGen and EventGen for every
+    # case, models trained on every walk record) beside the default with the
+    # single-event parts sampled exactly, or the reverse
+    other = None
+    if not args.no_other_form:
+        o_flags = args.nee_flags ^ 2
+        o_paper = bool(o_flags & 2)
+        name = "the paper's step as printed" if o_paper else "exact single-event parts"
+        log(f"learned step, other form: {name}")
+        pko, _, to = train_and_pack(M, torch, args.train_samples, args.train_steps, all_rows=o_paper)
+        other = {"form": name, "flags": o_flags, "nee_samples": args.nee_samples, "train_seconds": to}
+        tot_o, tot_om = 0.0, 0.0
         for s in sigmas:
-            img, t = timed(lambda: st_render(s, 6201, packed=pke[1], flags=exact_parts["flags"], nee_samples=2))
+            img, t = timed(lambda: st_render(s, 6201, packed=pko[1], flags=o_flags))
             c = img["counters"].cpu().numpy()
             r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
             t_m = pt[s]["var"] / r_st**2 * npix / (pt[s]["paths"] / pt[s]["time"])
-            exact_parts[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, steps_per_path=float(c[2] / c[0]),
-                                       mean_st=float(image_moments(img, spp)[0].mean()),
-                                       speedup_matched_rmse=t_m / t, rmse_st_default=details[str(s)]["rmse_st"])
-            tot_e += t
-            tot_em += t_m
-            log(f"exact single-event parts sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default "
-                f"{details[str(s)]['rmse_st']:.3e}), speed-up {t_m / t:.2f}")
-        exact_parts["speedup_matched_rmse"] = tot_em / tot_e
+            mean_o = float(image_moments(img, spp)[0].mean())
+            other[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, steps_per_path=float(c[2] / c[0]), mean_st=mean_o,
+                                 mean_bias=mean_o / details[str(s)]["mean_ref"] - 1.0,
+                                 speedup_matched_rmse=t_m / t, rmse_st_default=details[str(s)]["rmse_st"])
+            tot_o += t
+            tot_om += t_m
+            log(f"{name} sigma_t={s}: {t * 1e3:.1f} ms, rmse {r_st:.3e} (default {details[str(s)]['rmse_st']:.3e}), "
+                f"bias {other[str(s)]['mean_bias']:+.4f}, speed-up {t_m / t:.2f}")
+        other["speedup_matched_rmse"] = tot_om / tot_o
 
     # (sigma_t r, g)-weighted training data: half the walks from the region
     # the renders use (g near 0.8, sigma_t r above tau_min)
@@ -1004,7 +1011,7 @@ def main():
         "cpu_baseline": cpu,
         "c5": c5,
         "table1": table1,
-        "exact_single_event_parts": exact_parts,
+        "other_step_form": other,
         "table1_sweep": sweep,
         "cvae_sample": sample,
         "walk_full": None if walk_full is None else dict(

@@ -17,7 +17,7 @@ def test_defaults_match_the_documented_configuration(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
     assert (a.gpus, a.width, a.spp, a.ref_spp) == (1, 512, 256, 4096)
-    assert a.tau_min == 10.0 and a.nee_samples == 1 and a.nee_flags == 3 and a.min_chain == 64.0
+    assert a.tau_min == 10.0 and a.nee_samples == 1 and a.nee_flags == 1 and a.min_chain == 64.0
     assert a.train_samples == 1 << 22 and a.train_steps == 20000
 
 
