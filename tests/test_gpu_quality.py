@@ -76,9 +76,15 @@ def pipeline(msst, packed, st, g, n, seed, paper):
 
 
 # Asserted bounds on the medians over the 16 settings of the two-sample KS
-# distance (learned against walk) and on the worst setting's E[N] ratio.
-# Measured with this recipe: see the printed table of each run.
-BOUNDS = {"log N": 0.5, "cos theta": 0.5, "alpha | N > 1": 0.5, "beta | N > 1": 0.5, "|X|": 0.5}
+# distance (learned against walk).  Measured with this recipe (medians of
+# log N, cos theta, alpha, beta, |X|): exact single-event parts 0.141, 0.111,
+# 0.042, 0.069, 0.208; every record learned 0.141, 0.118, 0.071, 0.090, 0.493
+# (EventGen must then reproduce the point mass of |X| at 0 that the first
+# event, at the sphere's centre, puts there).
+BOUNDS = {
+    False: {"log N": 0.2, "cos theta": 0.15, "alpha | N > 1": 0.08, "beta | N > 1": 0.1, "|X|": 0.3},
+    True: {"log N": 0.2, "cos theta": 0.15, "alpha | N > 1": 0.1, "beta | N > 1": 0.12, "|X|": 0.6},
+}
 
 
 @pytest.mark.parametrize("paper", [True, False])
@@ -113,7 +119,7 @@ def test_learned_distributions_against_the_walk(msst, trained, paper):
            "|X|": np.median(arr[:, 8])}
     print("median KS: " + ", ".join(f"{k} {v:.3f}" for k, v in med.items()))
     for k, v in med.items():
-        assert v < BOUNDS[k], (k, v)
+        assert v < BOUNDS[paper][k], (k, v)
     assert np.all(np.abs(np.log(arr[:, 4] / arr[:, 3])) < np.log(2.0))
 
 
