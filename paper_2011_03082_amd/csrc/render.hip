@@ -30,6 +30,15 @@ constexpr int kRenderWaves = 4;
 // (WAIT), path finished and not yet banked (END), no work left (DONE).
 enum : int { S_NEED = 0, S_FLY = 2, S_WAIT = 3, S_DONE = 4, S_END = 5 };
 
+// Per-lane words kept in LDS ([word][thread]): the work unit's compensated
+// sum, compensation, sum of squares, event and step counts, next sample,
+// end of its sample range and index (U_NONE: no unit), then the lane's
+// launch totals of events, learned steps and truncated paths.
+enum : int {
+    U_SUM = 0, U_COMP, U_SQ, U_EV, U_ST, U_NEXT, U_END, U_UNIT, T_EVENTS, T_STEPS, T_TRUNC, kLaneWords
+};
+constexpr uint32_t U_NONE = 0xFFFFFFFFu;
+
 // Result of one work unit (one pixel, `chunk` consecutive samples): the
 // compensated radiance sum folded to binary32, the sum of squares and the
 // event / learned-step counts, written with one 16-byte store.
@@ -710,12 +719,6 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
     TicketPool pool;
     pool.reset();
     int state = S_NEED;
-    // unit state: the next sample to start and the end of the unit's range
-    int64_t unit = -1;
-    int px = 0, py = 0;
-    int s_next = 0, s_end = 0;
-    float acc_sum = 0.0f, acc_comp = 0.0f, acc_sq = 0.0f;
-    uint32_t acc_ev = 0, acc_st = 0;
     // current path
     Rng rng = make_rng(A.seed, MS_TAG_RENDER_PATH, 0);
     V3 o = v3(0, 0, 0), d = v3(0, 0, 1);
@@ -725,16 +728,20 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
     // step (wave-uniform): a pass also runs once the oldest wait reaches
     // max_wait, so rare steps do not idle lanes for long
     int end_age = 0, wait_age = 0;
-    // the lane's totals of events, learned steps and truncated paths for the
-    // launch counters live in LDS: touched once per work unit (truncations:
-    // once per truncated path), they would otherwise hold registers through
-    // the whole loop
+    // The lane's work unit (its accumulators, next sample, end of range and
+    // index; U_NONE when it has none) and its totals of events, learned
+    // steps and truncated paths for the launch counters live in LDS: touched
+    // once per sample or per unit, they would otherwise hold registers
+    // through the collision and decoder loops
     const int tid = threadIdx.x;
-    for (int q = 0; q < 3; ++q) tot[q][tid] = 0;
+    for (int q = 0; q < kLaneWords; ++q) tot[q][tid] = 0;
+    tot[U_UNIT][tid] = U_NONE;
 
-    auto start_path = [&](int q) __attribute__((always_inline)) {
+    auto start_path = [&](uint32_t pixel, int q) __attribute__((always_inline)) {
+        const int py = (int)udiv_exact(pixel, (uint32_t)A.width, A.inv_width);
+        const int px = (int)pixel - py * A.width;
         const uint64_t sample = A.sample_offset + (uint64_t)q;
-        const uint64_t id = (uint64_t)(uint32_t)(py * A.width + px) | (sample << 32);
+        const uint64_t id = (uint64_t)pixel | (sample << 32);
         const Rng rp = make_rng(A.seed, MS_TAG_RENDER_PIXEL, id);
         const uint4 jw = rp.block(0);
         rng = make_rng(A.seed, MS_TAG_RENDER_PATH, id);
@@ -766,12 +773,19 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
     auto restart = [&]() __attribute__((always_inline)) {
         end_age = 0;
         bool start = false;
+        int s_next = 0;
         if (state == S_END) {
+            float acc_sum = __uint_as_float(tot[U_SUM][tid]), acc_comp = __uint_as_float(tot[U_COMP][tid]);
             neumaier_add(acc_sum, acc_comp, Lp);
-            acc_sq = __builtin_fmaf(Lp, Lp, acc_sq);
-            acc_ev += p_ev;
-            acc_st += p_st;
-            if (s_next < s_end) {
+            const float acc_sq = __builtin_fmaf(Lp, Lp, __uint_as_float(tot[U_SQ][tid]));
+            const uint32_t acc_ev = tot[U_EV][tid] + p_ev, acc_st = tot[U_ST][tid] + p_st;
+            s_next = (int)tot[U_NEXT][tid];
+            if (s_next < (int)tot[U_END][tid]) {
+                tot[U_SUM][tid] = __float_as_uint(acc_sum);
+                tot[U_COMP][tid] = __float_as_uint(acc_comp);
+                tot[U_SQ][tid] = __float_as_uint(acc_sq);
+                tot[U_EV][tid] = acc_ev;
+                tot[U_ST][tid] = acc_st;
                 start = true;
             } else {
                 // the unit's last sample: its record
@@ -780,35 +794,34 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                 rec.sumsq = acc_sq;
                 rec.events = acc_ev;
                 rec.steps = acc_st;
-                A.part[unit] = rec;
-                tot[0][tid] += acc_ev;
-                tot[1][tid] += acc_st;
-                unit = -1;
+                A.part[tot[U_UNIT][tid]] = rec;
+                tot[T_EVENTS][tid] += acc_ev;
+                tot[T_STEPS][tid] += acc_st;
+                tot[U_UNIT][tid] = U_NONE;
             }
             state = S_NEED;
         }
-        const bool need = state == S_NEED && unit < 0;
+        const bool need = state == S_NEED && tot[U_UNIT][tid] == U_NONE;
         const uint64_t tk = pool.take(need, A.ticket, 64);
         if (need) {
             if (tk < (uint64_t)A.n_units) {
-                unit = (int64_t)tk;
+                tot[U_UNIT][tid] = (uint32_t)tk;
                 // pixel-major: a wave's block of tickets covers few pixels
                 const uint32_t pixel = udiv_exact((uint32_t)tk, (uint32_t)A.n_chunks, A.inv_n_chunks);
                 const int ch = (int)((uint32_t)tk - pixel * (uint32_t)A.n_chunks);
-                py = (int)udiv_exact(pixel, (uint32_t)A.width, A.inv_width);
-                px = (int)pixel - py * A.width;
                 s_next = ch * A.chunk;
-                s_end = s_next + A.chunk < A.spp ? s_next + A.chunk : A.spp;
-                acc_sum = acc_comp = acc_sq = 0.0f;
-                acc_ev = acc_st = 0;
+                tot[U_END][tid] = (uint32_t)(s_next + A.chunk < A.spp ? s_next + A.chunk : A.spp);
+                tot[U_SUM][tid] = tot[U_COMP][tid] = tot[U_SQ][tid] = 0u;
+                tot[U_EV][tid] = tot[U_ST][tid] = 0u;
                 start = true;
             } else {
                 state = S_DONE;
             }
         }
         if (start) {
-            start_path(s_next);
-            ++s_next;
+            const uint32_t unit = tot[U_UNIT][tid];
+            start_path(udiv_exact(unit, (uint32_t)A.n_chunks, A.inv_n_chunks), s_next);
+            tot[U_NEXT][tid] = (uint32_t)(s_next + 1);
         }
     };
 
@@ -1116,14 +1129,15 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                     learned_pass(wmask, path_end);
             }
             if (path_end) {
-                if (truncated) tot[2][tid] += 1;
+                if (truncated) tot[T_TRUNC][tid] += 1;
                 state = S_END;
             }
             restart_due = restart_now();
         } while (!restart_due);
     }
     if (A.counters) {
-        const uint64_t a1 = wave_sum_u64(tot[0][tid]), a2 = wave_sum_u64(tot[1][tid]), a3 = wave_sum_u64(tot[2][tid]);
+        const uint64_t a1 = wave_sum_u64(tot[T_EVENTS][tid]), a2 = wave_sum_u64(tot[T_STEPS][tid]),
+                       a3 = wave_sum_u64(tot[T_TRUNC][tid]);
         if (lane_id() == 0) {
             if (a1) atomicAdd(A.counters + 1, (unsigned long long)a1);
             if (a2) atomicAdd(A.counters + 2, (unsigned long long)a2);
@@ -1138,7 +1152,7 @@ template <int MODE, int NP, bool GRID>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
     __shared__ RenderLds lds_all[kRenderWaves];
     __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
-    __shared__ uint32_t lds_tot[3][64 * kRenderWaves];
+    __shared__ uint32_t lds_tot[kLaneWords][64 * kRenderWaves];
     RenderLds& L = lds_all[threadIdx.x >> 6];
     if (NP == 0) {
         for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
