@@ -253,7 +253,8 @@ def train_one(M, torch, walk, model, shape, steps, batch=4096, seed=0, kl_warmup
 
 def table1_sweep(M, torch, W, n_samples, steps, n_eval=10000, seed=0):
     """The architecture sweep of Table 1: every examined (D, W, L) of each
-    model that fits one 16-wide tile is trained on the same walks, and its
+    model (one 16-wide MFMA tile per layer, two for W = 20 or L = 9) is
+    trained on the same walks, and its
     samples are compared with the walk on the Sec. 5.3 evaluation grid
     (sigma_t in {1, 4, 20, 100}, g in {-0.7, 0, 0.4, 0.9}, albedo 1) by the
     mean two-sample KS distance of log N (LengthGen), cos theta given the true

@@ -140,13 +140,16 @@ ms_status ms_random_walk(const ms_walk_desc* desc, const ms_walk_out* out, void*
  *   LengthGen  cond (log sigma_t r, g)                                -> log N
  *   PathGen    cond (log sigma_t r, g, log N)                         -> (cos theta, alpha, beta)
  *   EventGen   cond (log sigma_t r, g, albedo, cos theta, alpha, beta, log N) -> (X, W)
- * Limits: width <= 16, p_out + p_in <= 16, latent + p_in <= 16,
- * 2 * p_out <= 16, 2 * latent <= 16, n_linear == 3.
+ * Limits: 2 <= n_linear <= 4 (Table 1's depths D = 1..3), width <= 32,
+ * p_in <= 16, p_out + p_in <= 32, latent + p_in <= 32, 2 * p_out <= 32,
+ * 2 * latent <= 32 (all of Table 1's settings).
  *
  * Master parameter layout (FP32, cvae_param_count floats): 2 * n_linear
- * layers, encoder first; each layer = 16 x 16 row-major weights (row =
- * output unit) then 16 biases; unused rows and columns are zero and stay
- * zero.  Encoder input is (target, cond); decoder input is (z, cond);
+ * layers, encoder first; each layer = S x S row-major weights (row = output
+ * unit) then S biases, S = 16 when width, p_out + p_in, latent + p_in,
+ * 2 p_out and 2 latent are all <= 16 (one MFMA tile per layer) and S = 32
+ * otherwise (a 2 x 2 grid of tiles); unused rows and columns are zero and
+ * stay zero.  Encoder input is (target, cond); decoder input is (z, cond);
  * output rows are (mean[0..k), log variance[0..k)); log variances are
  * clamped to [-12, 8].
  */
@@ -227,7 +230,7 @@ ms_status cvae_train_step(const ms_cvae_shape* shape, float* master_dev, float* 
  * device memory (code under HIP graph capture, tight training loops,
  * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
  * cvae_train_step; the per-block partials live in a static device array of
- * the library (about 2.2 MB per device, held until the process ends, sized
+ * the library (about 8.7 MB per device, held until the process ends, sized
  * for the largest batch (2^20) and network (n_linear 4) accepted; a
  * larger batch fails with MS_ERR_INVALID_ARGUMENT and a larger network with
  * MS_ERR_UNSUPPORTED before anything is launched).
@@ -342,7 +345,9 @@ typedef struct {
 
 typedef struct {
     int32_t method, sampler;
-    const void* packed[3];   /* LengthGen, PathGen, EventGen (ST with CVAE) */
+    const void* packed[3];   /* LengthGen, PathGen, EventGen (ST with CVAE); one-tile
+                              * models (S = 16, latent <= 8); other models leave the
+                              * image's sum NaN and trace nothing */
     /* learned steps where sigma_t r >= tau_min (> 0); r capped at st_max / sigma_t.
      * The decoders are trained on sigma_t r in [0.1, 200] (the training walk's
      * st_range): tau_min below 0.1 or st_max above 200 asks them to extrapolate. */

@@ -26,7 +26,7 @@ SAMPLER_CVAE, SAMPLER_EXACT_WALK = 0, 1
 NEE_BEFORE_ABSORPTION = 1  # render flag: CVAE steps add direct light before the absorption test
 STEP_PAPER = 2  # render flag: the learned step as printed (PathGen and EventGen for every case)
 MAX_NEE = 16
-LAYER_FLOATS = 16 * 16 + 16
+LAYER_FLOATS = 16 * 16 + 16  # one-tile shapes (every network width <= 16)
 
 
 def default_threads() -> int:
@@ -120,6 +120,8 @@ def lib():
         L.or_round_bf16.restype = dbl
         L.or_round_fp8_e4m3.argtypes = [dbl]
         L.or_round_fp8_e4m3.restype = dbl
+        L.or_cvae_param_count.argtypes = [C.POINTER(_Shape)]
+        L.or_cvae_param_count.restype = i64
         L.or_cvae_init.argtypes = [C.POINTER(_Shape), u64, vp]
         L.or_cvae_loss_grad.argtypes = [C.POINTER(_Shape), vp, i32, vp, vp, u64, i64, u64, dbl, vp, vp, vp]
         L.or_cvae_loss_grad.restype = dbl
@@ -228,7 +230,14 @@ SHAPES = {
 
 
 def n_params(shape):
-    return 2 * shape["n_linear"] * LAYER_FLOATS
+    s = _shape(shape)
+    return int(lib().or_cvae_param_count(C.byref(s)))
+
+
+def layer_stride(shape):
+    """Row stride S of a layer's S x S weight block (16 or 32)."""
+    lf = n_params(shape) // (2 * shape["n_linear"])
+    return 16 if lf == 16 * 16 + 16 else 32
 
 
 def softplus(x):

@@ -16,8 +16,10 @@
  *
  * Parameter layout (shared interface with the GPU library, implemented
  * independently on each side): 2 * n_linear layers, encoder first; each
- * layer is a 16 x 16 row-major weight block (row = output unit, column =
- * input unit) followed by 16 biases; unused rows and columns are zero.
+ * layer is an S x S row-major weight block (row = output unit, column =
+ * input unit) followed by S biases; unused rows and columns are zero.
+ * S = 16 when every width of the two networks (hidden units, inputs,
+ * outputs) is at most 16, else 32 (Table 1's widest settings).
  */
 #include "msst_oracle.h"
 
@@ -29,6 +31,25 @@
 #define OR_LV_MAX (8.0)
 
 static int or_n_linear(const or_cvae_shape* s) { return s->n_linear > 0 ? s->n_linear : 3; }
+
+/* Row stride S of the parameter layout (see above). */
+static int or_stride(const or_cvae_shape* s) {
+    int m = s->width;
+    if (s->p_out + s->p_in > m) m = s->p_out + s->p_in;
+    if (s->latent + s->p_in > m) m = s->latent + s->p_in;
+    if (2 * s->p_out > m) m = 2 * s->p_out;
+    if (2 * s->latent > m) m = 2 * s->latent;
+    return m <= 16 ? 16 : 32;
+}
+
+static int or_layer_floats(const or_cvae_shape* s) {
+    int S = or_stride(s);
+    return S * S + S;
+}
+
+int64_t or_cvae_param_count(const or_cvae_shape* s) {
+    return (int64_t)(2 * or_n_linear(s)) * or_layer_floats(s);
+}
 
 double or_softplus(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
 static double or_sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
@@ -86,25 +107,26 @@ static void or_net_dims(const or_cvae_shape* s, int decoder, or_dims* d) {
     }
 }
 
-static const double* or_layer(const double* params, int layer) {
-    return params + (size_t)layer * OR_LAYER_FLOATS;
+static const double* or_layer(const double* params, int layer, int lf) {
+    return params + (size_t)layer * lf;
 }
 
 void or_cvae_init(const or_cvae_shape* s, uint64_t seed, double* params) {
     int nl = or_n_linear(s);
-    memset(params, 0, sizeof(double) * (size_t)(2 * nl) * OR_LAYER_FLOATS);
+    const int S = or_stride(s), lf = or_layer_floats(s);
+    memset(params, 0, sizeof(double) * (size_t)(2 * nl) * lf);
     for (int net = 0; net < 2; ++net) {
         or_dims dm;
         or_net_dims(s, net, &dm);
         for (int j = 0; j < nl; ++j) {
             int layer = net * nl + j;
             double bound = 1.0 / sqrt((double)dm.n_in[j]);
-            double* w = params + (size_t)layer * OR_LAYER_FLOATS;
+            double* w = params + (size_t)layer * lf;
             for (int r = 0; r < dm.n_out[j]; ++r) {
                 for (int c = 0; c <= dm.n_in[j]; ++c) {
                     /* c == n_in stands for the bias of row r */
-                    int flat = (c < dm.n_in[j]) ? r * OR_TILE + c : OR_TILE * OR_TILE + r;
-                    uint32_t p = (uint32_t)(layer * OR_LAYER_FLOATS + flat);
+                    int flat = (c < dm.n_in[j]) ? r * S + c : S * S + r;
+                    uint32_t p = (uint32_t)(layer * lf + flat);
                     uint32_t wd[4];
                     or_philox_blocks(seed, OR_TAG_CVAE_INIT, (uint64_t)s->model, p >> 2, 1, wd);
                     double u = or_u01(wd[p & 3u]);
@@ -126,36 +148,36 @@ static double or_q(double x, int precision) {
  * emulated precision prescribes.  For FP8 the weights are divided by the
  * per-layer weight scale max|W| / 448 and the inputs by the given activation
  * scale before rounding; the product is rescaled afterwards. */
-static void or_linear(const double* layer, int n_in, int n_out, const double* a, int precision,
+static void or_linear(const double* layer, int S, int n_in, int n_out, const double* a, int precision,
                       double act_scale, double* pre) {
     const double* W = layer;
-    const double* b = layer + OR_TILE * OR_TILE;
+    const double* b = layer + S * S;
     double sw = 1.0, sa = 1.0;
     if (precision == OR_PREC_FP8) {
         double mx = 0.0;
-        for (int r = 0; r < OR_TILE; ++r)
-            for (int c = 0; c < OR_TILE; ++c) mx = fmax(mx, fabs(W[r * OR_TILE + c]));
+        for (int r = 0; r < S; ++r)
+            for (int c = 0; c < S; ++c) mx = fmax(mx, fabs(W[r * S + c]));
         sw = mx > 0.0 ? mx / 448.0 : 1.0;
         sa = act_scale > 0.0 ? act_scale : 1.0;
     }
     for (int r = 0; r < n_out; ++r) {
         double acc = 0.0;
         for (int c = 0; c < n_in; ++c)
-            acc += or_q(W[r * OR_TILE + c] / sw, precision) * or_q(a[c] / sa, precision);
+            acc += or_q(W[r * S + c] / sw, precision) * or_q(a[c] / sa, precision);
         pre[r] = acc * sw * sa + b[r];
     }
 }
 
 typedef struct {
-    double a[9][OR_TILE];   /* a[j] = input of layer j; a[nl] = output */
-    double pre[8][OR_TILE]; /* pre-activations */
+    double a[9][OR_MAX_WIDTH];   /* a[j] = input of layer j; a[nl] = output */
+    double pre[8][OR_MAX_WIDTH]; /* pre-activations */
 } or_trace;
 
-static void or_mlp_forward(const double* params, int first_layer, int nl, const or_dims* dm,
+static void or_mlp_forward(const double* params, int S, int first_layer, int nl, const or_dims* dm,
                            int precision, const double* act_scales, or_trace* t) {
     for (int j = 0; j < nl; ++j) {
         double sa = act_scales ? act_scales[j] : 1.0;
-        or_linear(or_layer(params, first_layer + j), dm->n_in[j], dm->n_out[j], t->a[j],
+        or_linear(or_layer(params, first_layer + j, S * S + S), S, dm->n_in[j], dm->n_out[j], t->a[j],
                   precision, sa, t->pre[j]);
         for (int r = 0; r < dm->n_out[j]; ++r)
             t->a[j + 1][r] = (j < nl - 1) ? or_softplus(t->pre[j][r]) : t->pre[j][r];
@@ -164,25 +186,26 @@ static void or_mlp_forward(const double* params, int first_layer, int nl, const 
 
 /* Backward through an MLP given d loss / d output; accumulates parameter
  * gradients and returns d loss / d input in din. */
-static void or_mlp_backward(const double* params, int first_layer, int nl, const or_dims* dm,
+static void or_mlp_backward(const double* params, int S, int first_layer, int nl, const or_dims* dm,
                             const or_trace* t, const double* dout, double* grad, double* din) {
-    double dcur[OR_TILE];
+    const int lf = S * S + S;
+    double dcur[OR_MAX_WIDTH];
     memcpy(dcur, dout, sizeof dcur);
     for (int j = nl - 1; j >= 0; --j) {
-        double dpre[OR_TILE];
+        double dpre[OR_MAX_WIDTH];
         for (int r = 0; r < dm->n_out[j]; ++r)
             dpre[r] = (j < nl - 1) ? dcur[r] * or_sigmoid(t->pre[j][r]) : dcur[r];
-        const double* W = or_layer(params, first_layer + j);
-        double* gW = grad + (size_t)(first_layer + j) * OR_LAYER_FLOATS;
+        const double* W = or_layer(params, first_layer + j, lf);
+        double* gW = grad + (size_t)(first_layer + j) * lf;
         for (int r = 0; r < dm->n_out[j]; ++r) {
-            for (int c = 0; c < dm->n_in[j]; ++c) gW[r * OR_TILE + c] += dpre[r] * t->a[j][c];
-            gW[OR_TILE * OR_TILE + r] += dpre[r];
+            for (int c = 0; c < dm->n_in[j]; ++c) gW[r * S + c] += dpre[r] * t->a[j][c];
+            gW[S * S + r] += dpre[r];
         }
-        double dnext[OR_TILE];
-        for (int c = 0; c < OR_TILE; ++c) dnext[c] = 0.0;
+        double dnext[OR_MAX_WIDTH];
+        for (int c = 0; c < OR_MAX_WIDTH; ++c) dnext[c] = 0.0;
         for (int c = 0; c < dm->n_in[j]; ++c) {
             double acc = 0.0;
-            for (int r = 0; r < dm->n_out[j]; ++r) acc += W[r * OR_TILE + c] * dpre[r];
+            for (int r = 0; r < dm->n_out[j]; ++r) acc += W[r * S + c] * dpre[r];
             dnext[c] = acc;
         }
         memcpy(dcur, dnext, sizeof dcur);
@@ -202,7 +225,8 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
     or_dims de, dd;
     or_net_dims(s, 0, &de);
     or_net_dims(s, 1, &dd);
-    if (grad) memset(grad, 0, sizeof(double) * (size_t)(2 * nl) * OR_LAYER_FLOATS);
+    const int S = or_stride(s), lf = or_layer_floats(s);
+    if (grad) memset(grad, 0, sizeof(double) * (size_t)(2 * nl) * lf);
     double kl_sum = 0.0, nll_sum = 0.0;
     for (int b = 0; b < batch; ++b) {
         const double* y = target + (size_t)b * P;
@@ -217,7 +241,7 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
         memset(&td, 0, sizeof td);
         for (int i = 0; i < P; ++i) te.a[0][i] = y[i];
         for (int i = 0; i < C; ++i) te.a[0][P + i] = c[i];
-        or_mlp_forward(params, 0, nl, &de, OR_PREC_FP64, NULL, &te);
+        or_mlp_forward(params, S, 0, nl, &de, OR_PREC_FP64, NULL, &te);
         double muz[16], lvz_raw[16], lvz[16], z[16];
         for (int i = 0; i < L; ++i) {
             muz[i] = te.a[nl][i];
@@ -227,11 +251,11 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
         }
         for (int i = 0; i < L; ++i) td.a[0][i] = z[i];
         for (int i = 0; i < C; ++i) td.a[0][L + i] = c[i];
-        or_mlp_forward(params, nl, nl, &dd, OR_PREC_FP64, NULL, &td);
+        or_mlp_forward(params, S, nl, nl, &dd, OR_PREC_FP64, NULL, &td);
         double kl = 0.0, nll = 0.0;
         for (int i = 0; i < L; ++i) kl += 0.5 * (muz[i] * muz[i] + exp(lvz[i]) - lvz[i] - 1.0);
-        double dout_d[OR_TILE];
-        for (int i = 0; i < OR_TILE; ++i) dout_d[i] = 0.0;
+        double dout_d[OR_MAX_WIDTH];
+        for (int i = 0; i < OR_MAX_WIDTH; ++i) dout_d[i] = 0.0;
         for (int i = 0; i < P; ++i) {
             double mu = td.a[nl][i], lvr = td.a[nl][P + i], lv = or_clamp_lv(lvr);
             double r = y[i] - mu, iv = exp(-lv);
@@ -242,10 +266,10 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
         kl_sum += kl;
         nll_sum += nll;
         if (!grad) continue;
-        double ddin[OR_TILE];
-        or_mlp_backward(params, nl, nl, &dd, &td, dout_d, grad, ddin);
-        double dout_e[OR_TILE];
-        for (int i = 0; i < OR_TILE; ++i) dout_e[i] = 0.0;
+        double ddin[OR_MAX_WIDTH];
+        or_mlp_backward(params, S, nl, nl, &dd, &td, dout_d, grad, ddin);
+        double dout_e[OR_MAX_WIDTH];
+        for (int i = 0; i < OR_MAX_WIDTH; ++i) dout_e[i] = 0.0;
         for (int i = 0; i < L; ++i) {
             double dz = ddin[i];
             double sd = exp(0.5 * lvz[i]);
@@ -253,11 +277,11 @@ double or_cvae_loss_grad(const or_cvae_shape* s, const double* params, int32_t b
             dout_e[L + i] = (0.5 * dz * eps[i] * sd + kl_weight * 0.5 * (exp(lvz[i]) - 1.0)) *
                             or_clamp_mask(lvz_raw[i]);
         }
-        or_mlp_backward(params, 0, nl, &de, &te, dout_e, grad, NULL);
+        or_mlp_backward(params, S, 0, nl, &de, &te, dout_e, grad, NULL);
     }
     double inv = 1.0 / (double)batch;
     if (grad)
-        for (size_t i = 0; i < (size_t)(2 * nl) * OR_LAYER_FLOATS; ++i) grad[i] *= inv;
+        for (size_t i = 0; i < (size_t)(2 * nl) * lf; ++i) grad[i] *= inv;
     if (kl_out) *kl_out = kl_sum * inv;
     if (nll_out) *nll_out = nll_sum * inv;
     return (kl_sum + nll_sum) * inv;
@@ -292,7 +316,7 @@ void or_cvae_decode(const or_cvae_shape* s, const double* params, int32_t precis
     memset(&td, 0, sizeof td);
     for (int i = 0; i < L; ++i) td.a[0][i] = z[i];
     for (int i = 0; i < C; ++i) td.a[0][L + i] = cond_std[i];
-    or_mlp_forward(params, nl, nl, &dd, precision, act_scales, &td);
+    or_mlp_forward(params, or_stride(s), nl, nl, &dd, precision, act_scales, &td);
     for (int i = 0; i < P; ++i) {
         mu[i] = td.a[nl][i];
         logvar[i] = or_clamp_lv(td.a[nl][P + i]);
@@ -340,7 +364,7 @@ void or_cvae_act_scales(const or_cvae_shape* s, const double* params, const doub
         memset(&td, 0, sizeof td);
         for (int k = 0; k < L; ++k) td.a[0][k] = nrm[k];
         for (int k = 0; k < C; ++k) td.a[0][L + k] = (cond[i * C + k] - stats[k]) / stats[16 + k];
-        or_mlp_forward(params, nl, nl, &dd, OR_PREC_FP64, NULL, &td);
+        or_mlp_forward(params, or_stride(s), nl, nl, &dd, OR_PREC_FP64, NULL, &td);
         for (int j = 0; j < nl; ++j)
             for (int k = 0; k < dd.n_in[j]; ++k) mx[j] = fmax(mx[j], fabs(td.a[j][k]));
     }

@@ -88,9 +88,8 @@ typedef struct {
 int or_random_walk(const or_walk_desc* d, const or_walk_out* o);
 
 /* ---------------- CVAE (cvae.c) ---------------- */
-#define OR_TILE 16
-#define OR_LAYER_FLOATS (OR_TILE * OR_TILE + OR_TILE)
-#define OR_CVAE_PARAMS (6 * OR_LAYER_FLOATS)
+/* Widest layer (hidden units, network inputs or outputs) of any shape. */
+#define OR_MAX_WIDTH 32
 
 typedef struct {
     int32_t model;   /* 0 LengthGen, 1 PathGen, 2 EventGen */
@@ -103,6 +102,9 @@ double or_softplus(double x);
 double or_round_bf16(double x);
 double or_round_fp8_e4m3(double x);
 
+/* Parameters of a shape: 2 n_linear layers of S x S weights and S biases,
+ * S = 16 if every network width is at most 16, else 32 (see cvae.c). */
+int64_t or_cvae_param_count(const or_cvae_shape* s);
 void or_cvae_init(const or_cvae_shape* s, uint64_t seed, double* params);
 
 /* Mean KL + NLL over the batch; grad (may be NULL) receives the gradient of

@@ -38,6 +38,27 @@ __device__ __forceinline__ void normals4(const Rng& r, uint32_t c0, float* n) {
 struct LayerDims {
     int n_in, n_out;
 };
+
+// Feature blocks per layer dimension: every layer is stored and computed as
+// a (16 T) x (16 T) grid of 16 x 16 MFMA tiles, T = 1 when all of the
+// network's widths (hidden units, both networks' inputs and outputs) fit one
+// tile and T = 2 up to 32 (Table 1's widest settings: 20 hidden units, or
+// 2 x 9 encoder outputs).
+__host__ __device__ inline int shape_blocks(const Shape& s) {
+    int m = s.width;
+    m = m > s.p_out + s.p_in ? m : s.p_out + s.p_in;
+    m = m > s.latent + s.p_in ? m : s.latent + s.p_in;
+    m = m > 2 * s.p_out ? m : 2 * s.p_out;
+    m = m > 2 * s.latent ? m : 2 * s.latent;
+    return m <= kTile ? 1 : 2;
+}
+// Floats of one layer: (16 T)^2 row-major weights, then 16 T biases.
+__host__ __device__ inline int layer_floats(const Shape& s) {
+    const int S = kTile * shape_blocks(s);
+    return S * S + S;
+}
+constexpr int kMaxBlocks = 2;
+constexpr int kMaxLayerFloats = (kTile * kMaxBlocks) * (kTile * kMaxBlocks) + kTile * kMaxBlocks;
 __host__ __device__ inline LayerDims layer_dims(const Shape& s, int layer) {
     const int nl = s.n_linear;
     const bool dec = layer >= nl;
@@ -50,14 +71,15 @@ __host__ __device__ inline LayerDims layer_dims(const Shape& s, int layer) {
 __global__ void cvae_init_kernel(Shape s, uint64_t seed, float* master, int n_params) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n_params) return;
-    const int layer = p / kLayerFloats, flat = p % kLayerFloats;
+    const int lf = layer_floats(s), S = kTile * shape_blocks(s);
+    const int layer = p / lf, flat = p % lf;
     const LayerDims d = layer_dims(s, layer);
     int row, col;
-    if (flat < kTile * kTile) {
-        row = flat / kTile;
-        col = flat % kTile;
+    if (flat < S * S) {
+        row = flat / S;
+        col = flat % S;
     } else {
-        row = flat - kTile * kTile;
+        row = flat - S * S;
         col = 0;
     }
     float v = 0.0f;
@@ -242,87 +264,126 @@ struct TrainArgs {
     double* loss_partial; // [blocks][2]
 };
 
-// Per-wave LDS: inputs of the 6 layers and two work tiles.
+// Per-wave LDS: inputs of the 2 NL layers and two work buffers, each 16 T
+// feature rows (T stacked 16 x 16 tiles) of 16 samples.
+template <int T>
 struct WaveLds {
-    float act[2 * kMaxNL][kTile * kTile];
-    float work[2][kTile * kTile];
+    float act[2 * kMaxNL][kTile * kTile * T];
+    float work[2][kTile * kTile * T];
 };
 
-__device__ __forceinline__ bf16x4 w_frag(const float* layer) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(layer + frag_row() * kTile + frag_k0());
+// Weight fragments of block (o, k) of a layer with row stride 16 T: the A
+// operand of the forward product (output rows 16 o .., input columns
+// 16 k ..), its transpose (for dX = W^T dPre) and the biases of output block o.
+template <int T>
+__device__ __forceinline__ bf16x4 w_frag(const float* layer, int o, int k) {
+    constexpr int S = kTile * T;
+    const f32x4 v = *reinterpret_cast<const f32x4*>(layer + (kTile * o + frag_row()) * S + kTile * k + frag_k0());
     return to_bf16x4(v);
 }
-__device__ __forceinline__ bf16x4 wt_frag(const float* layer) {
-    const int c = frag_row(), k0 = frag_k0();
-    return to_bf16x4(layer[(k0 + 0) * kTile + c], layer[(k0 + 1) * kTile + c], layer[(k0 + 2) * kTile + c],
-                     layer[(k0 + 3) * kTile + c]);
+template <int T>
+__device__ __forceinline__ bf16x4 wt_frag(const float* layer, int o, int k) {
+    constexpr int S = kTile * T;
+    const float* p = layer + (kTile * o + frag_k0()) * S + kTile * k + frag_row();
+    return to_bf16x4(p[0], p[S], p[2 * S], p[3 * S]);
 }
-__device__ __forceinline__ f32x4 bias_d(const float* layer) {
-    const int k0 = frag_k0();
-    const float* b = layer + kTile * kTile;
-    return f32x4{b[k0], b[k0 + 1], b[k0 + 2], b[k0 + 3]};
+template <int T>
+__device__ __forceinline__ f32x4 bias_d(const float* layer, int o) {
+    constexpr int S = kTile * T;
+    const float* b = layer + S * S + kTile * o + frag_k0();
+    return f32x4{b[0], b[1], b[2], b[3]};
 }
 
-// Forward of one net (NL layers starting at FIRST) from act[FIRST].  Hidden
-// units at or beyond `width` do not exist: their activations are forced to 0,
-// so their (zero-initialised) weights and biases receive zero gradients.
-template <int FIRST, int NL>
-__device__ __forceinline__ f32x4 net_forward(const bf16x4* wf, const f32x4* bs, WaveLds& L, f32x4* pre, int width) {
-    constexpr int first = FIRST, nl = NL;
+// Forward of one net (NL layers starting at FIRST) from act[FIRST]; the last
+// layer's output blocks go to `out`.  Hidden units at or beyond `width` do
+// not exist: their activations are forced to 0, so their (zero-initialised)
+// weights and biases receive zero gradients.
+template <int FIRST, int NL, int T>
+__device__ __forceinline__ void net_forward(const bf16x4 (*wf)[T][T], const f32x4 (*bs)[T], WaveLds<T>& L,
+                                            f32x4 (*pre)[T], int width, f32x4* out) {
     const int k0 = frag_k0();
-    f32x4 acc;
 #pragma unroll
-    for (int j = 0; j < nl; ++j) {
-        const bf16x4 x = to_bf16x4(tile_load_d(L.act[first + j]));
-        acc = mfma_bf16(wf[first + j], x, bs[first + j]);
-        pre[first + j] = acc;
-        if (j < nl - 1) {
-            f32x4 a;
+    for (int j = 0; j < NL; ++j) {
+        const int layer = FIRST + j;
+        bf16x4 x[T];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = k0 + q < width ? bf16_round(softplus(acc[q])) : 0.0f;
-            tile_store_d(L.act[first + j + 1], a);
+        for (int k = 0; k < T; ++k) x[k] = to_bf16x4(tile_load_d(L.act[layer] + kTile * kTile * k));
+#pragma unroll
+        for (int o = 0; o < T; ++o) {
+            f32x4 acc = bs[layer][o];
+#pragma unroll
+            for (int k = 0; k < T; ++k) acc = mfma_bf16(wf[layer][o][k], x[k], acc);
+            pre[layer][o] = acc;
+            out[o] = acc;
+        }
+        if (j < NL - 1) {
+#pragma unroll
+            for (int o = 0; o < T; ++o) {
+                f32x4 a;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    a[q] = kTile * o + k0 + q < width ? bf16_round(softplus(pre[layer][o][q])) : 0.0f;
+                tile_store_d(L.act[layer + 1] + kTile * kTile * o, a);
+            }
             wave_sync();
         }
     }
-    return acc;
 }
 
 // Backward of one net given d loss / d (last linear output) in D layout.
 // Accumulates dW (D layout: row = output unit, column = input unit) and db,
-// and returns d loss / d (input of the first layer) in D layout.
-template <int FIRST, int NL>
-__device__ __forceinline__ f32x4 net_backward(const bf16x4* wt, WaveLds& L, const f32x4* pre, f32x4 dpre,
-                                              f32x4* dw, f32x4* db) {
-    constexpr int first = FIRST, nl = NL;
-    f32x4 dx = f32x4{0, 0, 0, 0};
+// and writes d loss / d (input of the first layer) in D layout to dx.
+template <int FIRST, int NL, int T>
+__device__ __forceinline__ void net_backward(const bf16x4 (*wt)[T][T], WaveLds<T>& L, const f32x4 (*pre)[T],
+                                             f32x4* dpre, f32x4 (*dw)[T][T], f32x4 (*db)[T], f32x4* dx) {
 #pragma unroll
-    for (int j = nl - 1; j >= 0; --j) {
-        const int layer = first + j;
-        db[layer] += dpre;
-        // dW += dPre X^T: both operands read transposed from LDS
-        tile_store_d(L.work[0], f32x4{bf16_round(dpre[0]), bf16_round(dpre[1]), bf16_round(dpre[2]),
-                                      bf16_round(dpre[3])});
+    for (int j = NL - 1; j >= 0; --j) {
+        const int layer = FIRST + j;
+#pragma unroll
+        for (int o = 0; o < T; ++o) {
+            db[layer][o] += dpre[o];
+            // dW += dPre X^T: both operands read transposed from LDS
+            tile_store_d(L.work[0] + kTile * kTile * o, f32x4{bf16_round(dpre[o][0]), bf16_round(dpre[o][1]),
+                                                               bf16_round(dpre[o][2]), bf16_round(dpre[o][3])});
+        }
         wave_sync();
-        const bf16x4 a = to_bf16x4(tile_load_t(L.work[0]));
-        const bf16x4 b = to_bf16x4(tile_load_t(L.act[layer]));
-        dw[layer] = mfma_bf16(a, b, dw[layer]);
+#pragma unroll
+        for (int o = 0; o < T; ++o) {
+            const bf16x4 a = to_bf16x4(tile_load_t(L.work[0] + kTile * kTile * o));
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                const bf16x4 b = to_bf16x4(tile_load_t(L.act[layer] + kTile * kTile * k));
+                dw[layer][o][k] = mfma_bf16(a, b, dw[layer][o][k]);
+            }
+        }
         wave_sync();
         // dX = W^T dPre
-        dx = mfma_bf16(wt[layer], to_bf16x4(dpre), f32x4{0, 0, 0, 0});
-        if (j > 0) {
-            const f32x4 p = pre[layer - 1];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dpre[q] = dx[q] * sigmoid(p[q]);
+        for (int k = 0; k < T; ++k) {
+            f32x4 acc = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int o = 0; o < T; ++o) acc = mfma_bf16(wt[layer][o][k], to_bf16x4(dpre[o]), acc);
+            dx[k] = acc;
+        }
+        if (j > 0) {
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dpre[k][q] = dx[k][q] * sigmoid(pre[layer - 1][k][q]);
+            }
         }
     }
-    return dx;
 }
 
-template <int NL>
+template <int NL, int T>
 __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
-    __shared__ WaveLds lds_all[kTrainWaves];
+    constexpr int TT = kTile * kTile * T;  // floats of one activation buffer
+    constexpr int S = kTile * T;           // row stride of a layer's weights
+    constexpr int LF = S * S + S;          // floats per layer
+    constexpr int kLat = 8 * T;            // latent sizes up to 8 T (2 L <= 16 T)
+    __shared__ WaveLds<T> lds_all[kTrainWaves];
     const int wave = threadIdx.x >> 6;
-    WaveLds& L = lds_all[wave];
+    WaveLds<T>& L = lds_all[wave];
     const Shape s = a.s;
     constexpr int nl = NL;
     const int P = s.p_out, Lt = s.latent, C = s.p_in;
@@ -331,20 +392,30 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
 
     // all layers' weight fragments (both orientations) and biases of this
     // lane, loaded once: the tile loop is a chain of dependent steps
-    bf16x4 wf[2 * NL], wt[2 * NL];
-    f32x4 bs[2 * NL];
+    bf16x4 wf[2 * NL][T][T], wt[2 * NL][T][T];
+    f32x4 bs[2 * NL][T];
 #pragma unroll
     for (int i = 0; i < 2 * NL; ++i) {
-        const float* layer = a.master + i * kLayerFloats;
-        wf[i] = w_frag(layer);
-        wt[i] = wt_frag(layer);
-        bs[i] = bias_d(layer);
+        const float* layer = a.master + i * LF;
+#pragma unroll
+        for (int o = 0; o < T; ++o) {
+            bs[i][o] = bias_d<T>(layer, o);
+#pragma unroll
+            for (int k = 0; k < T; ++k) {
+                wf[i][o][k] = w_frag<T>(layer, o, k);
+                wt[i][o][k] = wt_frag<T>(layer, o, k);
+            }
+        }
     }
-    f32x4 dw[2 * NL], db[2 * NL], pre[2 * NL];
+    f32x4 dw[2 * NL][T][T], db[2 * NL][T], pre[2 * NL][T];
 #pragma unroll
     for (int i = 0; i < 2 * NL; ++i) {
-        dw[i] = f32x4{0, 0, 0, 0};
-        db[i] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int o = 0; o < T; ++o) {
+            db[i][o] = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < T; ++k) dw[i][o][k] = f32x4{0, 0, 0, 0};
+        }
     }
     double kl_acc = 0.0, nll_acc = 0.0;
 
@@ -353,13 +424,13 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
     const int n_waves = gridDim.x * kTrainWaves;
     for (int tile = wave_global; tile < n_tiles; tile += n_waves) {
         const int b = tile * kTile + (lane & 15);  // sample of this lane's column
-        // zero the two input tiles, then gather (target, cond) rows
-        for (int q = lane; q < kTile * kTile; q += 64) {
+        // zero the two input buffers, then gather (target, cond) rows
+        for (int q = lane; q < TT; q += 64) {
             L.act[0][q] = 0.0f;
             L.act[nl][q] = 0.0f;
         }
         wave_sync();
-        float mu_z[8], lv_z[8], lvr_z[8], eps[8];
+        float mu_z[kLat], lv_z[kLat], lvr_z[kLat], eps[kLat];
         if (lane < 16) {
             int64_t row = b;
             if (a.sample_rows) {
@@ -375,8 +446,10 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
         }
         wave_sync();
         // encoder
-        const f32x4 oe = net_forward<0, NL>(wf, bs, L, pre, s.width);
-        tile_store_d(L.work[0], oe);
+        f32x4 oe[T];
+        net_forward<0, NL, T>(wf, bs, L, pre, s.width, oe);
+#pragma unroll
+        for (int o = 0; o < T; ++o) tile_store_d(L.work[0] + kTile * kTile * o, oe[o]);
         wave_sync();
         if (lane < 16) {
             const Rng rr = make_rng(a.seed, MS_TAG_CVAE_REPARAM, a.id_offset + (uint64_t)b);
@@ -394,9 +467,11 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
         }
         wave_sync();
         // decoder
-        const f32x4 od = net_forward<NL, NL>(wf, bs, L, pre, s.width);
-        tile_store_d(L.work[0], od);
-        for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
+        f32x4 od[T];
+        net_forward<NL, NL, T>(wf, bs, L, pre, s.width, od);
+#pragma unroll
+        for (int o = 0; o < T; ++o) tile_store_d(L.work[0] + kTile * kTile * o, od[o]);
+        for (int q = lane; q < TT; q += 64) L.work[1][q] = 0.0f;
         wave_sync();
         if (lane < 16) {
             int64_t row = b;
@@ -418,9 +493,13 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             nll_acc += (double)nll;
         }
         wave_sync();
-        const f32x4 dzc = net_backward<NL, NL>(wt, L, pre, tile_load_d(L.work[1]), dw, db);
-        tile_store_d(L.work[0], dzc);
-        for (int q = lane; q < kTile * kTile; q += 64) L.work[1][q] = 0.0f;
+        f32x4 dcur[T], dzc[T];
+#pragma unroll
+        for (int o = 0; o < T; ++o) dcur[o] = tile_load_d(L.work[1] + kTile * kTile * o);
+        net_backward<NL, NL, T>(wt, L, pre, dcur, dw, db, dzc);
+#pragma unroll
+        for (int o = 0; o < T; ++o) tile_store_d(L.work[0] + kTile * kTile * o, dzc[o]);
+        for (int q = lane; q < TT; q += 64) L.work[1][q] = 0.0f;
         wave_sync();
         if (lane < 16) {
             for (int i = 0; i < Lt; ++i) {
@@ -433,7 +512,9 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
             }
         }
         wave_sync();
-        net_backward<0, NL>(wt, L, pre, tile_load_d(L.work[1]), dw, db);
+#pragma unroll
+        for (int o = 0; o < T; ++o) dcur[o] = tile_load_d(L.work[1] + kTile * kTile * o);
+        net_backward<0, NL, T>(wt, L, pre, dcur, dw, db, dzc);
         wave_sync();
     }
 
@@ -441,38 +522,51 @@ __global__ __launch_bounds__(256) void cvae_train_kernel(const TrainArgs a) {
 #pragma unroll
     for (int i = 0; i < 2 * nl; ++i) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float v = db[i][q];
-            v += __shfl_xor(v, 1);
-            v += __shfl_xor(v, 2);
-            v += __shfl_xor(v, 4);
-            v += __shfl_xor(v, 8);
-            db[i][q] = v;
+        for (int o = 0; o < T; ++o) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float v = db[i][o][q];
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 8);
+                db[i][o][q] = v;
+            }
         }
     }
-    __syncthreads();
-    // block reduction in a fixed order through LDS (reuses the tile space)
-    const int n_params = 2 * nl * kLayerFloats;
-    float* red = reinterpret_cast<float*>(lds_all);  // [kTrainWaves][n_params]
-    {
-        float* mine = red + wave * n_params;
-        const int c = frag_row(), k0 = frag_k0();
+    // block reduction through LDS (reusing the tile space): the waves add
+    // their gradients into one buffer one after the other, a fixed order
+    const int n_params = 2 * nl * LF;
+    float* red = reinterpret_cast<float*>(lds_all);  // [n_params]
+    static_assert(sizeof(lds_all) >= sizeof(float) * 2 * kMaxNL * LF, "gradient buffer exceeds the LDS tiles");
+    const int c = frag_row(), k0 = frag_k0();
+    for (int w = 0; w < kTrainWaves; ++w) {
+        __syncthreads();
+        if (wave != w) continue;
 #pragma unroll
         for (int i = 0; i < 2 * nl; ++i) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) mine[i * kLayerFloats + (k0 + q) * kTile + c] = dw[i][q];
-            if (c == 0) {
+            for (int o = 0; o < T; ++o) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) mine[i * kLayerFloats + kTile * kTile + k0 + q] = db[i][q];
+                for (int k = 0; k < T; ++k) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float& dst = red[i * LF + (kTile * o + k0 + q) * S + kTile * k + c];
+                        dst = w == 0 ? dw[i][o][k][q] : dst + dw[i][o][k][q];
+                    }
+                }
+                if (c == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float& dst = red[i * LF + S * S + kTile * o + k0 + q];
+                        dst = w == 0 ? db[i][o][q] : dst + db[i][o][q];
+                    }
+                }
             }
         }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < n_params; p += blockDim.x) {
-        float acc = 0.0f;
-        for (int w = 0; w < kTrainWaves; ++w) acc += red[w * n_params + p];
-        a.partial[(int64_t)blockIdx.x * n_params + p] = acc;
-    }
+    for (int p = threadIdx.x; p < n_params; p += blockDim.x) a.partial[(int64_t)blockIdx.x * n_params + p] = red[p];
     // loss partials: lanes 0..15 of each wave hold sums
     __syncthreads();
     double* dred = reinterpret_cast<double*>(lds_all);
@@ -596,26 +690,27 @@ __device__ __forceinline__ uint32_t fp8_e4m3_bits(float x) {
 __global__ __launch_bounds__(256) void cvae_calib_kernel(Shape s, const float* master, const double* stats,
                                                          const float* cond, int64_t n, PackedModel* pm) {
     const int nl = s.n_linear, L = s.latent, C = s.p_in;
+    const int S = kTile * shape_blocks(s), lf = layer_floats(s);
     float mx[kMaxLayers] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        float a[kTile], nrm[8];
+        float a[2 * kTile], nrm[2 * kTile];
         const Rng r = make_rng(0, MS_TAG_CVAE_SAMPLE, (uint64_t)i);
         for (int j = 0; 4 * j < L; ++j) normals4(r, (uint32_t)j, nrm + 4 * j);
-        for (int k = 0; k < kTile; ++k) a[k] = 0.0f;
+        for (int k = 0; k < 2 * kTile; ++k) a[k] = 0.0f;
         for (int k = 0; k < L; ++k) a[k] = nrm[k];
         for (int k = 0; k < C; ++k) a[L + k] = (float)((cond[i * C + k] - stats[k]) / stats[16 + k]);
         for (int j = 0; j < nl; ++j) {
             const LayerDims d = layer_dims(s, nl + j);
             for (int k = 0; k < d.n_in; ++k) mx[j] = fmaxf(mx[j], fabsf(a[k]));
             if (j == nl - 1) break;
-            const float* layer = master + (nl + j) * kLayerFloats;
-            float o[kTile];
+            const float* layer = master + (nl + j) * lf;
+            float o[2 * kTile];
             for (int row = 0; row < d.n_out; ++row) {
-                float acc = layer[kTile * kTile + row];
-                for (int k = 0; k < d.n_in; ++k) acc = fmaf(layer[row * kTile + k], a[k], acc);
+                float acc = layer[S * S + row];
+                for (int k = 0; k < d.n_in; ++k) acc = fmaf(layer[row * S + k], a[k], acc);
                 o[row] = softplus(acc);
             }
-            for (int k = 0; k < kTile; ++k) a[k] = k < d.n_out ? o[k] : 0.0f;
+            for (int k = 0; k < 2 * kTile; ++k) a[k] = k < d.n_out ? o[k] : 0.0f;
         }
     }
     __shared__ float red[kMaxLayers][256];
@@ -644,6 +739,7 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
                                  PackedModel* pm) {
     const int lane = threadIdx.x;  // 64 threads
     const int nl = s.n_linear;
+    const int T = shape_blocks(s), S = kTile * T, lf = layer_floats(s);
     if (lane == 0) {
         pm->magic = (int32_t)kPackedMagic;
         pm->model = s.model;
@@ -653,6 +749,8 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
         pm->width = s.width;
         pm->n_linear = nl;
         pm->precision = precision;
+        pm->blocks = T;
+        pm->pad_[0] = pm->pad_[1] = pm->pad_[2] = 0;
     }
     if (lane < 16) {
         pm->mean_c[lane] = stats ? (float)stats[lane] : 0.0f;
@@ -663,11 +761,11 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
     __shared__ float smax[64];
     for (int j = 0; j < kMaxLayers; ++j) {
         const bool real = j < nl;
-        const float* layer = master + (nl + (real ? j : 0)) * kLayerFloats;
+        const float* layer = master + (nl + (real ? j : 0)) * lf;
         float scale = 1.0f;
         if (precision == MS_PREC_FP8) {
             float mx = 0.0f;
-            for (int q = lane; q < kTile * kTile; q += 64) mx = fmaxf(mx, real ? fabsf(layer[q]) : 0.0f);
+            for (int q = lane; q < S * S; q += 64) mx = fmaxf(mx, real ? fabsf(layer[q]) : 0.0f);
             smax[lane] = mx;
             __syncthreads();
             for (int off = 32; off > 0; off >>= 1) {
@@ -682,25 +780,37 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
             pm->in_scale[j] = in_sc;
             pm->out_scale[j] = scale / in_sc;  // s_w s_a, exact: s_a is a power of two
         }
-        if (lane < 16) pm->bias[j][lane] = real ? layer[kTile * kTile + lane] : 0.0f;
+        if (lane < 2 * kTile) {
+            const float b = real && lane < S ? layer[S * S + lane] : 0.0f;
+            if (lane < kTile) pm->bias[j][lane] = b;
+            else pm->bias_hi[j][lane - kTile] = b;
+        }
         const int r = lane & 15, kg = lane >> 4;
-        uint32_t w0 = 0, w1 = 0;
-        if (real) {
-            if (precision == MS_PREC_FP8) {
-                // K = 32 operand in the permuted order of decoder_tile_fp8:
-                // bytes 0..3 = columns 4 kg .. 4 kg + 3, bytes 4..7 = 0
-                uint32_t bytes[4];
-                for (int q = 0; q < 4; ++q) bytes[q] = fp8_e4m3_bits(layer[r * kTile + 4 * kg + q] / scale);
-                w0 = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | (bytes[3] << 24);
-                w1 = 0u;
-            } else {
-                const float* row = layer + r * kTile + 4 * kg;
+        for (int ti = 0; ti < 4; ++ti) {
+            uint32_t w0 = 0, w1 = 0;
+            if (real && precision == MS_PREC_FP8 && ti < T) {
+                // K = 32 operand in the permuted order of the FP8 decoders:
+                // bytes 0..3 = columns 4 kg .. 4 kg + 3 of input block 0,
+                // bytes 4..7 = the same columns of input block 1 (0 when
+                // the layer has one block)
+                const float* row = layer + (kTile * ti + r) * S + 4 * kg;
+                uint32_t lo[4], hi[4];
+                for (int q = 0; q < 4; ++q) {
+                    lo[q] = fp8_e4m3_bits(row[q] / scale);
+                    hi[q] = T == 2 ? fp8_e4m3_bits(row[kTile + q] / scale) : 0u;
+                }
+                w0 = lo[0] | (lo[1] << 8) | (lo[2] << 16) | (lo[3] << 24);
+                w1 = hi[0] | (hi[1] << 8) | (hi[2] << 16) | (hi[3] << 24);
+            } else if (real && precision != MS_PREC_FP8 && ti < T * T) {
+                const int o = ti >> 1, k = ti & 1;
+                const float* row = layer + (kTile * o + r) * S + kTile * k + 4 * kg;
                 w0 = (uint32_t)bf16_bits(row[0]) | ((uint32_t)bf16_bits(row[1]) << 16);
                 w1 = (uint32_t)bf16_bits(row[2]) | ((uint32_t)bf16_bits(row[3]) << 16);
             }
+            uint32_t* dst = ti == 0 ? pm->frag[j][lane] : pm->frag_hi[j][ti - 1][lane];
+            dst[0] = w0;
+            dst[1] = w1;
         }
-        pm->frag[j][lane][0] = w0;
-        pm->frag[j][lane][1] = w1;
     }
 }
 
@@ -709,15 +819,19 @@ __global__ void cvae_pack_kernel(Shape s, const float* master, const double* sta
 
 constexpr int kSampleWaves = 4;
 
+template <int T>
 struct SampleLds {
-    float x[64][kTile];
-    float o[64][kTile];
+    float x[64][kTile * T];
+    float o[64][kTile * T];
 };
 
+// T: tiles per layer dimension of the packed model (pm->blocks).
+template <int T>
 __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm, const float* cond, int64_t n,
                                                           uint64_t seed, uint64_t id_offset, float* out) {
-    __shared__ SampleLds lds_all[kSampleWaves];
-    SampleLds& L = lds_all[threadIdx.x >> 6];
+    if ((pm->blocks == 2) != (T == 2)) return;
+    __shared__ SampleLds<T> lds_all[kSampleWaves];
+    SampleLds<T>& L = lds_all[threadIdx.x >> 6];
     const int lane = lane_id();
     const int P = pm->p_out, Lt = pm->latent, C = pm->p_in;
     const int64_t n_chunks = (n + 63) / 64;
@@ -729,8 +843,8 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
     for (int64_t chunk = wave_global; chunk < n_chunks; chunk += n_waves) {
         const int64_t i = chunk * 64 + lane;
         const bool valid = i < n;
-        float nrm[16];
-        for (int q = 0; q < kTile; ++q) L.x[lane][q] = 0.0f;
+        float nrm[kTile * T];  // latent + p_out <= 16 T normals
+        for (int q = 0; q < kTile * T; ++q) L.x[lane][q] = 0.0f;
         if (valid) {
             const Rng r = make_rng(seed, MS_TAG_CVAE_SAMPLE, id_offset + (uint64_t)i);
             for (int j = 0; 4 * j < Lt + P; ++j) normals4(r, (uint32_t)j, nrm + 4 * j);
@@ -742,9 +856,19 @@ __global__ __launch_bounds__(256) void cvae_sample_kernel(const PackedModel* pm,
         const int n_tiles = remaining >= 64 ? 4 : (int)((remaining + 15) / 16);
         for (int t = 0; t < n_tiles; ++t) {
             const int path = 16 * t + frag_row();
-            const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
-            const f32x4 o = !three ? decoder_tile_layers(pm, xin) : fp8 ? decoder_tile_fp8(w, xin) : decoder_tile(w, xin);
-            *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+            if constexpr (T == 1) {
+                const f32x4 xin = *reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]);
+                const f32x4 o = !three ? decoder_tile_layers(pm, xin) : fp8 ? decoder_tile_fp8(w, xin)
+                                                                            : decoder_tile(w, xin);
+                *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o;
+            } else {
+                const f32x4 xin[2] = {*reinterpret_cast<const f32x4*>(&L.x[path][frag_k0()]),
+                                      *reinterpret_cast<const f32x4*>(&L.x[path][kTile + frag_k0()])};
+                f32x4 o[2];
+                decoder_tile_wide(pm, xin, o);
+                *reinterpret_cast<f32x4*>(&L.o[path][frag_k0()]) = o[0];
+                *reinterpret_cast<f32x4*>(&L.o[path][kTile + frag_k0()]) = o[1];
+            }
         }
         wave_sync();
         if (valid) {
@@ -765,11 +889,11 @@ static ms_status check_shape(const ms_cvae_shape* sh, Shape* out) {
     MS_REQUIRE(sh != nullptr, "CVAE shape is NULL");
     MS_REQUIRE(sh->model >= 0 && sh->model <= 2, "CVAE model must be 0, 1 or 2");
     MS_REQUIRE(sh->p_in >= 1 && sh->p_out >= 1 && sh->latent >= 1 && sh->width >= 1, "CVAE sizes must be positive");
-    if (sh->width > 16 || sh->p_out + sh->p_in > 16 || sh->latent + sh->p_in > 16 || 2 * sh->p_out > 16 ||
-        2 * sh->latent > 16 || sh->n_linear < 2 || sh->n_linear > kMaxNL)
+    if (sh->width > 32 || sh->p_out + sh->p_in > 32 || sh->latent + sh->p_in > 32 || 2 * sh->p_out > 32 ||
+        2 * sh->latent > 32 || sh->p_in > 16 || sh->n_linear < 2 || sh->n_linear > kMaxNL)
         return set_error(MS_ERR_UNSUPPORTED,
-                         "CVAE shape unsupported: needs width <= 16, 2 <= n_linear <= 4, "
-                         "p_out + p_in <= 16, latent + p_in <= 16, 2 p_out <= 16, 2 latent <= 16");
+                         "CVAE shape unsupported: needs width <= 32, 2 <= n_linear <= 4, p_in <= 16, "
+                         "p_out + p_in <= 32, latent + p_in <= 32, 2 p_out <= 32, 2 latent <= 32");
     *out = Shape{sh->model, sh->p_in, sh->p_out, sh->latent, sh->width, sh->n_linear};
     return MS_OK;
 }
@@ -793,11 +917,11 @@ constexpr size_t train_scratch_bytes(int nb, int n_params) {
 }
 
 // Device-resident scratch of cvae_train_step_noalloc, sized for the largest
-// batch and network the training kernels accept (about 2.2 MB); each device
+// batch and network the training kernels accept (about 8.7 MB); each device
 // holds its own copy for the life of the process.  Host code must not pass
 // this name to a kernel: it is a host-side stand-in, not a device address.
 // Its per-device address comes from hipGetSymbolAddress (noalloc_scratch).
-constexpr size_t kTrainScratchBytes = train_scratch_bytes(train_blocks(kMaxTrainBatch), 2 * kMaxNL * kLayerFloats);
+constexpr size_t kTrainScratchBytes = train_scratch_bytes(train_blocks(kMaxTrainBatch), 2 * kMaxNL * kMaxLayerFloats);
 static __device__ __align__(256) unsigned char scratch[kTrainScratchBytes];
 
 }  // namespace msst
@@ -809,7 +933,7 @@ ms_status cvae_param_count(const ms_cvae_shape* shape, size_t* n_floats) {
     ms_status st = msst::check_shape(shape, &s);
     if (st != MS_OK) return st;
     MS_REQUIRE(n_floats != nullptr, "cvae_param_count: n_floats is NULL");
-    *n_floats = (size_t)(2 * s.n_linear * msst::kLayerFloats);
+    *n_floats = (size_t)(2 * s.n_linear * msst::layer_floats(s));
     return MS_OK;
 }
 
@@ -821,7 +945,7 @@ ms_status cvae_init(const ms_cvae_shape* shape, uint64_t seed, float* master_dev
     MS_REQUIRE(master_dev != nullptr, "cvae_init: master_dev is NULL");
     int cus;
     if ((st = device_cu_count(&cus)) != MS_OK) return st;
-    const int n = 2 * s.n_linear * kLayerFloats;
+    const int n = 2 * s.n_linear * layer_floats(s);
     hipLaunchKernelGGL(cvae_init_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, s, seed,
                        master_dev, n);
     MS_LAUNCHED();
@@ -921,7 +1045,7 @@ ms_status cvae_workspace_size(const ms_cvae_shape* shape, int32_t batch, size_t*
     if (st != MS_OK) return st;
     MS_REQUIRE(bytes != nullptr, "cvae_workspace_size: bytes is NULL");
     MS_REQUIRE(batch > 0 && batch % 16 == 0 && batch <= kMaxTrainBatch, "cvae_workspace_size: batch must be a positive multiple of 16, <= 2^20");
-    *bytes = train_scratch_bytes(train_blocks(batch), 2 * s.n_linear * kLayerFloats);
+    *bytes = train_scratch_bytes(train_blocks(batch), 2 * s.n_linear * layer_floats(s));
     return MS_OK;
 }
 
@@ -974,7 +1098,7 @@ static ms_status train_step_launch(const char* who, bool noalloc, const ms_cvae_
                    "%s: invalid AdamW hyper-parameters", who);
     }
     const int nb = train_blocks(batch);
-    const int n_params = 2 * s.n_linear * kLayerFloats;
+    const int n_params = 2 * s.n_linear * layer_floats(s);
     const size_t need = train_scratch_bytes(nb, n_params);
     if (!noalloc) {
         MS_REQUIRE(ws_dev != nullptr, "%s: workspace is NULL", who);
@@ -1004,10 +1128,19 @@ static ms_status train_step_launch(const char* who, bool noalloc, const ms_cvae_
     ta.partial = reinterpret_cast<float*>(ws_dev);
     ta.loss_partial = reinterpret_cast<double*>(reinterpret_cast<char*>(ws_dev) + train_partial_bytes(nb, n_params));
     hipStream_t hs = (hipStream_t)stream;
-    switch (s.n_linear) {
-        case 2: hipLaunchKernelGGL(cvae_train_kernel<2>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
-        case 3: hipLaunchKernelGGL(cvae_train_kernel<3>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
-        default: hipLaunchKernelGGL(cvae_train_kernel<4>, dim3(nb), dim3(64 * kTrainWaves), 0, hs, ta); break;
+    const dim3 grid(nb), block(64 * kTrainWaves);
+    if (shape_blocks(s) == 1) {
+        switch (s.n_linear) {
+            case 2: hipLaunchKernelGGL((cvae_train_kernel<2, 1>), grid, block, 0, hs, ta); break;
+            case 3: hipLaunchKernelGGL((cvae_train_kernel<3, 1>), grid, block, 0, hs, ta); break;
+            default: hipLaunchKernelGGL((cvae_train_kernel<4, 1>), grid, block, 0, hs, ta); break;
+        }
+    } else {
+        switch (s.n_linear) {
+            case 2: hipLaunchKernelGGL((cvae_train_kernel<2, 2>), grid, block, 0, hs, ta); break;
+            case 3: hipLaunchKernelGGL((cvae_train_kernel<3, 2>), grid, block, 0, hs, ta); break;
+            default: hipLaunchKernelGGL((cvae_train_kernel<4, 2>), grid, block, 0, hs, ta); break;
+        }
     }
     MS_LAUNCHED();
     AdamArgs aa{};
@@ -1103,8 +1236,13 @@ ms_status cvae_sample(const void* packed_dev, const float* cond_dev, int64_t n, 
     if (st != MS_OK) return st;
     int64_t blocks = (n + 64 * kSampleWaves - 1) / (64 * kSampleWaves);
     if (blocks > cus * 8) blocks = cus * 8;
-    hipLaunchKernelGGL(cvae_sample_kernel, dim3((unsigned)blocks), dim3(64 * kSampleWaves), 0, (hipStream_t)stream,
-                       reinterpret_cast<const PackedModel*>(packed_dev), cond_dev, n, seed, id_offset, out_dev);
+    // the packed model's block count is on the device: each instance returns
+    // at once unless it matches
+    const PackedModel* pm = reinterpret_cast<const PackedModel*>(packed_dev);
+    hipLaunchKernelGGL(cvae_sample_kernel<1>, dim3((unsigned)blocks), dim3(64 * kSampleWaves), 0, (hipStream_t)stream,
+                       pm, cond_dev, n, seed, id_offset, out_dev);
+    hipLaunchKernelGGL(cvae_sample_kernel<2>, dim3((unsigned)blocks), dim3(64 * kSampleWaves), 0, (hipStream_t)stream,
+                       pm, cond_dev, n, seed, id_offset, out_dev);
     MS_LAUNCHED();
     clear_error();
     return MS_OK;

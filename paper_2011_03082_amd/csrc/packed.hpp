@@ -22,9 +22,24 @@ struct PackedModel {
     float in_scale[kMaxLayers];
     float bias[kMaxLayers][16];
     // A-operand fragments per decoder layer and lane: 4 bfloat16 (BF16) or
-    // 8 FP8 E4M3 values of weight row l % 16 (FP8 uses K = 32, upper half 0).
+    // 8 FP8 E4M3 values of weight row l % 16 (FP8 uses K = 32, upper half 0
+    // for one-block layers).
     uint32_t frag[kMaxLayers][64][2];
+    // Two-block layers only (32 features in two 16-row blocks): biases of
+    // output rows 16..31 and the other tiles.  BF16 tile t = 2 o + k (t = 0
+    // in frag, t = 1..3 in frag_hi[t - 1]) is the weight block of output
+    // block o and input block k; FP8 tile o (frag, frag_hi[0]) is output
+    // block o, its K = 32 covering both input blocks (bytes 0..3 block 0,
+    // bytes 4..7 block 1).
+    float bias_hi[kMaxLayers][16];
+    uint32_t frag_hi[kMaxLayers][3][64][2];
+    int32_t blocks;  // 16 x 16 tiles per layer dimension, 1 or 2
+    int32_t pad_[3];
 };
+
+__device__ __forceinline__ const uint32_t* frag_tile(const PackedModel* pm, int layer, int t) {
+    return t == 0 ? pm->frag[layer][lane_id()] : pm->frag_hi[layer][t - 1][lane_id()];
+}
 static_assert(sizeof(PackedModel) % 16 == 0, "PackedModel must stay 16-byte sized");
 
 __device__ __forceinline__ bf16x4 load_frag_bf16(const PackedModel* pm, int layer) {
@@ -147,6 +162,52 @@ __device__ __forceinline__ f32x4 decoder_tile_layers(const PackedModel* pm, f32x
         }
     }
     return acc;
+}
+
+// Two-block decoders (Table 1's widest settings), any depth: inputs and
+// outputs are 32 features of one 16-path tile, xin[0] rows 0..15 and
+// xin[1] rows 16..31 in D layout; weights read per layer.
+__device__ __forceinline__ void decoder_tile_wide(const PackedModel* pm, const f32x4* xin, f32x4* out) {
+    const int nl = pm->n_linear;
+    const int k0 = frag_k0();
+    const bool fp8 = pm->precision == MS_PREC_FP8;
+    f32x4 x[2] = {xin[0], xin[1]};
+    for (int j = 0; j < nl; ++j) {
+        f32x4 acc[2];
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+            const f32x4 b = *reinterpret_cast<const f32x4*>(o == 0 ? &pm->bias[j][k0] : &pm->bias_hi[j][k0]);
+            if (fp8) {
+                const uint2 u = *reinterpret_cast<const uint2*>(frag_tile(pm, j, o));
+                const fp8x8 a = (fp8x8)(((uint64_t)u.y << 32) | u.x);
+                const float isc = pm->in_scale[j], sc = pm->out_scale[j];
+                const uint64_t lo = (uint32_t)to_fp8x4_lo(scaled(x[0], isc));
+                const uint64_t hi = (uint32_t)to_fp8x4_lo(scaled(x[1], isc));
+                f32x4 r = mfma_fp8(a, (fp8x8)(lo | (hi << 32)), f32x4{0, 0, 0, 0});
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = __builtin_fmaf(r[q], sc, b[q]);
+                acc[o] = r;
+            } else {
+                f32x4 r = b;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const uint2 u = *reinterpret_cast<const uint2*>(frag_tile(pm, j, 2 * o + k));
+                    r = mfma_bf16(__builtin_bit_cast(bf16x4, u), to_bf16x4(x[k]), r);
+                }
+                acc[o] = r;
+            }
+        }
+        if (j < nl - 1) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) x[o][q] = softplus(acc[o][q]);
+            }
+        } else {
+            out[0] = acc[0];
+            out[1] = acc[1];
+        }
+    }
 }
 
 }  // namespace msst

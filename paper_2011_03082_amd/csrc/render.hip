@@ -1239,7 +1239,7 @@ __global__ void render_check_models(const RenderArgs A, unsigned long long* flag
         ok &= pm->magic == (int32_t)kPackedMagic && pm->model == m && pm->latent >= 1 && pm->latent <= 8 &&
               pm->latent + pm->p_in <= 16 && pm->p_in == want_in[m] && pm->p_out == want_out[m] &&
               (pm->precision == MS_PREC_BF16 || pm->precision == MS_PREC_FP8) && pm->n_linear >= 2 &&
-              pm->n_linear <= kMaxLayers;
+              pm->n_linear <= kMaxLayers && pm->blocks == 1 && pm->width <= 16;
     }
     *flag = ok ? 0ull : 1ull;
 }

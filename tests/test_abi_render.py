@@ -90,10 +90,11 @@ def test_render_rejects_invalid_scene_camera_and_buffers(M):
 
 
 @pytest.mark.parametrize("shape", [
-    dict(model=0, p_in=2, p_out=1, latent=4, width=17, n_linear=3),
+    dict(model=0, p_in=2, p_out=1, latent=4, width=33, n_linear=3),
     dict(model=0, p_in=2, p_out=1, latent=4, width=16, n_linear=5),
     dict(model=0, p_in=2, p_out=1, latent=4, width=16, n_linear=1),
-    dict(model=2, p_in=7, p_out=6, latent=9, width=16, n_linear=3),
+    dict(model=2, p_in=7, p_out=6, latent=17, width=16, n_linear=3),
+    dict(model=2, p_in=17, p_out=6, latent=4, width=16, n_linear=3),
     dict(model=3, p_in=2, p_out=1, latent=4, width=16, n_linear=3),
 ])
 def test_cvae_rejects_unsupported_shapes(M, shape):
@@ -101,6 +102,23 @@ def test_cvae_rejects_unsupported_shapes(M, shape):
     st = M.lib().cvae_param_count(C.byref(M.cvae_shape(shape)), C.byref(n))
     assert st in (M._abi.MS_ERR_INVALID_ARGUMENT, M._abi.MS_ERR_UNSUPPORTED)
     assert M.lib().ms_last_error().decode()
+
+
+@pytest.mark.parametrize("shape, stride", [
+    (dict(model=2, p_in=7, p_out=6, latent=5, width=16, n_linear=3), 16),
+    (dict(model=2, p_in=7, p_out=6, latent=9, width=16, n_linear=3), 32),
+    (dict(model=2, p_in=7, p_out=6, latent=5, width=20, n_linear=4), 32),
+    (dict(model=1, p_in=3, p_out=3, latent=9, width=8, n_linear=2), 32),
+])
+def test_cvae_param_count_follows_the_layer_stride(M, oracle, shape, stride):
+    """2 n_linear layers of S x S weights and S biases, S = 32 once any
+    width of the two networks exceeds 16 (2 x 9 encoder outputs, 20 hidden
+    units), on both sides of the shared layout."""
+    n = C.c_size_t()
+    assert M.lib().cvae_param_count(C.byref(M.cvae_shape(shape)), C.byref(n)) == 0
+    assert n.value == 2 * shape["n_linear"] * (stride * stride + stride)
+    assert oracle.n_params(shape) == n.value
+    assert oracle.layer_stride(shape) == stride
 
 
 def test_mesh_bvh_rejects_invalid(M):

@@ -1,7 +1,10 @@
 """The architectures of Table 1 on the GPU: hidden-layer counts D in {1, 2,
-3}, widths below 16 and latent sizes 2 / 5 / 6, against the FP64 oracle --
-initialisation, bfloat16 gradients, AdamW keeping non-existent units at zero,
-BF16 / FP8 decoder sampling and the sphere tracer with such decoders."""
+3}, widths 4 to 20 and latent sizes 2 to 9 -- one 16 x 16 MFMA tile per layer
+where every width fits, a 2 x 2 grid of tiles (row stride 32) for 20 hidden
+units or 2 x 9 encoder outputs -- against the FP64 oracle: initialisation,
+bfloat16 gradients, AdamW keeping non-existent units at zero, BF16 / FP8
+decoder sampling, and the sphere tracer with one-tile decoders (two-tile ones
+are refused by the renderer)."""
 import numpy as np
 import pytest
 import torch
@@ -19,27 +22,43 @@ CASES["D1-length-W4-L6"] = W.table1_shape(0, 1, 4, 6)
 CASES["D3-path-W12-L5"] = W.table1_shape(1, 3, 12, 5)
 CASES["D3-event-W16-L5"] = W.table1_shape(2, 3, 16, 5)
 CASES["D1-event-W12-L5"] = W.table1_shape(2, 1, 12, 5)
+# two-tile layers
+CASES["D2-event-W20-L5"] = W.table1_shape(2, 2, 20, 5)
+CASES["D2-event-W16-L9"] = W.table1_shape(2, 2, 16, 9)
+CASES["D1-path-W8-L9"] = W.table1_shape(1, 1, 8, 9)
+CASES["D3-event-W20-L9"] = W.table1_shape(2, 3, 20, 9)
+CASES["D3-path-W16-L9"] = W.table1_shape(1, 3, 16, 9)
 
 
 def dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda().contiguous()
 
 
-def real_mask(shape):
+def dims(shape):
     nl = shape["n_linear"]
-    mask = np.zeros((2 * nl, 272), bool)
+    out = []
     for net in range(2):
         in0 = shape["latent"] + shape["p_in"] if net else shape["p_out"] + shape["p_in"]
         outl = 2 * shape["p_out"] if net else 2 * shape["latent"]
         for j in range(nl):
-            n_in = in0 if j == 0 else shape["width"]
-            n_out = outl if j == nl - 1 else shape["width"]
-            Wm = np.zeros((16, 16), bool)
-            Wm[:n_out, :n_in] = True
-            b = np.zeros(16, bool)
-            b[:n_out] = True
-            mask[net * nl + j] = np.concatenate([Wm.ravel(), b])
-    return mask.ravel()
+            out.append((in0 if j == 0 else shape["width"], outl if j == nl - 1 else shape["width"]))
+    return out
+
+
+def stride(shape):
+    return 16 if max(max(d) for d in dims(shape)) <= 16 else 32
+
+
+def real_mask(shape):
+    S = stride(shape)
+    mask = []
+    for n_in, n_out in dims(shape):
+        Wm = np.zeros((S, S), bool)
+        Wm[:n_out, :n_in] = True
+        b = np.zeros(S, bool)
+        b[:n_out] = True
+        mask.append(np.concatenate([Wm.ravel(), b]))
+    return np.concatenate(mask)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -47,7 +66,8 @@ def test_init_and_gradient_parity(msst, oracle, name):
     announce(f"table1 init + grad {name}")
     shape = CASES[name]
     n = msst.cvae_param_count(shape)
-    assert n == 2 * shape["n_linear"] * 272
+    S = stride(shape)
+    assert n == 2 * shape["n_linear"] * (S * S + S)
     master = torch.empty(n, dtype=torch.float32, device="cuda")
     msst.cvae_init(shape, 41, master)
     np.testing.assert_allclose(master.cpu().numpy(), oracle.cvae_init(shape, 41), rtol=1e-6, atol=1e-7)
@@ -73,13 +93,14 @@ def test_init_and_gradient_parity(msst, oracle, name):
     np.testing.assert_allclose(loss.cpu().numpy(), (l64, kl64, nll64), rtol=LOSS_REL, atol=1e-3)
 
 
-def test_training_keeps_missing_units_at_zero(msst):
-    announce("table1 training W=8")
-    shape = CASES["final-0"]
+@pytest.mark.parametrize("name", ["final-0", "D2-event-W20-L5"])
+def test_training_keeps_missing_units_at_zero(msst, name):
+    announce(f"table1 training {name}")
+    shape = CASES[name]
     n_rows, B = 1 << 14, 512
     rng = np.random.default_rng(1)
-    cond = rng.normal(size=(n_rows, 2)).astype(np.float32)
-    target = (0.5 * cond[:, :1] + 0.1 * rng.normal(size=(n_rows, 1))).astype(np.float32)
+    cond = rng.normal(size=(n_rows, shape["p_in"])).astype(np.float32)
+    target = (0.5 * cond[:, :1] + 0.1 * rng.normal(size=(n_rows, shape["p_out"]))).astype(np.float32)
     master = torch.empty(msst.cvae_param_count(shape), dtype=torch.float32, device="cuda")
     msst.cvae_init(shape, 3, master)
     m, v = torch.zeros_like(master), torch.zeros_like(master)
@@ -145,3 +166,24 @@ def test_sphere_tracing_with_table1_decoders(msst, oracle, arch):
     assert o["steps"].sum() > 100
     # measured: one of 1600 paths (a bfloat16 flip in a four-layer decoder)
     assert frac < 2e-3
+
+
+def test_renderer_refuses_two_tile_decoders(msst, oracle):
+    """The in-kernel decoders take one tile per layer; a two-tile model (here
+    EventGen with 20 hidden units) leaves the image NaN and traces nothing."""
+    announce("table1 render refuses two-tile decoders")
+    from test_gpu_render import c4_inputs
+    shapes = list(W.TABLE1_SHAPES)
+    shapes[2] = CASES["D2-event-W20-L5"]
+    packed = []
+    for m, shape in enumerate(shapes):
+        master = oracle.cvae_init(shape, seed=700 + m).astype(np.float32).astype(np.float64)
+        p = torch.empty(msst.cvae_packed_bytes(), dtype=torch.uint8, device="cuda")
+        msst.cvae_pack(shape, dev(master), dev(W.render_test_stats(m), torch.float64), 1, p)
+        packed.append(p)
+    prims, cam, light, med = c4_inputs(40.0, 16)
+    rend = msst.Renderer(prims, cam, light)
+    img = rend.render(med, method=2, sampler=0, packed=packed, spp=2, seed=3, tau_min=2.0)
+    torch.cuda.synchronize()
+    assert torch.isnan(img["sum"]).all()
+    assert int(img["counters"][1]) == 0 and int(img["counters"][2]) == 0

@@ -10,22 +10,48 @@ import torch
 LOG2PI = math.log(2 * math.pi)
 
 
-def real_param_mask(shape):
-    """True where a parameter is a real weight or bias (not 16x16 padding)."""
+def layer_dims(shape):
+    """(n_in, n_out) of the 2 n_linear layers, encoder first."""
     nl = shape["n_linear"]
-    mask = np.zeros((2 * nl, 16 * 16 + 16), bool)
+    dims = []
     for net in range(2):
         in0 = shape["latent"] + shape["p_in"] if net else shape["p_out"] + shape["p_in"]
         outl = 2 * shape["p_out"] if net else 2 * shape["latent"]
         for j in range(nl):
-            n_in = in0 if j == 0 else shape["width"]
-            n_out = outl if j == nl - 1 else shape["width"]
-            W = np.zeros((16, 16), bool)
-            W[:n_out, :n_in] = True
-            b = np.zeros(16, bool)
-            b[:n_out] = True
-            mask[net * nl + j] = np.concatenate([W.ravel(), b])
-    return mask.ravel()
+            dims.append((in0 if j == 0 else shape["width"], outl if j == nl - 1 else shape["width"]))
+    return dims
+
+
+def stride_of(shape):
+    """Row stride of the layout: 16 when every width fits one 16-wide tile."""
+    widest = max(max(d) for d in layer_dims(shape))
+    return 16 if widest <= 16 else 32
+
+
+def real_param_mask(shape):
+    """True where a parameter is a real weight or bias (not S x S padding)."""
+    S = stride_of(shape)
+    mask = []
+    for n_in, n_out in layer_dims(shape):
+        W = np.zeros((S, S), bool)
+        W[:n_out, :n_in] = True
+        b = np.zeros(S, bool)
+        b[:n_out] = True
+        mask.append(np.concatenate([W.ravel(), b]))
+    return np.concatenate(mask)
+
+
+def restride(p, n_layers, S_from, S_to):
+    """The same weights and biases in the layout of another row stride."""
+    out = np.zeros(n_layers * (S_to * S_to + S_to))
+    for layer in range(n_layers):
+        src = p[layer * (S_from * S_from + S_from):(layer + 1) * (S_from * S_from + S_from)]
+        dst = out[layer * (S_to * S_to + S_to):(layer + 1) * (S_to * S_to + S_to)]
+        m = min(S_from, S_to)
+        W = dst[:S_to * S_to].reshape(S_to, S_to)
+        W[:m, :m] = src[:S_from * S_from].reshape(S_from, S_from)[:m, :m]
+        dst[S_to * S_to:S_to * S_to + m] = src[S_from * S_from:S_from * S_from + m]
+    return out
 
 
 def batch(shape, B, seed):
@@ -39,6 +65,10 @@ def table1_cases():
     out["table1-D1-length-W4-L6"] = W.table1_shape(0, 1, 4, 6)
     out["table1-D3-path-W12-L5"] = W.table1_shape(1, 3, 12, 5)
     out["table1-D3-event-W16-L5"] = W.table1_shape(2, 3, 16, 5)
+    # two-tile layouts (row stride 32): 20 hidden units, 2 x 9 encoder outputs
+    out["table1-D2-event-W20-L5"] = W.table1_shape(2, 2, 20, 5)
+    out["table1-D1-path-W8-L9"] = W.table1_shape(1, 1, 8, 9)
+    out["table1-D3-event-W20-L9"] = W.table1_shape(2, 3, 20, 9)
     return out
 
 
@@ -252,6 +282,40 @@ def test_narrow_network_equals_wide_network_with_silent_units(oracle, model):
     assert abs(ln - lw) < 1e-12 * max(1.0, abs(ln))
     real = real_param_mask(narrow)
     np.testing.assert_allclose(gw[real], gn[real], rtol=1e-10, atol=1e-13)
+
+
+def test_twenty_units_with_four_silent_equal_sixteen_across_the_stride(oracle):
+    """Table 1's W = 20 EventGen (row stride 32) with the four extra hidden
+    units given incoming weights but no outgoing ones is the W = 16 network
+    (row stride 16): same loss, same gradient on every real parameter of the
+    narrow one, and no gradient into the silent units' incoming weights and
+    biases (nothing downstream depends on them)."""
+    import workloads as W
+    narrow = W.table1_shape(2, 2, 16, 5)
+    wide = W.table1_shape(2, 2, 20, 5)
+    assert oracle.layer_stride(narrow) == 16 and oracle.layer_stride(wide) == 32
+    nl = narrow["n_linear"]
+    p = oracle.cvae_init(narrow, seed=13)
+    q = restride(p, 2 * nl, 16, 32).reshape(2 * nl, 32 * 32 + 32)
+    rng = np.random.default_rng(5)
+    for layer, (n_in, n_out) in enumerate(layer_dims(wide)):
+        if n_out == 20:  # hidden layers: the extra units get incoming weights and biases
+            Wm = q[layer, :1024].reshape(32, 32)
+            Wm[16:20, :n_in] = rng.normal(size=(4, n_in))
+            q[layer, 1024 + 16:1024 + 20] = rng.normal(size=4)
+    q = q.ravel()
+    cond, target = batch(narrow, 8, 6)
+    ln, kln, nlln, gn = oracle.cvae_loss_grad(narrow, p, cond, target, seed=4, step=1)
+    lw, klw, nllw, gw = oracle.cvae_loss_grad(wide, q, cond, target, seed=4, step=1)
+    assert abs(ln - lw) < 1e-12 * max(1.0, abs(ln))
+    g_back = restride(gw, 2 * nl, 32, 16)
+    real = real_param_mask(narrow)
+    np.testing.assert_allclose(g_back[real], gn[real], rtol=1e-10, atol=1e-13)
+    gw2 = gw.reshape(2 * nl, 1056)
+    for layer, (n_in, n_out) in enumerate(layer_dims(wide)):
+        if n_out == 20:
+            assert np.all(gw2[layer, :1024].reshape(32, 32)[16:20] == 0)
+            assert np.all(gw2[layer, 1024 + 16:1024 + 20] == 0)
 
 
 def _normals_seed0(oracle, i, L):
