@@ -46,8 +46,8 @@ ALG_PER_EVENT = 350.0
 ALG_PER_STEP_ONE_EVENT = 2600.0
 ALG_PER_EXTRA_EVENT = 1000.0
 OPS_PER_PATH = 400.0         # counted: camera ray, primary intervals, banking the result
-OPS_PER_EVENT = 470.0        # counted: one plain collision
-OPS_PER_STEP = 5300.0        # counted: one learned step with two representative events
+OPS_PER_EVENT = 460.0        # counted: one plain collision
+OPS_PER_STEP = 5600.0        # counted: one learned step with one representative event
 MFMA_FLOP_PER_STEP = 2944.0  # real decoder MACs x 2 (LengthGen + PathGen + EventGen)
 OPS_PER_WALK_EVENT = 186.0   # one walk event: Philox block, HG sample, scatter, flight, exit test
 PEAK_VALU_LANEOPS = 256 * 2.4e9 * 64   # 3.93e13 lane-op slots/s, non-packed FP32 VALU
