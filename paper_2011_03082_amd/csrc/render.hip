@@ -1151,8 +1151,13 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
 template <int MODE, int NP, bool GRID>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void render_kernel(const RenderArgs A) {
     __shared__ RenderLds lds_all[kRenderWaves];
-    __shared__ float lds_prims[NP == 0 ? kMaxManyPrims * 8 : 8];
     __shared__ uint32_t lds_tot[kLaneWords][64 * kRenderWaves];
+    // many primitives: the scene's n_prims x 8 floats in dynamic LDS, sized
+    // at launch, so that the usual scenes (64 spheres: 2 KB) leave room for
+    // four blocks per CU
+    extern __shared__ float lds_dyn[];
+    __shared__ float lds_none[8];
+    float* lds_prims = NP == 0 ? lds_dyn : lds_none;
     RenderLds& L = lds_all[threadIdx.x >> 6];
     if (NP == 0) {
         for (int q = threadIdx.x; q < A.n_prims * 8; q += blockDim.x) lds_prims[q] = A.prims[q];
@@ -1322,9 +1327,10 @@ __global__ void sdf_grid_mesh_kernel(const float* tris, int n_tris, int res, dou
 // One render_kernel instance per (mode, geometry policy, radius source).
 template <int NP, bool GRID>
 static void launch_render(int mode, dim3 grid, dim3 block, hipStream_t hs, const RenderArgs& A) {
-    if (mode == kModePlain) hipLaunchKernelGGL((render_kernel<kModePlain, NP, GRID>), grid, block, 0, hs, A);
-    else if (mode == kModeStExact) hipLaunchKernelGGL((render_kernel<kModeStExact, NP, GRID>), grid, block, 0, hs, A);
-    else hipLaunchKernelGGL((render_kernel<kModeStCvae, NP, GRID>), grid, block, 0, hs, A);
+    const size_t lds = NP == 0 ? (size_t)A.n_prims * 8 * sizeof(float) : 0;
+    if (mode == kModePlain) hipLaunchKernelGGL((render_kernel<kModePlain, NP, GRID>), grid, block, lds, hs, A);
+    else if (mode == kModeStExact) hipLaunchKernelGGL((render_kernel<kModeStExact, NP, GRID>), grid, block, lds, hs, A);
+    else hipLaunchKernelGGL((render_kernel<kModeStCvae, NP, GRID>), grid, block, lds, hs, A);
 }
 
 static int default_chunk(int64_t npix, int spp) {
