@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--density-sigmas", type=str, default="80,160,320,640,1280")
     ap.add_argument("--density-albedo", type=float, default=0.9999)
     ap.add_argument("--density-width", type=int, default=256)
+    ap.add_argument("--density-event-steps", type=int, default=100000,
+                    help="AdamW steps of the EventGen beside the density sweep's default models (0: skip)")
     ap.add_argument("--absorption-sigma", type=float, default=80.0)
     ap.add_argument("--absorption-points", type=int, default=6)
     ap.add_argument("--restart-min", type=int, default=0)
@@ -133,7 +135,7 @@ def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, 
 
 
 def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precisions=(1,), shapes=None,
-                   walk_kw=None, timing=None, all_rows=False):
+                   walk_kw=None, timing=None, all_rows=False, model_steps=None):
     """GPU walk -> features -> FP64 standardisation -> AdamW training -> pack.
 
     The KL weight ramps linearly from 0 to 1 over the first kl_warmup of the
@@ -141,7 +143,9 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
     ({precision: [three packed models]}, per-model losses, seconds).  shapes:
     three architecture dicts (default: width 16, three linear maps, latent 4);
     walk_kw: extra training-walk options (e.g. a focus region); timing: a dict
-    that receives the walk's and the training steps' GPU times."""
+    that receives the walk's and the training steps' GPU times; model_steps:
+    per-model step counts (LengthGen, PathGen, EventGen) in place of `steps`,
+    each model on its own learning-rate and KL schedule."""
     t0 = time.time()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -160,17 +164,19 @@ def train_and_pack(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6
     cur = torch.cuda.current_stream()
     for st in streams:
         st.wait_stream(cur)
+    n_steps = list(model_steps) if model_steps is not None else [steps] * 3
     t_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_ev[0].record()
-    for step in range(1, steps + 1):
-        for su, st in zip(setups, streams):
-            train_step_model(M, su, step, steps, kl_warmup, stream=st)
+    for step in range(1, max(n_steps) + 1):
+        for su, st, n in zip(setups, streams, n_steps):
+            if step <= n:
+                train_step_model(M, su, step, n, kl_warmup, stream=st)
     for st in streams:
         cur.wait_stream(st)
     t_ev[1].record()
     torch.cuda.synchronize()
     if timing is not None:
-        us = t_ev[0].elapsed_time(t_ev[1]) * 1e3 / steps
+        us = t_ev[0].elapsed_time(t_ev[1]) * 1e3 / max(n_steps)
         timing["train_step_us_three_models"] = us
         timing["train_samples_per_s_per_model"] = batch / (us * 1e-6)
     packs, losses = {p: [] for p in precisions}, []
@@ -907,6 +913,13 @@ def main():
     density = None
     if not args.no_density:
         density = []
+        # the same recipe with EventGen trained longer: the image bias of the
+        # learned steps is EventGen's (placement of the representative
+        # events); fitting it longer trades that bias for variance
+        pk_ev = None
+        if args.density_event_steps > 0:
+            pk_ev = train_and_pack(M, torch, args.train_samples, args.train_steps,
+                                   model_steps=(args.train_steps, args.train_steps, args.density_event_steps))[0][1]
         dw = args.density_width
         drend = M.Renderer(W.scene_c4(), W.camera_c4(dw, dw), W.light_c4())
         for k, s_ in enumerate(float(x) for x in args.density_sigmas.split(",")):
@@ -928,6 +941,16 @@ def main():
                        st_steps_per_path=float(cs[2] / cs[0]),
                        st_mean_bias=float(sm.mean() / r_mean.mean() - 1.0),
                        speedup_matched_rmse=float(pv.mean()) / e_st**2 / spp * t_pt / t_st)
+            if pk_ev is not None:
+                img_ev, t_long = timed(lambda: drend.render(med, method=2, sampler=0, packed=pk_ev, spp=spp,
+                                                          seed=9300 + k, tau_min=args.tau_min,
+                                                          nee_samples=args.nee_samples, flags=args.nee_flags,
+                                                          min_chain=args.min_chain, **kw))
+                se, _ = image_moments(img_ev, spp)
+                e_ev = float(np.sqrt(max(float(((se - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+                row.update(event_long=dict(eventgen_steps=args.density_event_steps, st_ms=t_long * 1e3, rmse_st=e_ev,
+                                           st_mean_bias=float(se.mean() / r_mean.mean() - 1.0),
+                                           speedup_matched_rmse=float(pv.mean()) / e_ev**2 / spp * t_pt / t_long))
             density.append(row)
             log(f"density sigma_t={s_:g} (albedo {args.density_albedo}): PT {t_pt * 1e3:.1f} ms "
                 f"({row['pt_events_per_path']:.1f} events/path), ST {t_st * 1e3:.1f} ms "
