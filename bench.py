@@ -542,8 +542,8 @@ def cpu_baseline(oracle, W, args, models):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a "
-              "design (id-range sharding), not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding over GPUs by Philox id "
+              "ranges is designed but not implemented", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
