@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--nee-flags", type=int, default=1,
                     help="1 = direct light of learned steps before absorption, 2 = the paper's step as printed "
                          "(PathGen and EventGen for every step; the models are then trained on every walk record)")
-    ap.add_argument("--min-chain", type=float, default=64.0,
+    ap.add_argument("--min-chain", type=float, default=256.0,
                     help="cost rule: learned steps only where the deepest possible step bypasses at least this many "
                          "collisions (0 = always)")
     ap.add_argument("--chunk", type=int, default=0)

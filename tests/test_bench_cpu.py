@@ -17,16 +17,19 @@ def test_defaults_match_the_documented_configuration(monkeypatch):
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
     assert (a.gpus, a.width, a.spp, a.ref_spp) == (1, 512, 256, 4096)
-    assert a.tau_min == 10.0 and a.nee_samples == 1 and a.nee_flags == 1 and a.min_chain == 64.0
+    assert a.tau_min == 10.0 and a.nee_samples == 1 and a.nee_flags == 1 and a.min_chain == 256.0
     assert a.train_samples == 1 << 22 and a.train_steps == 20000
 
 
 def test_cost_rule_of_the_sphere_box_launches(monkeypatch):
     """The bench's CPU baseline applies the render kernel's cost rule: the
     unit sphere's centre (radius 0.999) bypasses 0.5 (0.999 sigma_t)^2 0.2
-    collisions -- under 64 at sigma_t 10 and 20, above at 40 and 80."""
+    collisions -- under 256 at sigma_t 10, 20 and 40 (160), above at 80 (638);
+    under 64 only at 10 and 20."""
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = bench.parse()
+    assert [bench.c4_tau(s, a) for s in (10.0, 20.0, 40.0, 80.0)] == [1e30, 1e30, 1e30, 10.0]
+    a.min_chain = 64.0
     assert [bench.c4_tau(s, a) for s in (10.0, 20.0, 40.0, 80.0)] == [1e30, 1e30, 10.0, 10.0]
     a.min_chain = 0.0
     assert bench.c4_tau(20.0, a) == 10.0
