@@ -54,3 +54,31 @@ def test_image_moments():
     mean, var = bench.image_moments(img, 4)
     np.testing.assert_allclose(mean.numpy(), [1.0, (2.0 + 1e-7) / 4], rtol=1e-7)
     assert var.min() >= 0
+
+
+def test_subset_pixels_and_anchor_statistics():
+    """The oracle anchor's pixel subset is the centre of every stride x
+    stride block, and its matched-RMSE inputs are taken on those pixels
+    only: the plain tracer's variance on the subset, and each image's error
+    against the oracle with the oracle's own noise removed."""
+    w = h = 32
+    for stride in (8, 16):
+        pix = bench.subset_pixels(w, h, stride)
+        assert pix.size == (w // stride) * (h // stride)
+        assert set((pix % w).tolist()) == set(range(stride // 2, w, stride))
+        assert set((pix // w).tolist()) == set(range(stride // 2, h, stride))
+    rng = np.random.default_rng(0)
+    pix = bench.subset_pixels(w, h, 8)
+    truth = rng.uniform(0.5, 1.0, w * h)
+    n_o, n_r = 4096, 1024
+    sub = dict(pix=pix, mean=truth[pix], var=np.full(pix.size, 0.04), spp=n_o, seconds=0.0)
+    ref_var = np.full(w * h, 0.09)
+    pt_var = np.where(np.arange(w * h) % 2 == 0, 1.0, 3.0)
+    img = truth + 0.1  # an image off by 0.1 everywhere
+    a = bench.anchor_stats(sub, truth, ref_var, n_r, {"x": img}, pt_var)
+    # the subset's pixels are all even (centres at 4, 12, ...): variance 1, not the image mean 2
+    assert a["pt_var_subset"] == 1.0
+    np.testing.assert_allclose(a["rmse_x_vs_oracle"], np.sqrt(0.01 - 0.04 / n_o), rtol=1e-12)
+    np.testing.assert_allclose(a["rmse_x_vs_reference_on_subset"], np.sqrt(0.01 - 0.09 / n_r), rtol=1e-12)
+    assert a["pixels"] == pix.size and a["lit_pixels"] == pix.size
+    assert a["z_rms"] == 0.0 and a["z_global"] == 0.0
