@@ -420,7 +420,10 @@ def anchor_stats(sub, ref_mean, ref_var, ref_spp, images, pt_var):
     rv = ref_var[p] / ref_spp
     d = ref_mean[p] - sub["mean"]
     v = rv + ov
-    lit = v > 0
+    # pixels with any light; radiances near 1e-20 have squares that flush to
+    # zero in the GPU's binary32 sums, so variances below 1e-12 of the largest
+    # are taken as none (such pixels add nothing to any RMSE either)
+    lit = v > 1e-12 * v.max()
     z = d[lit] / np.sqrt(v[lit])
     out = dict(pixels=int(p.size), lit_pixels=int(lit.sum()), oracle_spp=sub["spp"], oracle_seconds=sub["seconds"],
                z_rms=float(np.sqrt(np.mean(z * z))), z_mean=float(z.mean()), z_max=float(np.abs(z).max()),

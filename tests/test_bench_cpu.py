@@ -82,3 +82,13 @@ def test_subset_pixels_and_anchor_statistics():
     np.testing.assert_allclose(a["rmse_x_vs_reference_on_subset"], np.sqrt(0.01 - 0.09 / n_r), rtol=1e-12)
     assert a["pixels"] == pix.size and a["lit_pixels"] == pix.size
     assert a["z_rms"] == 0.0 and a["z_global"] == 0.0
+    # a pixel whose variances are negligible (squares flushed to zero) but
+    # whose means differ is left out of the z-test instead of dominating it
+    ref2 = truth.copy()
+    ref2[pix[0]] += 1e-20
+    ref_var2 = ref_var.copy()
+    ref_var2[pix[0]] = 0.0
+    sub2 = dict(sub, var=sub["var"].copy())
+    sub2["var"][0] = 1e-60
+    a2 = bench.anchor_stats(sub2, ref2, ref_var2, n_r, {"x": img}, pt_var)
+    assert a2["lit_pixels"] == pix.size - 1 and a2["z_max"] < 1.0
