@@ -63,7 +63,8 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
+    """Command-line options (argv: a list in place of sys.argv)."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -122,7 +123,7 @@ def parse():
                          "the single-event parts exactly, and the reverse)")
     ap.add_argument("--diagnostics", action="store_true",
                     help="also render sphere tracing with exact in-sphere walks and a tau_min sweep (untimed)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def train_models(M, torch, n_samples, steps, batch=4096, seed=0, kl_warmup=0.6, precision=1, shapes=None,

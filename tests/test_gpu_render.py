@@ -332,18 +332,35 @@ def test_full_size_c4_sampled_pixels(msst, oracle):
     assert frac < 1e-2
 
 
-def test_full_size_c4_learned_sampled_pixels(msst, oracle):
-    """512 x 512 with the benchmark's sphere-tracing options (tau_min 6, two
-    representative events lit before absorption, default launch shape), BF16
-    decoders; 200 sampled pixels path by path against the oracle."""
-    announce("render C4 512^2 ST sampled parity")
+def bench_st_options():
+    """The sphere-tracing options bench.py renders with by default (the
+    oracle takes the same ones but the launch cost rule, which lets every
+    launch tested with it here take learned steps)."""
+    import bench
+    a = bench.parse([])
+    return dict(tau_min=a.tau_min, nee_samples=a.nee_samples, flags=a.nee_flags), a.min_chain
+
+
+@pytest.mark.parametrize("options", ["bench", "dense"])
+def test_full_size_c4_learned_sampled_pixels(msst, oracle, options):
+    """512 x 512 at sigma_t 80 in the default launch shape, BF16 decoders:
+    with the benchmark's sphere-tracing options (its tau_min, representative
+    events, light before absorption and launch cost rule), and with more and
+    smaller steps (tau_min 6, two representative events); 200 sampled pixels
+    with learned steps path by path against the oracle."""
+    announce(f"render C4 512^2 ST sampled parity options={options}")
     prims, cam, light, med = c4_inputs(80.0, 512)
     models, src = models_for_test(oracle)
     packed = pack_all(msst, src, 1)
-    opts = dict(spp=1, seed=17, tau_min=6.0, nee_samples=2, flags=1)
-    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, **opts)
+    if options == "bench":
+        st, min_chain = bench_st_options()
+    else:
+        st, min_chain = dict(tau_min=6.0, nee_samples=2, flags=1), 0.0
+    opts = dict(spp=1, seed=17, **st)
+    g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, min_chain=min_chain, **opts)
     rng = np.random.default_rng(1)
     stepped = np.flatnonzero(g["steps"] > 0)
+    assert stepped.size > 1000
     pix = np.sort(rng.choice(stepped, 200, replace=False)).astype(np.int32)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, pixels=pix, **opts)
@@ -365,10 +382,13 @@ def test_full_size_c5_sampled_pixels(msst, oracle, method, precision):
     models, src = models_for_test(oracle)
     packed = pack_all(msst, src, precision) if method == ST else (None, None, None)
     opts = dict(spp=1, seed=23)
+    min_chain = 0.0
     if method == ST:
-        opts.update(tau_min=6.0, nee_samples=2, flags=1)
+        # the benchmark's options; the cost rule leaves a grid scene its steps
+        st, min_chain = bench_st_options()
+        opts.update(st)
     r = msst.Renderer(prims, cam, light, grid=grid_g)
-    out = r.render(med, method=method, sampler=CVAE, packed=packed, **opts)
+    out = r.render(med, method=method, sampler=CVAE, packed=packed, min_chain=min_chain, **opts)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items()}
     rng = np.random.default_rng(2)
@@ -382,6 +402,8 @@ def test_full_size_c5_sampled_pixels(msst, oracle, method, precision):
     frac, _ = compare_paths(sub, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; steps {o['steps'].sum()}, events {o['events'].sum()}")
     assert frac < 1.4e-2
+    if method == ST:
+        assert o["steps"].sum() > 10
 
 
 def test_image_stats_fp64(msst):
