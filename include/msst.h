@@ -103,7 +103,7 @@ typedef struct {
     double sigma_t, g, albedo, radius;                 /* ANALOG */
     double st_range[2], g_range[2], albedo_range[2];   /* TRAINING */
     uint32_t max_events;                               /* 0 = 2^20 */
-    int32_t blocks_per_cu;                             /* launch shape, 0 = default */
+    int32_t blocks_per_cu;                             /* 256-thread blocks per CU, 1..64; 0 = 2 */
     /* TRAINING: (sigma_t r, g)-weighted data (Sec. 5.3 names over-weighting
      * parameter regions as a lever for quality).  With probability
      * focus_fraction (decided by the fourth uniform of the photon's parameter
