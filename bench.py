@@ -700,7 +700,7 @@ def main():
     # Many pixels at fewer samples: a learned step's direct light comes from one
     # representative event weighted by the whole bypassed chain, so a few pixels
     # carry much of the sphere tracer's squared error, and a sparser subset
-    # misjudges it by up to 15 % (1/64 of the pixels at sigma_t 80)
+    # misestimates it by up to 15 % (1/64 of the pixels at sigma_t 80)
     if not args.no_oracle_anchor:
         import oracle
         o_scene = oracle.Scene(W.scene_c4())
