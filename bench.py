@@ -589,14 +589,19 @@ def main():
         return out, e0.elapsed_time(e1) / 1e3
 
     def timed_mean(fn, reps):
-        # warm, then the mean of reps timed calls (the tracers the headline
-        # compares are both timed over args.steps calls); the last output
+        # the mean of reps calls queued back to back behind an untimed one, so
+        # that no interval holds the host's enqueue time (as the sphere
+        # tracer's timed steps run back to back); the last output
         fn()
-        ts = []
+        evs, out = [], None
         for _ in range(max(1, reps)):
-            out, t = timed(fn, warm=False)
-            ts.append(t)
-        return out, float(np.mean(ts))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        return out, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
 
     def rmse(img, s):
         mean, _ = image_moments(img, spp)
@@ -684,7 +689,11 @@ def main():
         confirm = None
         if not args.no_confirm:
             med_s = W.medium_c4(s)
-            img_c, t_c = timed_mean(lambda: rend.render(med_s, method=1, spp=s_conf, seed=2501, **kw), args.steps)
+            # the timed renders' samples per work unit (the header's default
+            # rule at spp), so that only the sample count differs
+            unit = args.chunk or min(spp, max(2, -(-npix * spp // (1 << 24))))
+            kw_c = dict(kw, chunk=min(unit, s_conf))
+            img_c, t_c = timed_mean(lambda: rend.render(med_s, method=1, spp=s_conf, seed=2501, **kw_c), args.steps)
             mc, _ = image_moments(img_c, s_conf)
             r_conf = float(np.sqrt(max(float(((mc.float() - ref[s]) ** 2).mean()) - ref_noise2[s], 1e-30)))
             confirm = dict(spp=s_conf, rmse=r_conf, ms=t_c * 1e3, speedup=t_c / t_sigma[s])
