@@ -588,20 +588,25 @@ def main():
         torch.cuda.synchronize()
         return out, e0.elapsed_time(e1) / 1e3
 
-    def timed_mean(fn, reps):
-        # the mean of reps calls queued back to back behind an untimed one, so
+    def timed_images(fns):
+        # the calls queued back to back behind an untimed run of the first, so
         # that no interval holds the host's enqueue time (as the sphere
-        # tracer's timed steps run back to back); the last output
-        fn()
-        evs, out = [], None
-        for _ in range(max(1, reps)):
+        # tracer's timed steps run back to back): their outputs and mean time
+        fns[0]()
+        evs, outs = [], []
+        for fn in fns:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            out = fn()
+            outs.append(fn())
             e1.record(stream)
             evs.append((e0, e1))
         torch.cuda.synchronize()
-        return out, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
+        return outs, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs])) / 1e3
+
+    def timed_mean(fn, reps):
+        # reps identical calls: the last output and the mean time
+        outs, t = timed_images([fn] * max(1, reps))
+        return outs[-1], t
 
     def rmse(img, s):
         mean, _ = image_moments(img, spp)
@@ -654,12 +659,13 @@ def main():
     mk = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     ev = [[mk() for _ in sigmas] for _ in range(args.steps)]
     t_start = time.time()
-    last = {}
+    last, outs = {}, {s: [] for s in sigmas}
     for k in range(args.steps):
         for i, s in enumerate(sigmas):
             ev[k][i][0].record(stream)
             last[s] = st_render(s, 4000 + k)
             ev[k][i][1].record(stream)
+            outs[s].append(last[s])
     torch.cuda.synchronize()
     wall = time.time() - t_start
     t_sigma = {s: float(np.mean([ev[k][i][0].elapsed_time(ev[k][i][1]) for k in range(args.steps)])) / 1e3
@@ -670,19 +676,22 @@ def main():
 
     # matched RMSE: the plain tracer needs S* = mean per-pixel variance /
     # RMSE_ST^2 samples per pixel (RMSE_ST with the reference's own noise
-    # removed) to reach the sphere tracer's error, at its measured rate
+    # removed) to reach the sphere tracer's error, at its measured rate.
+    # RMSE_ST^2 is the mean over the timed steps' images (one seed each): a
+    # learned step lights a whole chain from one event, so its squared error
+    # is heavy-tailed and one image estimates it less steadily
     details, counters = {}, np.zeros(4)
     tot_st, tot_pt = 0.0, 0.0
     for s in sigmas:
         img = last[s]
         c = img["counters"].cpu().numpy()
         counters += c
-        r_raw = rmse(img, s)
-        r_st = float(np.sqrt(max(r_raw**2 - ref_noise2[s], 1e-30)))
+        r_raw2 = float(np.mean([rmse(im, s) ** 2 for im in outs[s]]))
+        r_st = float(np.sqrt(max(r_raw2 - ref_noise2[s], 1e-30)))
         r_pt = float(np.sqrt(max(pt[s]["rmse"] ** 2 - ref_noise2[s], 1e-30)))
         s_star = pt[s]["var"] / r_st**2
         t_pt_match = s_star * npix / (pt[s]["paths"] / pt[s]["time"])
-        mean_st = float(image_moments(img, spp)[0].mean())
+        mean_st = float(np.mean([float(image_moments(im, spp)[0].mean()) for im in outs[s]]))
         # confirmation: the plain tracer actually run at ceil(S*) spp (its own
         # seed), its RMSE and time beside the sphere tracer's
         s_conf = max(1, int(np.ceil(s_star)))
@@ -727,9 +736,12 @@ def main():
         for i, s in enumerate(sigmas):
             sub = oracle_subset(oracle, o_scene, W.camera_c4(width, width), W.light_c4(), W.medium_c4(s),
                                 args.oracle_spp, 11000 + i, stride=4)
-            st_mean = image_moments(last[s], spp)[0].cpu().numpy()
+            ims = {f"st{j}": image_moments(im, spp)[0].cpu().numpy() for j, im in enumerate(outs[s])}
             a = anchor_stats(sub, ref[s].double().cpu().numpy(), ref_var_np[s], args.ref_spp,
-                             {"st": st_mean, "pt": pt_mean_np[s]}, pt_var_np[s])
+                             dict(ims, pt=pt_mean_np[s]), pt_var_np[s])
+            # the sphere tracer's error on the subset: the mean square over its images
+            for key in ("vs_oracle", "vs_reference_on_subset"):
+                a[f"rmse_st_{key}"] = float(np.sqrt(np.mean([a.pop(f"rmse_{j}_{key}") ** 2 for j in ims])))
             t_pt_o = a["pt_var_subset"] / a["rmse_st_vs_oracle"] ** 2 * npix / (pt[s]["paths"] / pt[s]["time"])
             a["speedup_matched_rmse_oracle"] = t_pt_o / t_sigma[s]
             details[str(s)]["oracle_anchor"] = a
@@ -967,29 +979,34 @@ def main():
             img = drend.render(med, method=1, spp=args.ref_spp, seed=9000 + k, **kw)
             r_mean, r_var = image_moments(img, args.ref_spp)
             r_noise2 = float(r_var.mean()) / args.ref_spp
-            img_pt, t_pt = timed(lambda: drend.render(med, method=1, spp=spp, seed=9100 + k, **kw))
+            reps = max(1, args.steps)
+            img_pt, t_pt = timed_mean(lambda: drend.render(med, method=1, spp=spp, seed=9100 + k, **kw), reps)
             pm, pv = image_moments(img_pt, spp)
-            img_st, t_st = timed(lambda: drend.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=9200 + k,
-                                                      tau_min=args.tau_min, nee_samples=args.nee_samples,
-                                                      flags=args.nee_flags, min_chain=args.min_chain, **kw))
-            sm, _ = image_moments(img_st, spp)
-            e_st = float(np.sqrt(max(float(((sm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+
+            def st_images(pk, seed0):
+                # reps images, one seed each, timed back to back: their mean
+                # time, the mean square of their errors and their mean
+                ims, t = timed_images([
+                    (lambda j=j: drend.render(med, method=2, sampler=0, packed=pk, spp=spp, seed=seed0 + 1000 * j,
+                                              tau_min=args.tau_min, nee_samples=args.nee_samples,
+                                              flags=args.nee_flags, min_chain=args.min_chain, **kw))
+                    for j in range(reps)])
+                means = [image_moments(im, spp)[0] for im in ims]
+                e2 = float(np.mean([float(((m - r_mean) ** 2).mean()) for m in means]))
+                return ims[-1], t, float(np.sqrt(max(e2 - r_noise2, 1e-30))), float(np.mean([float(m.mean()) for m in means]))
+
+            img_st, t_st, e_st, sm_mean = st_images(packed, 9200 + k)
             e_pt = float(np.sqrt(max(float(((pm - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
             cp, cs = img_pt["counters"].cpu().numpy(), img_st["counters"].cpu().numpy()
             row = dict(sigma_t=s_, pt_ms=t_pt * 1e3, st_ms=t_st * 1e3, rmse_pt=e_pt, rmse_st=e_st,
                        pt_events_per_path=float(cp[1] / cp[0]), st_events_per_path=float(cs[1] / cs[0]),
                        st_steps_per_path=float(cs[2] / cs[0]),
-                       st_mean_bias=float(sm.mean() / r_mean.mean() - 1.0),
+                       st_mean_bias=sm_mean / float(r_mean.mean()) - 1.0,
                        speedup_matched_rmse=float(pv.mean()) / e_st**2 / spp * t_pt / t_st)
             if pk_ev is not None:
-                img_ev, t_long = timed(lambda: drend.render(med, method=2, sampler=0, packed=pk_ev, spp=spp,
-                                                          seed=9300 + k, tau_min=args.tau_min,
-                                                          nee_samples=args.nee_samples, flags=args.nee_flags,
-                                                          min_chain=args.min_chain, **kw))
-                se, _ = image_moments(img_ev, spp)
-                e_ev = float(np.sqrt(max(float(((se - r_mean) ** 2).mean()) - r_noise2, 1e-30)))
+                _, t_long, e_ev, se_mean = st_images(pk_ev, 9300 + k)
                 row.update(event_long=dict(eventgen_steps=args.density_event_steps, st_ms=t_long * 1e3, rmse_st=e_ev,
-                                           st_mean_bias=float(se.mean() / r_mean.mean() - 1.0),
+                                           st_mean_bias=se_mean / float(r_mean.mean()) - 1.0,
                                            speedup_matched_rmse=float(pv.mean()) / e_ev**2 / spp * t_pt / t_long))
             density.append(row)
             log(f"density sigma_t={s_:g} (albedo {args.density_albedo}): PT {t_pt * 1e3:.1f} ms "
