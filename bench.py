@@ -652,6 +652,17 @@ def main():
         opts.update(extra)
         return rend.render(W.medium_c4(s), **opts)
 
+    def st_scored(s, seed0, **extra):
+        # args.steps sphere-traced images, one seed each, timed back to back:
+        # the last image, the mean time, the RMSE (mean square over the images,
+        # the reference's own noise removed) and the mean of the image means
+        ims, t = timed_images([(lambda j=j: st_render(s, seed0 + 100000 * j, **extra))
+                               for j in range(max(1, args.steps))])
+        e2 = float(np.mean([rmse(im, s) ** 2 for im in ims]))
+        r = float(np.sqrt(max(e2 - ref_noise2[s], 1e-30)))
+        m = float(np.mean([float(image_moments(im, spp)[0].mean()) for im in ims]))
+        return ims[-1], t, r, m
+
     for w in range(args.warmup):
         for s in sigmas:
             st_render(s, 3000 + w)
@@ -768,8 +779,7 @@ def main():
         table1 = {"shapes": W.TABLE1_SHAPES, "train_seconds": t1,
                   "loss_last": [l["last"] for l in losses1]}
         for s in sigmas:
-            img, t = timed(lambda: st_render(s, 6001, packed=pk1[1]))
-            r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
+            img, t, r_st, _ = st_scored(s, 6001, packed=pk1[1])
             s_star = pt[s]["var"] / r_st**2
             t_pt_match = s_star * npix / (pt[s]["paths"] / pt[s]["time"])
             table1[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, speedup_matched_rmse=t_pt_match / t,
@@ -791,11 +801,9 @@ def main():
         other = {"form": name, "flags": o_flags, "nee_samples": args.nee_samples, "train_seconds": to}
         tot_o, tot_om = 0.0, 0.0
         for s in sigmas:
-            img, t = timed(lambda: st_render(s, 6201, packed=pko[1], flags=o_flags))
+            img, t, r_st, mean_o = st_scored(s, 6201, packed=pko[1], flags=o_flags)
             c = img["counters"].cpu().numpy()
-            r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
             t_m = pt[s]["var"] / r_st**2 * npix / (pt[s]["paths"] / pt[s]["time"])
-            mean_o = float(image_moments(img, spp)[0].mean())
             other[str(s)] = dict(ms=t * 1e3, rmse_st=r_st, steps_per_path=float(c[2] / c[0]), mean_st=mean_o,
                                  mean_bias=mean_o / details[str(s)]["mean_ref"] - 1.0,
                                  speedup_matched_rmse=t_m / t, rmse_st_default=details[str(s)]["rmse_st"])
@@ -815,8 +823,7 @@ def main():
                                     all_rows=paper_step)
         focus = dict(fkw, train_seconds=tf)
         for s in sigmas:
-            img, t = timed(lambda: st_render(s, 6101, packed=pkf[1]))
-            r_st = float(np.sqrt(max(rmse(img, s) ** 2 - ref_noise2[s], 1e-30)))
+            img, t, r_st, _ = st_scored(s, 6101, packed=pkf[1])
             s_star = pt[s]["var"] / r_st**2
             focus[str(s)] = dict(ms=t * 1e3, rmse_st=r_st,
                                  speedup_matched_rmse=s_star * npix / (pt[s]["paths"] / pt[s]["time"]) / t)
@@ -987,7 +994,7 @@ def main():
                 # reps images, one seed each, timed back to back: their mean
                 # time, the mean square of their errors and their mean
                 ims, t = timed_images([
-                    (lambda j=j: drend.render(med, method=2, sampler=0, packed=pk, spp=spp, seed=seed0 + 1000 * j,
+                    (lambda j=j: drend.render(med, method=2, sampler=0, packed=pk, spp=spp, seed=seed0 + 100000 * j,
                                               tau_min=args.tau_min, nee_samples=args.nee_samples,
                                               flags=args.nee_flags, min_chain=args.min_chain, **kw))
                     for j in range(reps)])
