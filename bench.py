@@ -104,6 +104,9 @@ def parse(argv=None):
     ap.add_argument("--density-sigmas", type=str, default="80,160,320,640,1280")
     ap.add_argument("--density-albedo", type=float, default=0.9999)
     ap.add_argument("--density-width", type=int, default=256)
+    ap.add_argument("--density-nee-samples", type=int, default=2,
+                    help="representative events per learned step in the density sweep (its chains run to 10^4 "
+                         "events, and a second event halves the heavy tail of their direct light)")
     ap.add_argument("--density-event-steps", type=int, default=100000,
                     help="AdamW steps of the EventGen beside the density sweep's default models (0: skip)")
     ap.add_argument("--absorption-sigma", type=float, default=80.0)
@@ -995,7 +998,7 @@ def main():
                 # time, the mean square of their errors and their mean
                 ims, t = timed_images([
                     (lambda j=j: drend.render(med, method=2, sampler=0, packed=pk, spp=spp, seed=seed0 + 100000 * j,
-                                              tau_min=args.tau_min, nee_samples=args.nee_samples,
+                                              tau_min=args.tau_min, nee_samples=args.density_nee_samples,
                                               flags=args.nee_flags, min_chain=args.min_chain, **kw))
                     for j in range(reps)])
                 means = [image_moments(im, spp)[0] for im in ims]
@@ -1107,7 +1110,8 @@ def main():
                                 "g U[-0.9, 0.95], albedo U[0.9, 1]"),
         "density_sweep": None if density is None else {
             "workload": f"sphere+box scene {args.density_width}x{args.density_width}, {spp} spp, g=0.8, "
-                        f"albedo={args.density_albedo}, doubling sigma_t", "rows": density},
+                        f"albedo={args.density_albedo}, doubling sigma_t, {args.density_nee_samples} representative "
+                        f"events per learned step", "rows": density},
         "absorption_sweep": absorption,
         "rgb": rgb,
         "mesh": mesh,

@@ -370,6 +370,15 @@ typedef struct {
      * PLAIN_NEE).  Scenes whose deepest distance is not known in closed form
      * (a distance grid, many primitives, a mesh) always allow steps. */
     float min_chain;
+    /* Representative events per learned step by chain length (0 = off:
+     * nee_samples for every step).  A step's direct-light estimate weights
+     * one event by sum_{i<=N} albedo^i, so its variance grows with the square
+     * of that sum; with nee_chain > 0 a step of N events draws
+     * K = min(nee_samples, 1 + floor((N - 1) / nee_chain)) events, each
+     * weighted by 1/K of it: more events where the chain is long, one where
+     * it is short.  K depends on N only (drawn before the events), so the
+     * estimate stays unbiased.  At most 2^24. */
+    int32_t nee_chain;
 } ms_render_desc;
 
 /* MS_RENDER_NEE_BEFORE_ABSORPTION: direct light of a learned step estimated

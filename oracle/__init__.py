@@ -80,7 +80,8 @@ class _RenderDesc(C.Structure):
                 ("act_scales", C.c_void_p * 3), ("tau_min", C.c_double), ("st_max", C.c_double),
                 ("spp", C.c_int32), ("seed", C.c_uint64), ("sample_offset", C.c_uint64),
                 ("max_events", C.c_uint32), ("pixels", C.c_void_p), ("n_pixels", C.c_int64),
-                ("n_threads", C.c_int32), ("nee_samples", C.c_int32), ("flags", C.c_int32)]
+                ("n_threads", C.c_int32), ("nee_samples", C.c_int32), ("flags", C.c_int32),
+                ("nee_chain", C.c_int32)]
 
 
 class _StepResult(C.Structure):
@@ -367,7 +368,8 @@ class Scene:
 
 def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLER_CVAE,
            precision=PREC_FP64, models=None, tau_min=0.1, st_max=200.0, spp=1, seed=0,
-           sample_offset=0, max_events=1 << 20, pixels=None, n_threads=None, nee_samples=1, flags=0):
+           sample_offset=0, max_events=1 << 20, pixels=None, n_threads=None, nee_samples=1, flags=0,
+           nee_chain=0):
     """Renders (a pixel subset of) an image; returns per-pixel sums over spp.
 
     camera: dict(eye, look_at, up, vfov_deg, width, height); light: dict(pos,
@@ -380,7 +382,8 @@ def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLE
                   camera["height"])
     lt = _Light((C.c_double * 3)(*light["pos"]), light["intensity"])
     md = _Medium(medium["sigma_t"], medium["g"], medium["albedo"])
-    rd, keep = _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_samples, flags)
+    rd, keep = _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_samples, flags,
+                            nee_chain)
     rd.spp, rd.sample_offset, rd.max_events = spp, sample_offset, max_events
     npx = camera["width"] * camera["height"]
     if pixels is not None:
@@ -397,7 +400,7 @@ def render(scene, camera, light, medium, method=METHOD_PLAIN_NEE, sampler=SAMPLE
     return res
 
 
-def _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_samples, flags):
+def _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_samples, flags, nee_chain=0):
     """Render descriptor and the arrays it points into (keep them alive)."""
     keep = []
     rd = _RenderDesc()
@@ -418,19 +421,19 @@ def _render_desc(method, sampler, precision, models, tau_min, st_max, seed, nee_
         else:
             rd.shapes[i] = _shape(list(SHAPES.values())[i])
     rd.tau_min, rd.st_max, rd.seed = tau_min, st_max, seed
-    rd.nee_samples, rd.flags = nee_samples, flags
+    rd.nee_samples, rd.flags, rd.nee_chain = nee_samples, flags, nee_chain
     rd.max_events = 1 << 20
     return rd, keep
 
 
 def sphere_step(medium, p, d, r, path_id, c0=0, models=None, sampler=SAMPLER_CVAE, precision=PREC_FP64,
-                seed=0, nee_samples=1, flags=0):
+                seed=0, nee_samples=1, flags=0, nee_chain=0):
     """One sphere step around p (radius r, entered along unit d) for the path
     with Philox id path_id, its draw counter at c0: the learned step (models as
     for render) or the exact in-sphere walk.  Returns the world-frame exit,
     representative events, weights, N, survival, psi and the counter after
     the step."""
-    rd, keep = _render_desc(METHOD_ST, sampler, precision, models, 0.0, 200.0, seed, nee_samples, flags)
+    rd, keep = _render_desc(METHOD_ST, sampler, precision, models, 0.0, 200.0, seed, nee_samples, flags, nee_chain)
     md = _Medium(medium["sigma_t"], medium["g"], medium["albedo"])
     pa = np.ascontiguousarray(p, dtype=np.float64)
     da = np.ascontiguousarray(d, dtype=np.float64)

@@ -189,6 +189,9 @@ typedef struct {
     int32_t n_threads;
     int32_t nee_samples;   /* representative events per CVAE step (0 = 1), at most 16 */
     int32_t flags;         /* OR_NEE_BEFORE_ABSORPTION */
+    int32_t nee_chain;     /* > 0: a step of N events takes min(nee_samples,
+                            * 1 + floor((N - 1) / nee_chain)) representative
+                            * events; 0: nee_samples for every step */
 } or_render_desc;
 
 /* CVAE steps estimate their direct light before the absorption test, with

@@ -399,6 +399,14 @@ static void or_cvae_step(const or_render_desc* rd, const or_medium* md, uint64_t
     double phiN = exp(N * log(phi));
     out->survived = u[0] <= phiN;
     int lit = before ? 1 : out->survived;
+    /* With nee_chain, the step's own number of representative events: one
+     * more per nee_chain events of its chain, up to nee_samples (the
+     * variance of a one-event estimate grows with the square of its weight,
+     * which grows with N; K follows N alone, so the estimate stays unbiased) */
+    if (rd->nee_chain > 0) {
+        int64_t more = ((int64_t)N - 1) / rd->nee_chain;
+        if (more + 1 < K) K = (int)(more + 1);
+    }
     out->n_rep = lit ? K : 0;
     /* Lambda^(N) = sum_{i=1..N} albedo^i; survivors carry Lambda / albedo^N */
     double lam = phi >= 1.0 ? N : phi * -expm1(N * log(phi)) / (1.0 - phi);

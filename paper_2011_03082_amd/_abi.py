@@ -74,7 +74,7 @@ class RenderDesc(C.Structure):
                 ("seed", C.c_uint64), ("sample_offset", C.c_uint64), ("max_events", C.c_uint32),
                 ("blocks_per_cu", C.c_int32), ("cvae_batch_min", C.c_int32), ("restart_min", C.c_int32), ("max_wait", C.c_int32),
                 ("nee_samples", C.c_int32),
-                ("flags", C.c_int32), ("min_chain", C.c_float)]
+                ("flags", C.c_int32), ("min_chain", C.c_float), ("nee_chain", C.c_int32)]
 
 
 class ImageOut(C.Structure):

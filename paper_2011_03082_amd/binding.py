@@ -247,10 +247,11 @@ def make_medium(med):
 
 def render_desc(method, sampler=_abi.SAMPLER_CVAE, packed=(None, None, None), tau_min=0.1, st_max=200.0, spp=1,
                 chunk=0, seed=0, sample_offset=0, max_events=1 << 20, blocks_per_cu=0, cvae_batch_min=0,
-                nee_samples=1, flags=0, restart_min=0, max_wait=0, min_chain=0.0):
+                nee_samples=1, flags=0, restart_min=0, max_wait=0, min_chain=0.0, nee_chain=0):
     ptrs = (C.c_void_p * 3)(*[None if p is None else p.data_ptr() for p in packed])
     return _abi.RenderDesc(method, sampler, ptrs, tau_min, st_max, spp, chunk, seed, sample_offset, max_events,
-                           blocks_per_cu, cvae_batch_min, restart_min, max_wait, nee_samples, flags, min_chain)
+                           blocks_per_cu, cvae_batch_min, restart_min, max_wait, nee_samples, flags, min_chain,
+                           nee_chain)
 
 
 IMAGE_FIELDS = ("sum", "comp", "sumsq", "events", "steps", "counters")

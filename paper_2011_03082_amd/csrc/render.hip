@@ -73,7 +73,7 @@ struct RenderArgs {
     int batch_min;
     int restart_min;
     int max_wait;
-    int nee_samples;
+    int nee_samples, nee_chain;
     int flags;
     UnitRecord* part;  // [n_units], unit = pixel * n_chunks + chunk
     unsigned long long* ticket;
@@ -986,7 +986,19 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
         // Lambda and Lambda / albedo^N each in a form that stays finite
         // for any N (their product form overflows once albedo^-N does)
         const float lam = lambda_total(A, N);
-        const float w_nee = (before ? lam : lambda_weight(A, N)) / (float)A.nee_samples;
+        // this step's representative events: nee_samples, or with nee_chain
+        // one more per nee_chain events of the chain, up to nee_samples (an
+        // integer rule on N, so that the draws follow N alone): event k > 0
+        // exists iff N - 1 >= k nee_chain
+        auto events_of = [&](float n) __attribute__((always_inline)) -> int {
+            if (A.nee_chain <= 0) return A.nee_samples;
+            const uint32_t more = ((uint32_t)n - 1u) / (uint32_t)A.nee_chain;
+            return more + 1u < (uint32_t)A.nee_samples ? (int)more + 1 : A.nee_samples;
+        };
+        auto has_event = [&](int k) __attribute__((always_inline)) -> bool {
+            return A.nee_chain <= 0 || k == 0 || (uint32_t)N - 1u >= (uint32_t)k * (uint32_t)A.nee_chain;
+        };
+        const float w_nee = (before ? lam : lambda_weight(A, N)) / (float)events_of(N);
         float ct = 0.0f, al = 0.0f, be = 0.0f, ga = 1.0f;
         if (lit && !use_path) ct = hg_sample(A.g, u_hg).mu;
         const uint64_t pmask = ballot(use_path);
@@ -1018,35 +1030,48 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
             cp = cos_rev(psi);
             sp = sin_rev(psi);
         }
-        // The K representative events: event k's first-event test draws a
-        // block (k > 0) and, where EventGen answers, its normals follow; the
-        // EventGen rows of a group of events are decoded together (a lane's
-        // rows consecutive), as many events per group as 64 rows hold.
+        // The step's representative events: event k's first-event test
+        // draws a block (k > 0) and, where EventGen answers, its normals
+        // follow; the EventGen rows of a group of events are decoded together
+        // (a lane's rows consecutive), as many events per group as 64 rows
+        // hold.  The groups run to the wave's largest event count.
+        int k_all = A.nee_samples;
+        if (A.nee_chain > 0) {
+            float n_max = lit ? N : 1.0f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) n_max = __builtin_fmaxf(n_max, __shfl_xor(n_max, off));
+            // the same in every lane: a scalar loop bound
+            k_all = __builtin_amdgcn_readfirstlane(events_of(n_max));
+        }
         const int n_cand = __popcll(ballot(use_path));
-        const int group = n_cand > 0 ? (64 / n_cand < 1 ? 1 : 64 / n_cand) : A.nee_samples;
+        const int group = n_cand > 0 ? (64 / n_cand < 1 ? 1 : 64 / n_cand) : k_all;
         const int nb_ev = (A.pm[2]->latent + 6 + 3) >> 2;
         const float c7[7] = {lst, A.g, A.albedo, ct, al, be, lnN};
-        for (int ka = 0; ka < A.nee_samples; ka += group) {
-            const int kb = ka + group < A.nee_samples ? ka + group : A.nee_samples;
+        for (int ka = 0; ka < k_all; ka += group) {
+            const int kb = ka + group < k_all ? ka + group : k_all;
             // decisions and draw positions of the group's events
+            // bit k - ka: event k asks EventGen; bit 16 + k - ka: event k is
+            // one of this lit step's (a group holds at most 16 events)
             uint32_t evbits = 0;
             const uint32_t c0_group = pc0;
             for (int k = ka; k < kb; ++k) {
+                const bool has = lit && has_event(k);
                 float uf = u_first;
-                if (k > 0 && lit) uf = u01(prng.block(pc0++).x);
-                if (use_path && (paper || !(uf * lam <= A.albedo))) {
+                if (k > 0 && has) uf = u01(prng.block(pc0++).x);
+                if (has) evbits |= 1u << (16 + k - ka);
+                if (use_path && has && (paper || !(uf * lam <= A.albedo))) {
                     evbits |= 1u << (k - ka);
                     pc0 += (uint32_t)nb_ev;
                 }
             }
             int n_rows;
-            const int base = wave_prefix_small(__popc(evbits), n_rows);
+            const int base = wave_prefix_small(__popc(evbits & 0xFFFFu), n_rows);
             if (n_rows > 0) {
                 // EventGen (sigma_t r, g, albedo, cos theta, alpha, beta, N) -> (X, W)
                 uint32_t c = c0_group;
                 int j = 0;
                 for (int k = ka; k < kb; ++k) {
-                    if (k > 0 && lit) ++c;
+                    if (k > 0 && ((evbits >> (16 + k - ka)) & 1u)) ++c;
                     if ((evbits >> (k - ka)) & 1u) stage_row<6, 7>(A.pm[2], L, base + j++, prng, c, c7);
                 }
                 stage_normals<6>(A, A.pm[2], L, n_rows);
@@ -1065,7 +1090,8 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                     W = wl2 > 0.0f ? fast_rsq(wl2) * W : v3(0, 0, 1);
                 }
                 V3 Xw = v3(0, 0, 0), Ww = v3(0, 0, 1);
-                if (lit) {
+                const bool lit_k = ((evbits >> (16 + k - ka)) & 1u) != 0;
+                if (lit_k) {
                     // (X, W) rotated by psi about w_in, then into R = [e1 e2 d]
                     const V3 Xt = v3(cp * X.x - sp * X.y, sp * X.x + cp * X.y, X.z);
                     const V3 Wt = v3(cp * W.x - sp * W.y, sp * W.x + cp * W.y, W.z);
@@ -1075,8 +1101,8 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                 }
                 if constexpr (kWaveLight) {
                     uint64_t mk[kMaxManyPrims / 64];
-                    G.light_mask(A, lit, Xw, mk);
-                    if (lit) pLp += w_nee * G.light_masked(A, Xw, Ww, mk);
+                    G.light_mask(A, lit_k, Xw, mk);
+                    if (lit_k) pLp += w_nee * G.light_masked(A, Xw, Ww, mk);
                 }
             }
             wave_sync();
@@ -1394,6 +1420,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     // tau_min > 0 keeps every learned step off radius 0 (no log(0) condition)
     MS_REQUIRE(desc->tau_min > 0.0f && desc->st_max > 0.0f, "sphere_trace_render: need tau_min > 0, st_max > 0");
     MS_REQUIRE(desc->min_chain >= 0.0f, "sphere_trace_render: min_chain must be >= 0");
+    MS_REQUIRE(desc->nee_chain >= 0 && desc->nee_chain <= (1 << 24), "sphere_trace_render: nee_chain must be in [0, 2^24]");
     MS_REQUIRE(desc->nee_samples >= 0 && desc->nee_samples <= 16, "sphere_trace_render: nee_samples must be in [0, 16]");
     MS_REQUIRE(desc->restart_min >= 0 && desc->restart_min <= 64, "sphere_trace_render: restart_min must be in [0, 64]");
     MS_REQUIRE(desc->max_wait >= 0, "sphere_trace_render: max_wait must be >= 0");
@@ -1476,6 +1503,7 @@ ms_status sphere_trace_render(const ms_scene* scene, const ms_camera* cam, const
     A.max_events = desc->max_events ? desc->max_events : (1u << 20);
     A.batch_min = desc->cvae_batch_min ? desc->cvae_batch_min : 20;
     A.nee_samples = desc->nee_samples ? desc->nee_samples : 1;
+    A.nee_chain = desc->nee_chain;
     A.restart_min = desc->restart_min ? desc->restart_min : 16;
     A.max_wait = desc->max_wait ? desc->max_wait : 10;
     A.flags = desc->flags;

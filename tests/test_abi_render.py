@@ -145,3 +145,8 @@ def test_mesh_bvh_rejects_invalid(M):
 def test_render_rejects_negative_min_chain(M):
     assert status(M, desc=desc_with(M, min_chain=-1.0)) == M._abi.MS_ERR_INVALID_ARGUMENT
     assert b"min_chain" in M.lib().ms_last_error()
+
+
+def test_render_rejects_negative_nee_chain(M):
+    assert status(M, desc=desc_with(M, nee_chain=-1)) == M._abi.MS_ERR_INVALID_ARGUMENT
+    assert b"nee_chain" in M.lib().ms_last_error()

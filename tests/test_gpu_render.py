@@ -143,22 +143,24 @@ def test_learned_sphere_tracing_path_by_path(msst, oracle, precision, calibrated
     assert frac < 1e-3
 
 
-@pytest.mark.parametrize("nee_samples,flags", [(2, 0), (3, 1), (1, 2), (2, 3)])
-def test_learned_steps_with_several_events_path_by_path(msst, oracle, nee_samples, flags):
-    """K representative events per learned step, optionally lit before the
-    absorption test, and the paper's step as printed (flag 2: PathGen and
+@pytest.mark.parametrize("nee_samples,flags,chain", [(2, 0, 0), (3, 1, 0), (1, 2, 0), (2, 3, 0), (4, 1, 8),
+                                                     (3, 0, 12), (3, 3, 6)])
+def test_learned_steps_with_several_events_path_by_path(msst, oracle, nee_samples, flags, chain):
+    """K representative events per learned step (chain > 0: K set per step
+    by its chain length N, from one up to nee_samples), optionally lit before
+    the absorption test, and the paper's step as printed (flag 2: PathGen and
     EventGen in every case, no exact single-event parts): same draws, same
     per-path values as the oracle."""
-    announce(f"render ST CVAE parity K={nee_samples} flags={flags}")
+    announce(f"render ST CVAE parity K={nee_samples} flags={flags} nee_chain={chain}")
     prims, cam, light, med = c4_inputs(20.0, 40)
     med["albedo"] = float(np.float32(0.97))
     models, src = models_for_test(oracle)
     packed = pack_all(msst, src, 1)
     g = gpu_render(msst, prims, cam, light, med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=15,
-                   nee_samples=nee_samples, flags=flags)
+                   nee_samples=nee_samples, flags=flags, nee_chain=chain)
     o = oracle.render(oracle.Scene(prims), cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
                       precision=oracle.PREC_BF16, models=models, spp=1, seed=15, nee_samples=nee_samples,
-                      flags=flags)
+                      flags=flags, nee_chain=chain)
     frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; sphere steps {o['steps'].sum()}, events {o['events'].sum()}")
     assert o["steps"].sum() > 100
@@ -470,9 +472,11 @@ def test_c5_path_by_path(msst, oracle, method, sampler):
         assert o["steps"].sum() > 50
 
 
-@pytest.mark.parametrize("precision", [1, 2])
-def test_c5_learned_path_by_path(msst, oracle, precision):
-    announce(f"render C5 ST CVAE parity precision={precision}")
+@pytest.mark.parametrize("precision,nee_samples,chain", [(1, 1, 0), (2, 1, 0), (1, 3, 8)])
+def test_c5_learned_path_by_path(msst, oracle, precision, nee_samples, chain):
+    """The 64-sphere scene over its grid (shadow rays under the wave's
+    shared primitive mask), also with events per step set by the chain."""
+    announce(f"render C5 ST CVAE parity precision={precision} K={nee_samples} nee_chain={chain}")
     prims, cam, light, med = c5_inputs(32)
     res = 128
     grid_g = msst.build_sdf_grid(prims, res)
@@ -480,12 +484,13 @@ def test_c5_learned_path_by_path(msst, oracle, precision):
     models, src = models_for_test(oracle)
     packed = pack_all(msst, src, precision)
     r = msst.Renderer(prims, cam, light, grid=grid_g)
-    out = r.render(med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=22)
+    out = r.render(med, method=ST, sampler=CVAE, packed=packed, spp=1, seed=22, nee_samples=nee_samples,
+                   nee_chain=chain)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in out.items()}
     o = oracle.render(oracle.Scene(prims, sdf_fp16=grid_o), cam, light, med, method=oracle.METHOD_ST,
                       sampler=oracle.SAMPLER_CVAE, precision=oracle.PREC_BF16 if precision == 1 else oracle.PREC_FP8,
-                      models=models, spp=1, seed=22)
+                      models=models, spp=1, seed=22, nee_samples=nee_samples, nee_chain=chain)
     frac, _ = compare_paths(g, o, rel=LEARNED_REL)
     print(f"diverged {frac:.2e}; steps {o['steps'].sum()}")
     assert o["steps"].sum() > 50

@@ -189,11 +189,12 @@ def test_exact_walk_sphere_steps_match_plain_path_tracing(oracle, c4, sigma_t):
 
 
 def test_learned_step_estimators_share_their_expectation(oracle, c4):
-    """Averaging K representative events, or adding the direct light of every
-    learned step before its absorption test with weight sum_i albedo^i instead
-    of survivors only with that sum over albedo^N, leaves the expectation of
-    the sphere-traced estimator unchanged (Sec. 3.2, Sec. 4.3); the models are
-    untrained but fixed, so all four variants estimate the same quantity."""
+    """Averaging K representative events (also K set per step by the chain
+    length N), or adding the direct light of every learned step before its
+    absorption test with weight sum_i albedo^i instead of survivors only with
+    that sum over albedo^N, leaves the expectation of the sphere-traced
+    estimator unchanged (Sec. 3.2, Sec. 4.3); the models are untrained but
+    fixed, so all the variants estimate the same quantity."""
     cam, light, _ = small_c4(40.0, 12)
     med = dict(sigma_t=40.0, g=0.8, albedo=0.95)
     models = [dict(shape=W.SHAPE_LIST[m], params=oracle.cvae_init(W.SHAPE_LIST[m], seed=70 + m),
@@ -201,10 +202,12 @@ def test_learned_step_estimators_share_their_expectation(oracle, c4):
     spp = 192
     n = spp * cam["width"] * cam["height"]
     res = []
-    for i, (k, flags) in enumerate([(1, 0), (3, 0), (1, oracle.NEE_BEFORE_ABSORPTION),
-                                     (2, oracle.NEE_BEFORE_ABSORPTION)]):
+    for i, (k, flags, chain) in enumerate([(1, 0, 0), (3, 0, 0), (1, oracle.NEE_BEFORE_ABSORPTION, 0),
+                                            (2, oracle.NEE_BEFORE_ABSORPTION, 0),
+                                            (4, oracle.NEE_BEFORE_ABSORPTION, 3), (3, 0, 2)]):
         o = oracle.render(c4, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE,
-                          models=models, tau_min=1.0, spp=spp, seed=40 + i, nee_samples=k, flags=flags)
+                          models=models, tau_min=1.0, spp=spp, seed=40 + i, nee_samples=k, flags=flags,
+                          nee_chain=chain)
         m = o["sum"].sum() / n
         res.append((m, np.sqrt((o["sumsq"].sum() / n - m * m) / n), o["steps"].sum()))
     m0, s0, st0 = res[0]
@@ -217,3 +220,29 @@ def test_learned_step_estimators_share_their_expectation(oracle, c4):
     b = oracle.render(c4, cam, light, med, method=oracle.METHOD_ST, sampler=oracle.SAMPLER_CVAE, models=models,
                       tau_min=1.0, spp=2, seed=40, nee_samples=0)
     np.testing.assert_array_equal(a["sum"], b["sum"])
+
+
+def test_events_per_step_follow_the_chain_length(oracle):
+    """nee_chain: a step of N events takes min(nee_samples, 1 + (N - 1) //
+    nee_chain) representative events.  The rule follows N alone, so a step
+    whose chain asks for one event is the one-event step bit for bit (the same
+    draws), and one whose chain asks for all nee_samples events is the
+    uniform step with that many."""
+    models = [dict(shape=W.SHAPE_LIST[m], params=oracle.cvae_init(W.SHAPE_LIST[m], seed=80 + m),
+                   stats=W.render_test_stats(m)) for m in range(3)]
+    med = dict(sigma_t=40.0, g=0.8, albedo=0.99)
+    p, d, r = np.array([0.1, 0.0, 0.2]), np.array([0.0, 0.6, 0.8]), 0.5
+    kw = dict(models=models, flags=oracle.NEE_BEFORE_ABSORPTION)
+    seen = set()
+    for path_id in range(300):
+        a = oracle.sphere_step(med, p, d, r, path_id, nee_samples=4, nee_chain=6, **kw)
+        n = int(a["N"])
+        k = min(4, 1 + (n - 1) // 6)
+        assert a["n_rep"] == k
+        seen.add(k)
+        same = oracle.sphere_step(med, p, d, r, path_id, nee_samples=k, **kw)
+        for key in ("x", "w", "nee_w", "N", "psi", "c0"):
+            np.testing.assert_array_equal(a[key], same[key])
+        np.testing.assert_array_equal(a["X"][:k], same["X"][:k])
+        np.testing.assert_array_equal(a["first"][:k], same["first"][:k])
+    assert seen >= {1, 2}, seen
