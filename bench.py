@@ -389,6 +389,15 @@ def cpu_model_name():
     return "unknown"
 
 
+def default_chunk(npix, spp):
+    """The renderer's default samples per work unit (the rule its C header
+    states for ms_render_desc.chunk = 0)."""
+    c = min(64, -(-npix * spp // (1 << 23)))
+    if npix * -(-spp // c) > (1 << 24):
+        c = -(-npix * spp // (1 << 24))
+    return min(spp, max(2, c))
+
+
 def subset_pixels(width, height, stride=16):
     """Every stride-th pixel in x and y (the centre of each stride x stride block)."""
     import numpy as np
@@ -714,7 +723,7 @@ def main():
             med_s = W.medium_c4(s)
             # the timed renders' samples per work unit (the header's default
             # rule at spp), so that only the sample count differs
-            unit = args.chunk or min(spp, max(2, -(-npix * spp // (1 << 24))))
+            unit = args.chunk or default_chunk(npix, spp)
             kw_c = dict(kw, chunk=min(unit, s_conf))
             img_c, t_c = timed_mean(lambda: rend.render(med_s, method=1, spp=s_conf, seed=2501, **kw_c), args.steps)
             mc, _ = image_moments(img_c, s_conf)

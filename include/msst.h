@@ -353,7 +353,9 @@ typedef struct {
      * st_range): tau_min below 0.1 or st_max above 200 asks them to extrapolate. */
     float tau_min, st_max;
     int32_t spp;
-    int32_t chunk;           /* samples per work unit; 0 = max(2, ceil(pixels spp / 2^24)); at most 2^32 units */
+    int32_t chunk;           /* samples per work unit; 0 = min(64, ceil(pixels spp / 2^23)), or
+                              * ceil(pixels spp / 2^24) where that leaves more than 2^24 units,
+                              * at least 2 and at most spp; at most 2^32 units */
     uint64_t seed, sample_offset;
     uint32_t max_events;     /* per path; 0 = 2^20 */
     int32_t blocks_per_cu;   /* 256-thread blocks per CU, 1..64; 0 = 4 */

@@ -1359,8 +1359,15 @@ static void launch_render(int mode, dim3 grid, dim3 block, hipStream_t hs, const
     else hipLaunchKernelGGL((render_kernel<kModeStCvae, NP, GRID>), grid, block, lds, hs, A);
 }
 
+// Samples per work unit: about 2^23 units (32 per lane of a full launch,
+// enough to balance it) of at most 64 samples (longer units leave a longer
+// tail); a launch that would then exceed 2^24 units takes longer units to
+// keep its record buffer bounded.
 static int default_chunk(int64_t npix, int spp) {
-    int64_t c = (npix * spp + (1 << 24) - 1) >> 24;
+    const int64_t total = npix * spp;
+    int64_t c = (total + (1 << 23) - 1) >> 23;
+    if (c > 64) c = 64;
+    if (npix * ((spp + c - 1) / c) > (1 << 24)) c = (total + (1 << 24) - 1) >> 24;
     if (c < 2) c = 2;
     if (c > spp) c = spp;
     return (int)c;

@@ -150,3 +150,16 @@ def test_render_rejects_negative_min_chain(M):
 def test_render_rejects_negative_nee_chain(M):
     assert status(M, desc=desc_with(M, nee_chain=-1)) == M._abi.MS_ERR_INVALID_ARGUMENT
     assert b"nee_chain" in M.lib().ms_last_error()
+
+
+@pytest.mark.parametrize("w,h,spp", [(512, 512, 256), (256, 256, 256), (1024, 1024, 1024), (2048, 2048, 1024),
+                                     (32, 32, 3), (7, 5, 5)])
+def test_workspace_follows_the_default_samples_per_unit(M, w, h, spp):
+    """The workspace holds one 16-byte record per work unit, the units being
+    the pixels times ceil(spp / chunk) at the header's default chunk (the rule
+    bench.default_chunk restates), after 256 bytes of counters."""
+    import bench
+    chunk = bench.default_chunk(w * h, spp)
+    n_units = w * h * -(-spp // chunk)
+    need = 256 + -(-n_units * 16 // 256) * 256
+    assert M.sphere_trace_render_workspace_size(camera(M, width=w, height=h), M.render_desc(1, spp=spp)) == need

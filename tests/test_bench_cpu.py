@@ -92,3 +92,15 @@ def test_subset_pixels_and_anchor_statistics():
     sub2["var"][0] = 1e-60
     a2 = bench.anchor_stats(sub2, ref2, ref_var2, n_r, {"x": img}, pt_var)
     assert a2["lit_pixels"] == pix.size - 1 and a2["z_max"] < 1.0
+
+
+def test_default_samples_per_unit():
+    """The header's rule for ms_render_desc.chunk = 0 at the shapes rendered:
+    about 2^23 units of at most 64 samples, longer where that would leave more
+    than 2^24 units, at least 2."""
+    assert bench.default_chunk(512 * 512, 256) == 8
+    assert bench.default_chunk(256 * 256, 256) == 2
+    assert bench.default_chunk(1024 * 1024, 1024) == 64
+    assert bench.default_chunk(2048 * 2048, 1024) == 256
+    assert bench.default_chunk(32 * 32, 3) == 2
+    assert bench.default_chunk(7, 1) == 1
