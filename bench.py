@@ -104,6 +104,9 @@ def parse(argv=None):
     ap.add_argument("--density-sigmas", type=str, default="80,160,320,640,1280")
     ap.add_argument("--density-albedo", type=float, default=0.9999)
     ap.add_argument("--density-width", type=int, default=256)
+    ap.add_argument("--mesh-chunk", type=int, default=4,
+                    help="samples per work unit in the mesh section (measured 7-8 %% faster than the renderer's "
+                         "default of 8 at 512^2 x 256 spp)")
     ap.add_argument("--density-nee-samples", type=int, default=2,
                     help="representative events per learned step in the density sweep (its chains run to 10^4 "
                          "events, and a second event halves the heavy tail of their direct light)")
@@ -880,16 +883,17 @@ def main():
         mr = M.Renderer(None, W.camera_mesh(width, width), W.light_c4(), grid=grid, grid_lo=lo, grid_hi=hi, tris=tris)
         mesh = {"workload": f"closed mesh, {tris.shape[0]} triangles, {width}x{width}, {spp} spp, g=0.8, albedo=0.995",
                 "grid_seconds": t_grid}
+        kw_m = dict(kw, chunk=args.chunk or args.mesh_chunk)
         for s_ in (40.0, 80.0):
             med = W.medium_c4(s_)
-            img = mr.render(med, method=1, spp=args.ref_spp // 2, seed=9300, **kw)
+            img = mr.render(med, method=1, spp=args.ref_spp // 2, seed=9300, **kw_m)
             rm, rv = image_moments(img, args.ref_spp // 2)
             noise2 = float(rv.mean()) / (args.ref_spp // 2)
-            img_pt, t_pt = timed(lambda: mr.render(med, method=1, spp=spp, seed=9400, **kw))
+            img_pt, t_pt = timed(lambda: mr.render(med, method=1, spp=spp, seed=9400, **kw_m))
             pm, pv = image_moments(img_pt, spp)
             img_st, t_st = timed(lambda: mr.render(med, method=2, sampler=0, packed=packed, spp=spp, seed=9500,
                                                    tau_min=args.tau_min, nee_samples=args.nee_samples,
-                                                   flags=args.nee_flags, min_chain=args.min_chain, **kw))
+                                                   flags=args.nee_flags, min_chain=args.min_chain, **kw_m))
             sm, _ = image_moments(img_st, spp)
             e_st = max(float(((sm - rm) ** 2).mean()) - noise2, 1e-30)
             e_pt = max(float(((pm - rm) ** 2).mean()) - noise2, 1e-30)
