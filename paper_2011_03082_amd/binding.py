@@ -3,10 +3,11 @@
 Functions named like the C entry points take torch device tensors and plain
 numbers, fill the C descriptor structs and call the library on the current
 torch stream.  The helpers at the bottom only allocate outputs and
-workspaces and then call those functions; every step of the computation runs
-in the HIP kernels.
+workspaces and then call those functions, or write and read a model's
+training state; every step of the computation runs in the HIP kernels.
 """
 import ctypes as C
+import json
 
 import torch
 
@@ -186,6 +187,63 @@ def cvae_train_step_noalloc(shape, master, adam_m, adam_v, adam, cond, target, n
                                         None if adam is None else C.byref(adam), _ptr(cond), _ptr(target), n_rows,
                                         batch, sample_rows, seed, step, id_offset, kl_weight, _ptr(loss), _ptr(grad),
                                         _stream(stream)))
+
+
+TRAINING_STATE_FORMAT = "msst-cvae-training-state-1"
+
+
+def save_training_state(path, shape, master, adam_m, adam_v, step, stats=None, extra=None):
+    """Writes one CVAE's training state to a safetensors file: the FP32 master
+    weights, AdamW's first and second moments, the number of steps taken and
+    optionally the FP64 standardisation constants [64] and a JSON-able dict
+    `extra` (the training seed, schedule, ...).  The training step draws its
+    rows and noise from counter-based streams keyed by (seed, step) and
+    reduces its gradient in a fixed order, so continuing from the loaded
+    state with the next step number reproduces an uninterrupted run bit for
+    bit."""
+    from safetensors.torch import save_file
+    sh = cvae_shape(shape)
+    n = cvae_param_count(sh)
+    tensors = {}
+    for name, t in (("master", master), ("adam_m", adam_m), ("adam_v", adam_v)):
+        if t.dtype != torch.float32 or t.numel() != n:
+            raise ValueError(f"{name}: expected {n} float32 values, got {t.numel()} {t.dtype}")
+        tensors[name] = t.detach().reshape(-1).cpu().contiguous()
+    if stats is not None:
+        if stats.dtype != torch.float64 or stats.numel() != 64:
+            raise ValueError("stats: expected 64 float64 standardisation constants")
+        tensors["stats"] = stats.detach().reshape(-1).cpu().contiguous()
+    if int(step) < 0:
+        raise ValueError("step must be >= 0")
+    shape_d = {k: int(getattr(sh, k)) for k, _ in _abi.CvaeShape._fields_}
+    meta = {"format": TRAINING_STATE_FORMAT, "shape": json.dumps(shape_d), "step": str(int(step)),
+            "extra": json.dumps({} if extra is None else extra)}
+    save_file(tensors, str(path), metadata=meta)
+
+
+def load_training_state(path, device="cuda"):
+    """Reads a file written by save_training_state; returns dict(shape, master,
+    adam_m, adam_v, step, stats (None if not saved), extra) with the tensors
+    on `device`.  Raises ValueError for a file of another format or whose
+    tensors do not match the stored shape."""
+    from safetensors import safe_open
+    with safe_open(str(path), framework="pt") as f:
+        meta = f.metadata() or {}
+        if meta.get("format") != TRAINING_STATE_FORMAT:
+            raise ValueError(f"{path}: not a CVAE training state ({meta.get('format')!r})")
+        shape = json.loads(meta["shape"])
+        keys = set(f.keys())
+        t = {k: f.get_tensor(k) for k in keys}
+    n = cvae_param_count(shape)
+    for name in ("master", "adam_m", "adam_v"):
+        if name not in t or t[name].dtype != torch.float32 or t[name].numel() != n:
+            raise ValueError(f"{path}: {name} does not hold {n} float32 values")
+    stats = t.get("stats")
+    if stats is not None and (stats.dtype != torch.float64 or stats.numel() != 64):
+        raise ValueError(f"{path}: stats does not hold 64 float64 values")
+    return dict(shape=shape, master=t["master"].to(device), adam_m=t["adam_m"].to(device),
+                adam_v=t["adam_v"].to(device), step=int(meta["step"]),
+                stats=None if stats is None else stats.to(device), extra=json.loads(meta.get("extra", "{}")))
 
 
 def cvae_packed_bytes():

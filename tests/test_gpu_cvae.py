@@ -294,3 +294,43 @@ def test_sample_fp8_matches_fp8_emulating_oracle(msst, oracle, model, calibrated
     # the same rule as for bfloat16 with E4M3's unit roundoff (measured
     # median 0.14-0.37 u, p90 0.34-0.68 u)
     assert np.median(e64) < 0.5 * FP8_U and np.quantile(e64, 0.9) < FP8_U
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_resume_from_saved_state_is_bitwise(msst, tmp_path, model):
+    announce(f"cvae training resumed from a saved state, model={model}")
+    B, n_rows, steps, cut = 1024, 1 << 14, 12, 5
+    p_in, p_out = [(2, 1), (3, 3), (7, 6)][model]
+    rng = np.random.default_rng(40 + model)
+    cd = dev(rng.normal(size=(n_rows, p_in)))
+    td = dev(rng.normal(size=(n_rows, p_out)))
+    stats = msst.make_stats(cd, td)
+    n = msst.cvae_param_count(model)
+    ws = torch.empty(msst.cvae_workspace_size(model, B), dtype=torch.uint8, device="cuda")
+
+    def run(master, m, v, first, last):
+        loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+        for step in range(first, last + 1):
+            msst.cvae_train_step(model, master, m, v, msst.adam_params(step, lr=3e-3, weight_decay=0.01), cd, td,
+                                 n_rows, B, 1, 31, step, 0, ws, loss, kl_weight=min(1.0, step / 8))
+        return loss
+
+    master = torch.empty(n, dtype=torch.float32, device="cuda")
+    msst.cvae_init(model, 8, master)
+    m, v = torch.zeros_like(master), torch.zeros_like(master)
+    ref_loss = run(master, m, v, 1, steps)
+
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    msst.cvae_init(model, 8, a)
+    am, av = torch.zeros_like(a), torch.zeros_like(a)
+    run(a, am, av, 1, cut)
+    path = tmp_path / "state.safetensors"
+    msst.save_training_state(path, model, a, am, av, cut, stats=stats, extra={"seed": 31})
+    del a, am, av
+    st = msst.load_training_state(path)
+    assert st["step"] == cut and st["extra"] == {"seed": 31}
+    assert torch.equal(st["stats"], stats)
+    loss = run(st["master"], st["adam_m"], st["adam_v"], st["step"] + 1, steps)
+    for k, ref in (("master", master), ("adam_m", m), ("adam_v", v)):
+        assert torch.equal(st[k].view(torch.int32), ref.view(torch.int32)), k
+    assert torch.equal(loss, ref_loss)
