@@ -367,6 +367,71 @@ def measured_traffic():
         return None
 
 
+def primary_hit_labels(cam, prims):
+    """Per pixel of the camera (row-major, pixel centres): 0 where the primary
+    ray misses every primitive, else 1 + the index of the primitive it enters
+    first (pinhole camera of the renderer's ABI: forward, right and up axes
+    scaled by tan(vfov / 2) and the aspect ratio).  Measurement only: it
+    splits a render's per-pixel event and step counters by the part of the
+    body a pixel sees, the voluminous sphere or the thin box arm of the
+    sphere + box scene (the stand-in for the two kinds of geometry whose
+    event counts Sec. 5.4 compares)."""
+    import numpy as np
+    w, h = int(cam["width"]), int(cam["height"])
+    eye = np.asarray(cam["eye"], np.float64)
+    f = np.asarray(cam["look_at"], np.float64) - eye
+    f /= np.linalg.norm(f)
+    rt = np.cross(f, np.asarray(cam["up"], np.float64))
+    rt /= np.linalg.norm(rt)
+    uv = np.cross(rt, f)
+    th = np.tan(0.5 * np.radians(cam["vfov_deg"]))
+    px, py = np.meshgrid(np.arange(w) + 0.5, np.arange(h) + 0.5)
+    sx, sy = 2.0 * px / w - 1.0, 1.0 - 2.0 * py / h
+    d = f + (sx * th * w / h)[..., None] * rt + (sy * th)[..., None] * uv
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    best = np.full((h, w), np.inf)
+    label = np.zeros((h, w), np.int32)
+    for i, p in enumerate(np.asarray(prims, np.float64)):
+        q = eye - p[1:4]
+        if p[0] == 0.0:  # sphere: nearest root of |q + t d|^2 = r^2
+            b = d @ q
+            disc = b * b - (q @ q - p[4] ** 2)
+            with np.errstate(invalid="ignore"):
+                t0, t1 = -b - np.sqrt(disc), -b + np.sqrt(disc)
+            hit = (disc > 0.0) & (t1 > 0.0)
+            t = np.where(t0 > 0.0, t0, t1)
+        else:  # box: slabs
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ta = (-p[4:7] - q) / d
+                tb = (p[4:7] - q) / d
+            lo = np.nanmax(np.minimum(ta, tb), axis=-1)
+            hi = np.nanmin(np.maximum(ta, tb), axis=-1)
+            hit = (lo < hi) & (hi > 0.0)
+            t = np.where(lo > 0.0, lo, hi)
+        nearer = hit & (t < best)
+        best = np.where(nearer, t, best)
+        label = np.where(nearer, i + 1, label)
+    return label.reshape(-1)
+
+
+def region_counts(img, labels, spp, names):
+    """Events and sphere steps per path over the pixels of each label
+    (names: {label: name}): mean, 99th percentile and maximum of the
+    per-pixel means."""
+    import numpy as np
+    ev = img["events"].cpu().numpy().astype(np.float64) / spp
+    st = img["steps"].cpu().numpy().astype(np.float64) / spp
+    out = {}
+    for lab, name in names.items():
+        m = labels == lab
+        if not m.any():
+            continue
+        out[name] = dict(pixels=int(m.sum()), events_per_path=float(ev[m].mean()),
+                         events_p99=float(np.percentile(ev[m], 99)), events_max=float(ev[m].max()),
+                         steps_per_path=float(st[m].mean()), steps_p99=float(np.percentile(st[m], 99)))
+    return out
+
+
 def image_moments(img, spp):
     s = img["sum"].double() + img["comp"].double()
     mean = s / spp
@@ -997,6 +1062,8 @@ def main():
                                    model_steps=(args.train_steps, args.train_steps, args.density_event_steps))[0][1]
         dw = args.density_width
         drend = M.Renderer(W.scene_c4(), W.camera_c4(dw, dw), W.light_c4())
+        labels = primary_hit_labels(W.camera_c4(dw, dw), W.scene_c4())
+        region_names = {1: "sphere", 2: "box_arm"}
         for k, s_ in enumerate(float(x) for x in args.density_sigmas.split(",")):
             med = dict(W.medium_c4(s_), albedo=args.density_albedo)
             img = drend.render(med, method=1, spp=args.ref_spp, seed=9000 + k, **kw)
@@ -1025,7 +1092,9 @@ def main():
                        pt_events_per_path=float(cp[1] / cp[0]), st_events_per_path=float(cs[1] / cs[0]),
                        st_steps_per_path=float(cs[2] / cs[0]),
                        st_mean_bias=sm_mean / float(r_mean.mean()) - 1.0,
-                       speedup_matched_rmse=float(pv.mean()) / e_st**2 / spp * t_pt / t_st)
+                       speedup_matched_rmse=float(pv.mean()) / e_st**2 / spp * t_pt / t_st,
+                       regions=dict(pt=region_counts(img_pt, labels, spp, region_names),
+                                    st=region_counts(img_st, labels, spp, region_names)))
             if pk_ev is not None:
                 _, t_long, e_ev, se_mean = st_images(pk_ev, 9300 + k)
                 row.update(event_long=dict(eventgen_steps=args.density_event_steps, st_ms=t_long * 1e3, rmse_st=e_ev,
@@ -1037,6 +1106,12 @@ def main():
                 f"({row['st_events_per_path']:.1f} events + {row['st_steps_per_path']:.2f} steps), "
                 f"rmse {e_pt:.2e} / {e_st:.2e}, bias {row['st_mean_bias']:+.3f}, "
                 f"speed-up {row['speedup_matched_rmse']:.2f}")
+            for name in region_names.values():
+                rp, rs = row["regions"]["pt"].get(name), row["regions"]["st"].get(name)
+                if rp and rs:
+                    log(f"  {name} ({rp['pixels']} px): PT {rp['events_per_path']:.1f} events/path "
+                        f"(p99 {rp['events_p99']:.0f}), ST {rs['events_per_path']:.1f} events "
+                        f"(p99 {rs['events_p99']:.0f}) + {rs['steps_per_path']:.2f} steps")
 
     sweep = None
     if args.table1_sweep:

@@ -104,3 +104,64 @@ def test_default_samples_per_unit():
     assert bench.default_chunk(2048 * 2048, 1024) == 256
     assert bench.default_chunk(32 * 32, 3) == 2
     assert bench.default_chunk(7, 1) == 1
+
+
+def _project(cam, p):
+    """Pixel index (row-major) whose centre ray is nearest to world point p."""
+    eye = np.asarray(cam["eye"], float)
+    f = np.asarray(cam["look_at"], float) - eye
+    f /= np.linalg.norm(f)
+    rt = np.cross(f, cam["up"])
+    rt /= np.linalg.norm(rt)
+    uv = np.cross(rt, f)
+    th = np.tan(np.radians(cam["vfov_deg"]) / 2)
+    w, h = cam["width"], cam["height"]
+    v = np.asarray(p, float) - eye
+    sx = (v @ rt) / (v @ f) / (th * w / h)
+    sy = (v @ uv) / (v @ f) / th
+    px, py = int((sx + 1) / 2 * w), int((1 - sy) / 2 * h)
+    return py * w + px
+
+
+def test_primary_hit_labels_of_a_lone_sphere_cover_its_silhouette():
+    """The silhouette of a sphere of radius r seen from distance D subtends
+    a half-angle asin(r / D): a disc of radius tan(asin(r / D)) / tan(vfov / 2)
+    half-widths around the image centre."""
+    import workloads as W
+    w = 400
+    cam = dict(eye=(0.0, 0.0, 5.0), look_at=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), vfov_deg=30.0, width=w, height=w)
+    lab = bench.primary_hit_labels(cam, W.scene_sphere(1.0))
+    rad = np.tan(np.arcsin(1.0 / 5.0)) / np.tan(np.radians(15.0)) * (w / 2)
+    assert set(np.unique(lab)) == {0, 1}
+    assert abs((lab == 1).sum() / (np.pi * rad**2) - 1.0) < 0.01
+    # a wider image of the same view keeps the pixel aspect (the disc stays round)
+    cam2 = dict(cam, width=2 * w)
+    lab2 = bench.primary_hit_labels(cam2, W.scene_sphere(1.0)).reshape(w, 2 * w)
+    rows, cols = np.nonzero(lab2 == 1)
+    assert abs((cols.max() - cols.min()) / (rows.max() - rows.min()) - 1.0) < 0.02
+
+
+def test_primary_hit_labels_split_the_sphere_box_scene():
+    import workloads as W
+    cam = W.camera_c4(256, 256)
+    lab = bench.primary_hit_labels(cam, W.scene_c4())
+    # the arm's free end lies outside the sphere: its pixels see the box first
+    assert lab[_project(cam, (1.9, 0.0, 0.4))] == 2
+    assert lab[_project(cam, (1.6, 0.3, 0.4))] == 2
+    # the front of the sphere is nearer than the box buried in it
+    assert lab[_project(cam, (0.0, 0.0, 1.0))] == 1
+    assert lab[_project(cam, (-0.6, 0.5, 0.6))] == 1
+    # the corners of the view miss the body
+    assert lab[0] == 0 and lab[-1] == 0
+    n1, n2 = (lab == 1).sum(), (lab == 2).sum()
+    assert n1 > 2 * n2 > 0
+
+
+def test_region_counts_average_per_pixel_means():
+    labels = np.array([0, 1, 1, 2, 2, 2])
+    img = {"events": torch.tensor([9, 4, 8, 2, 2, 20], dtype=torch.int32),
+           "steps": torch.tensor([0, 2, 0, 0, 2, 0], dtype=torch.int32)}
+    r = bench.region_counts(img, labels, 2, {1: "sphere", 2: "box_arm", 3: "absent"})
+    assert set(r) == {"sphere", "box_arm"}
+    assert r["sphere"]["pixels"] == 2 and r["sphere"]["events_per_path"] == 3.0 and r["sphere"]["steps_per_path"] == 0.5
+    assert r["box_arm"]["events_per_path"] == 4.0 and r["box_arm"]["events_max"] == 10.0
