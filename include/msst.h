@@ -23,8 +23,11 @@
  *  - Randomness is Philox4x32-10 (Salmon et al., SC'11), counter =
  *    (draw index, id low word, id high word, stream tag), key = seed; so any
  *    split of an id range over calls or devices gives identical results.
- *  - Numerical events at run time (truncated walks, non-finite values) are
- *    reported through the optional counters, not through the status.
+ *  - Numerical events at run time do not change the status: truncated
+ *    walks and paths are counted in the optional counters, and non-finite
+ *    inputs or weights propagate to the outputs (cvae_train_step's loss and
+ *    gradient, an image's sums and with them ms_image_stats's mean), where
+ *    the caller tests for them.
  */
 #ifndef MSST_H
 #define MSST_H

@@ -334,3 +334,25 @@ def test_resume_from_saved_state_is_bitwise(msst, tmp_path, model):
     for k, ref in (("master", master), ("adam_m", m), ("adam_v", v)):
         assert torch.equal(st[k].view(torch.int32), ref.view(torch.int32)), k
     assert torch.equal(loss, ref_loss)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_master_weight_shows_in_loss_and_gradient(msst, bad):
+    """A non-finite master weight does not change the status; it reaches the
+    loss and the gradient, where a caller tests for it."""
+    announce(f"cvae non-finite master weight {bad}")
+    model, B, n_rows = 1, 256, 4096
+    rng = np.random.default_rng(6)
+    cd, td = dev(rng.normal(size=(n_rows, 3))), dev(rng.normal(size=(n_rows, 3)))
+    n = msst.cvae_param_count(model)
+    master = torch.empty(n, dtype=torch.float32, device="cuda")
+    msst.cvae_init(model, 3, master)
+    ws = torch.empty(msst.cvae_workspace_size(model, B), dtype=torch.uint8, device="cuda")
+    loss = torch.zeros(3, dtype=torch.float64, device="cuda")
+    grad = torch.zeros(n, dtype=torch.float32, device="cuda")
+    msst.cvae_train_step(model, master, None, None, None, cd, td, n_rows, B, 0, 5, 1, 0, ws, loss, grad)
+    assert torch.isfinite(loss).all() and torch.isfinite(grad).all()
+    real = np.flatnonzero(_real_mask(W.SHAPE_LIST[model]))
+    master[int(real[0])] = bad  # first weight of the encoder's first layer
+    msst.cvae_train_step(model, master, None, None, None, cd, td, n_rows, B, 0, 5, 1, 0, ws, loss, grad)
+    assert not torch.isfinite(loss[0]) and not torch.isfinite(grad).all()
