@@ -96,6 +96,8 @@ def parse(argv=None):
     ap.add_argument("--no-mesh", action="store_true")
     ap.add_argument("--no-focus", action="store_true")
     ap.add_argument("--no-density", action="store_true")
+    ap.add_argument("--jsonl", type=str, default=None,
+                    help="also append the result line to this file (one JSON object per run)")
     ap.add_argument("--no-confirm", action="store_true", help="skip the plain tracer's run at the matched spp")
     ap.add_argument("--no-walk-full", action="store_true")
     ap.add_argument("--no-sample", action="store_true")
@@ -1207,7 +1209,11 @@ def main():
         "diagnostics": diag,
         "wall_s_timed": wall,
     }
-    print(json.dumps(result), flush=True)
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.jsonl:
+        with open(args.jsonl, "a") as fh:
+            fh.write(line + "\n")
 
 
 if __name__ == "__main__":
