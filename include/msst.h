@@ -360,7 +360,10 @@ typedef struct {
                               * ceil(pixels spp / 2^24) where that leaves more than 2^24 units,
                               * at least 2 and at most spp; at most 2^32 units */
     uint64_t seed, sample_offset;
-    uint32_t max_events;     /* per path; 0 = 2^20 */
+    uint32_t max_events;     /* collisions per path (plain events plus sphere
+                              * steps, a step counting once); a path ends at
+                              * the next collision, keeping the light gathered
+                              * so far, and is counted as truncated; 0 = 2^20 */
     int32_t blocks_per_cu;   /* 256-thread blocks per CU, 1..64; 0 = 4 */
     int32_t cvae_batch_min;  /* waiting lanes that trigger a decoder pass, 1..64; 0 = 20 */
     int32_t restart_min;     /* lanes waiting for a new path that trigger a restart pass, 1..64; 0 = 16 */

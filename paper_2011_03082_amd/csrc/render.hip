@@ -95,6 +95,10 @@ struct RenderLds {
 
 enum : int { kModePlain = 0, kModeStExact = 1, kModeStCvae = 2 };
 
+// Events of one exact walk inside a sphere before it is cut off (the reference
+// sampler; a sphere of optical radius 200 takes about 10^5 on average).
+constexpr uint32_t kInnerWalkBound = 1u << 24;
+
 // ---------------------------------------------------------------- geometry
 
 __device__ __forceinline__ bool prim_interval(const float* pr, V3 o, V3 d, float& t0, float& t1) {
@@ -868,7 +872,10 @@ __device__ __forceinline__ void render_loop(const RenderArgs& A, RenderLds& L, c
                                     const float inv_phi = 1.0f / A.albedo;
                                     uint32_t nev = 0;
                                     for (;;) {
-                                        if (++nev > A.max_events) break;  // bounded even for degenerate input
+                                        // the path's max_events counts the step as one collision;
+                                        // the walk inside the sphere has a bound of its own, reached
+                                        // only with degenerate input
+                                        if (++nev > kInnerWalkBound) break;
                                         const uint4 ww = rng.block(c0++);
                                         resv = nev == 1 ? 1.0f : __builtin_fmaf(resv, inv_phi, 1.0f);
                                         if (u01(ww.w) * resv <= 1.0f) {
