@@ -150,6 +150,32 @@ def small_c4(sigma_t, w=24):
     return W.camera_c4(w, w), W.light_c4(), W.medium_c4(sigma_t)
 
 
+@pytest.mark.parametrize("exact", [False, True])
+def test_event_cap_only_touches_longer_paths(oracle, c4, exact):
+    """max_events ends a path at the collision after the cap (a sphere step
+    counting once): paths with at most cap collisions are unchanged, bit for
+    bit, and no path records more than cap."""
+    cam, light, med = small_c4(40.0)
+    kw = (dict(method=oracle.METHOD_ST, sampler=oracle.SAMPLER_EXACT_WALK) if exact
+          else dict(method=oracle.METHOD_PLAIN_NEE))
+    full = oracle.render(c4, cam, light, med, spp=1, seed=6, **kw)
+    n_full = full["events"].astype(np.int64) + full["steps"]
+    assert n_full.max() > 6
+    for cap in (1, 3, 6):
+        a = oracle.render(c4, cam, light, med, spp=1, seed=6, max_events=cap, **kw)
+        n = a["events"].astype(np.int64) + a["steps"]
+        short = n_full <= cap
+        np.testing.assert_array_equal(a["sum"][short], full["sum"][short])
+        np.testing.assert_array_equal(n[short], n_full[short])
+        assert (n[~short] == cap).all()
+        # a truncated path keeps the light it gathered before the cap: a
+        # prefix of the same stream's nonnegative terms
+        assert (a["sum"][~short] <= full["sum"][~short] * (1 + 1e-12)).all()
+        assert (a["sum"][~short] < full["sum"][~short]).any()
+    if exact:
+        assert full["steps"].sum() > 0
+
+
 def test_sphere_tracing_without_steps_is_plain(oracle, c4):
     cam, light, med = small_c4(10.0)
     a = oracle.render(c4, cam, light, med, method=oracle.METHOD_PLAIN_NEE, spp=4, seed=1)
